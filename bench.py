@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Benchmark of the approximate-normal transform and the nested MLMC levels.
+
+A step is one pass of the streaming transform over the whole device-resident
+batch: 2^30 FP32 uniforms (the u24 grid, generated on the device before the
+timed region) through the 16-row degree-1 dyadic table (FP32 coefficients) to
+2^30 FP32 approximate normals.  `value` is samples per second over the K timed
+steps.  The JSON line also carries
+  roofline      the transform kernel's algorithmic bytes / its event-timed
+                average duration against the 8 TB/s HBM peak
+  cpu_baseline  the FP64 oracle on a bounded sample of the same workload
+  sweep         the precision sweep (rows 8/16/32 x degree 1/3 x FP32/FP16/BF16
+                coefficients and outputs, plus the 1024-interval constant
+                table): samples/s, GB/s and the exact RMSE/max error against
+                FP64 Phi^-1 over the whole u24 input grid
+  bandwidth     the plain copy kernel on the same byte count
+  mlmc          nested-MLMC results (GBM and CIR) when run with --mlmc
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only-main] [--mlmc]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "approx N(0,1) samples/s (% HBM roofline); MLMC speedup vs exact at fixed RMSE"
+HBM_PEAK_GBS = 8000.0
+N_MAIN = 1 << 30
+SEED = 20201217
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--only-main", action="store_true",
+                    help="time the main transform and the copy probe only (for profiler runs)")
+    ap.add_argument("--mlmc", action="store_true", help="also run the nested MLMC measurements")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_kernel(fn, reps, stream):
+    """Average device time of fn() over reps launches, by HIP events on the
+    stream the library launches on (torch's current stream)."""
+    import torch
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    for i in range(reps):
+        starts[i].record(stream)
+        fn()
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    return float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
+
+
+def cpu_baseline(seconds):
+    """The oracle's dyadic transform (FP64 numpy, one thread) timed on 2^22
+    uniforms of the same stream, repeated until `seconds` of CPU work."""
+    from oracle import rng, tables, transform
+    from oracle.dtypes import round_f32
+    tab = round_f32(tables.dyadic_table(16, 1))
+    chunk = 1 << 22
+    u = rng.uniform_fill_f32(SEED, 3, 0, chunk).astype(np.float64)
+    reps, t = 0, 0.0
+    while t < seconds:
+        t1 = time.perf_counter()
+        transform.dyadic_transform(tab, u)
+        t += time.perf_counter() - t1
+        reps += 1
+    return {"value": reps * chunk / t, "unit": "samples/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first 2^22 uniforms of the benchmark stream through the oracle's FP64 dyadic "
+                      f"transform (16 rows, degree 1, FP32-rounded coefficients), {reps} repetitions, {t:.1f} s"}
+
+
+def exact_error_on_grid(A, torch, tab, out_dtype, kind):
+    """RMSE and max |Z~ - Phi^-1| over every point of the u24 grid (the exact
+    error for the input distribution of the sweep), both sides on the GPU."""
+    m = torch.arange(1 << 23, device="cuda", dtype=torch.float64)
+    u64 = (m + 0.5) * 2.0 ** -23
+    zx = A.exact_icdf(u64)
+    u32 = u64.float()
+    if kind == "const":
+        za = A.approx_icdf_const(tab, u32, out_dtype=out_dtype).double()
+    else:
+        za = A.approx_icdf_linear(tab, u32, out_dtype=out_dtype).double()
+    d = za - zx
+    return float(torch.sqrt(torch.mean(d * d)).item()), float(d.abs().max().item())
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        log("bench.py: only --gpus 1 is supported (the method's work shards by path/sample range; "
+            "a multi-GPU run is not part of this build)")
+        return 2
+    import torch
+    import paper_2012_09715_amd as A
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    log(f"device: {torch.cuda.get_device_name(dev)}")
+
+    # ---------------------------------------------------------- main workload
+    u = torch.empty(N_MAIN, dtype=torch.float32, device=dev)
+    z = torch.empty(N_MAIN, dtype=torch.float32, device=dev)
+    A.uniform_fill(u, SEED, 3, 0)
+    tab = A.Table.dyadic(16, 1, torch.float32)
+    torch.cuda.synchronize()
+    step = lambda: A.approx_icdf_linear(tab, u, z=z)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(stream)
+        step()
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
+    log(f"main transform: {kms:.4f} ms/launch (events), wall {wall / args.steps * 1e3:.4f} ms/step")
+    bytes_per_launch = N_MAIN * (4 + 4)
+    achieved = bytes_per_launch / (kms * 1e-3) / 1e9
+
+    # ---------------------------------------------------------- copy probe
+    cms = time_kernel(lambda: A.bw_probe(0, u, z), max(args.steps, 5), stream)
+    copy_gbs = bytes_per_launch / (cms * 1e-3) / 1e9
+    log(f"copy probe: {cms:.4f} ms, {copy_gbs:.1f} GB/s")
+
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic_transform_linear16_f32.json")
+    if os.path.exists(tfile):
+        with open(tfile) as f:
+            traffic = json.load(f).get("traffic_bytes_per_launch")
+
+    result = {
+        "metric": METRIC,
+        "value": N_MAIN * args.steps / wall,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "standalone transform: 2^30 device-resident FP32 uniforms (u24 grid, Philox) -> "
+                               "16-row degree-1 dyadic table, FP32 coefficients -> 2^30 FP32 approximate normals",
+                   "n": N_MAIN, "table_rows": 16, "degree": 1, "coef": "f32", "out": "f32"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "transform_kernel<DyadicF32<1>, OUT_F32>",
+                     "kernel_ms": kms, "algorithmic_bytes_per_launch": bytes_per_launch},
+        "bandwidth": {"copy_GBs": copy_gbs, "copy_ms": cms, "bytes": bytes_per_launch,
+                      "transform_vs_copy": achieved / copy_gbs},
+    }
+    if args.only_main:
+        print(json.dumps(result), flush=True)
+        return 0
+
+    # ---------------------------------------------------------- sweep
+    sweep = []
+    reps = 5
+    for T in (8, 16, 32):
+        for d in (1, 3):
+            for cdt, name in ((torch.float32, "f32"), (torch.float16, "f16"), (torch.bfloat16, "bf16")):
+                t = A.Table.dyadic(T, d, cdt)
+                zo = torch.empty(N_MAIN, dtype=cdt, device=dev)
+                ms = time_kernel(lambda: A.approx_icdf_linear(t, u, z=zo), reps, stream)
+                nb = N_MAIN * (4 + zo.element_size())
+                rmse, mx = exact_error_on_grid(A, torch, t, cdt, "dyadic")
+                sweep.append({"table": f"dyadic{T}", "degree": d, "coef": name, "out": name,
+                              "samples_per_s": N_MAIN / (ms * 1e-3), "GBs": nb / (ms * 1e-3) / 1e9,
+                              "hbm_frac": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "ms": ms,
+                              "rmse_vs_fp64": rmse, "max_err_vs_fp64": mx})
+                log(f"sweep {sweep[-1]}")
+                del zo
+    tc = A.Table.const(1024, 0, torch.float32)
+    ms = time_kernel(lambda: A.approx_icdf_const(tc, u, z=z), reps, stream)
+    rmse, mx = exact_error_on_grid(A, torch, tc, torch.float32, "const")
+    sweep.append({"table": "const1024", "degree": 0, "coef": "f32", "out": "f32",
+                  "samples_per_s": N_MAIN / (ms * 1e-3), "GBs": 8 * N_MAIN / (ms * 1e-3) / 1e9,
+                  "hbm_frac": 8 * N_MAIN / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "ms": ms,
+                  "rmse_vs_fp64": rmse, "max_err_vs_fp64": mx})
+    ms = time_kernel(lambda: A.exact_icdf(u, z=z), 3, stream)
+    sweep.append({"table": "exact_fp64", "out": "f32", "samples_per_s": N_MAIN / (ms * 1e-3), "ms": ms,
+                  "GBs": 8 * N_MAIN / (ms * 1e-3) / 1e9})
+    ms = time_kernel(lambda: A.uniform_fill(u, SEED, 3, 0), 3, stream)
+    sweep.append({"table": "uniform_fill_f32", "samples_per_s": N_MAIN / (ms * 1e-3), "ms": ms,
+                  "GBs": 4 * N_MAIN / (ms * 1e-3) / 1e9})
+    result["sweep"] = sweep
+    del u, z
+    torch.cuda.empty_cache()
+
+    # ---------------------------------------------------------- MLMC
+    if args.mlmc:
+        from paper_2012_09715_amd import mlmc_driver
+        result["mlmc"] = mlmc_driver.bench_summary(log=log)
+
+    # ---------------------------------------------------------- CPU baseline
+    log("cpu baseline (oracle) ...")
+    result["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,344 @@
+/*
+ * aicdf.h -- C ABI of libaicdf.so: approximate inverse-CDF random variables
+ * and nested multilevel Monte Carlo levels on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Giles & Sheridan-Methven, "Approximating inverse cumulative
+ * distribution functions to produce approximate random variables"
+ * (arXiv:2012.09715).  Section numbers below refer to that paper.
+ *
+ * Conventions (all entry points)
+ *  - Pointers named "device" are HIP device pointers on the current device;
+ *    pointers named "host" are host memory.  The caller owns every buffer it
+ *    passes; the library never frees caller memory.
+ *  - Opaque handles (aicdf_table, aicdf_surrogate) are library-owned and are
+ *    released with their destroy call; destroy(NULL) is a no-op.  A handle is
+ *    bound to the device that was current when it was created.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Transform calls only enqueue work and return; the MLMC level calls and
+ *    the calls returning host results synchronise `stream` before returning.
+ *  - Errors are reported only through the status code; aicdf_last_error()
+ *    returns a thread-local text for the last failing call.  No call prints,
+ *    throws across the ABI or aborts.
+ *  - n == 0 is a successful no-op.  A NULL data pointer with n > 0 gives
+ *    AICDF_EINVAL.  Input and output byte ranges that overlap give
+ *    AICDF_EALIAS (the paper's loops take restrict-qualified arrays, Code 1
+ *    and Code 2).  Unsupported dtype combinations give AICDF_EDTYPE.
+ *  - Values are not checked per element (hot path).  Inputs u are meant to be
+ *    in (0,1); u = 0 and u = 1 give finite values of the capped table entries
+ *    (or -inf/+inf for exact_icdf); NaN gives NaN for the dyadic and exact
+ *    transforms and the first constant for the piecewise-constant one; other
+ *    values outside [0,1] give finite, unspecified results.
+ */
+#ifndef AICDF_H
+#define AICDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t aicdf_status;
+#define AICDF_OK 0
+#define AICDF_EINVAL (-1)   /* bad argument (NULL, size, range, enum)       */
+#define AICDF_EDTYPE (-2)   /* unsupported dtype combination                */
+#define AICDF_EALIAS (-3)   /* input and output memory overlap              */
+#define AICDF_ENOMEM (-4)   /* host or device allocation failed             */
+#define AICDF_EHIP (-5)     /* a HIP runtime call failed (see last_error)   */
+#define AICDF_ERANGE (-6)   /* size beyond a documented maximum             */
+#define AICDF_EIO (-7)      /* file could not be read or written            */
+
+typedef enum {
+  AICDF_F64 = 0,
+  AICDF_F32 = 1,
+  AICDF_F16 = 2,
+  AICDF_BF16 = 3
+} aicdf_dtype;
+
+/* Thread-local description of the last failure in this thread ("" if none). */
+const char* aicdf_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Coefficient tables                                                        */
+/* ------------------------------------------------------------------------ */
+typedef struct aicdf_table aicdf_table;
+
+/* Piecewise-constant approximation on N = n_intervals equal intervals
+ * [k/N, (k+1)/N) (Section 2.2, Theorem 2.3; Section 3.2).  construction:
+ *   0  conditional mean E(Z | Phi(Z) in I_k)      (Corollary 2.4, "E"; the
+ *      paper's choice)
+ *   1  Phi^-1 of the interval midpoint            (Corollary 2.4, "C")
+ *   2  Phi^-1 of the endpoint nearer 1/2          (Corollary 2.4, "I")
+ * n_intervals: power of two in [2, 65536].  coef_t: F64, F32, F16 or BF16
+ * (each constant is rounded to nearest even in coef_t).  The table is built
+ * on the host in FP64 and copied to the current device.  *out receives the
+ * handle.  Errors: EINVAL, EDTYPE, ENOMEM, EHIP. */
+aicdf_status aicdf_table_const_create(uint32_t n_intervals, int32_t construction,
+                                      aicdf_dtype coef_t, aicdf_table** out);
+
+/* Piecewise-polynomial approximation on dyadic intervals (Section 2.3,
+ * Theorem 2.5 with decay rate r = 1/2; Section 3.3, Table 1).  A table of
+ * T = n_entries rows serves u in (0, 1/2]:
+ *   row 0        u = 1/2 exactly; all coefficients zero (Section 3.3)
+ *   row e        [2^-(e+1), 2^-e) for 1 <= e <= T-2
+ *   row T-1      the singular interval (0, 2^-(T-1))
+ * u > 1/2 is served by antisymmetry.  Each row holds the L2-best polynomial
+ * of the given degree on its interval, written in the local variable
+ * s = u * 2^(e+1) (s in [1,2), or (0,2) on the singular row):
+ *   D(u) = c_0 + c_1 s + ... + c_d s^d.
+ * n_entries in [3, 64]; degree in [0, 3]; coef_t: F32, F16 or BF16.
+ * Errors: EINVAL, EDTYPE, ENOMEM, EHIP. */
+aicdf_status aicdf_table_dyadic_create(uint32_t n_entries, uint32_t degree,
+                                       aicdf_dtype coef_t, aicdf_table** out);
+
+/* Copies the stored (coef_t-rounded) coefficients to host memory as doubles,
+ * row-major rows x cols (constant tables: N x 1; dyadic: T x (degree+1)).
+ * host_out may be NULL to query rows/cols; otherwise cap >= rows*cols.
+ * Errors: EINVAL, ERANGE. */
+aicdf_status aicdf_table_coeffs(const aicdf_table* table, double* host_out, size_t cap,
+                                uint32_t* rows, uint32_t* cols);
+
+void aicdf_table_destroy(aicdf_table* table);
+
+/* The same host FP64 construction without a device: writes the coef_t-rounded
+ * coefficients that aicdf_table_const_create (kind 0; param = construction)
+ * or aicdf_table_dyadic_create (kind 1; param = degree) would store, row-major,
+ * to host_out (cap >= rows*cols: n for kind 0, n*(degree+1) for kind 1).
+ * coef_t = F64 returns the unrounded FP64 fit for either kind.
+ * Errors: EINVAL, EDTYPE, ERANGE. */
+aicdf_status aicdf_table_host_coeffs(int32_t kind, uint32_t n, uint32_t param, aicdf_dtype coef_t,
+                                     double* host_out, size_t cap);
+
+/* ------------------------------------------------------------------------ */
+/* Streaming transforms U -> Z (Section 3)                                   */
+/* ------------------------------------------------------------------------ */
+
+/* z[i] = Q[m] with m = min(floor(N u[i]), N-1) on a constant table (Code 1;
+ * the clamp at N-1 covers u = 1, which the paper's loop leaves unguarded).
+ * u: device, n elements of u_t; z: device, n elements of z_t.
+ * (u_t, z_t) in {(F32,F32), (F32,F16), (F32,BF16), (F64,F32), (F64,F64)}.
+ * Output rounding is to nearest even.  Asynchronous on `stream`.
+ * Errors: EINVAL, EDTYPE, EALIAS, EHIP. */
+aicdf_status approx_icdf_const(const aicdf_table* table, size_t n, const void* u, aicdf_dtype u_t,
+                               void* z, aicdf_dtype z_t, void* stream);
+
+/* Dyadic piecewise-polynomial transform (Algorithm 1): predicate u < 1/2,
+ * reflection u' = 1 - u otherwise, row index e = min(B - 1 - E(u'), T - 1)
+ * read from the biased exponent E of u' (B = 127 for F32 input, 1023 for
+ * F64 input), s = u' 2^(e+1), Horner's rule with fused multiply-adds, sign
+ * restored.  F32 input evaluates in FP32; F64 input evaluates in FP64 on the
+ * stored coefficients.  Same dtype pairs, layout and errors as
+ * approx_icdf_const. */
+aicdf_status approx_icdf_linear(const aicdf_table* table, size_t n, const void* u, aicdf_dtype u_t,
+                                void* z, aicdf_dtype z_t, void* stream);
+
+/* The row (dyadic table) or interval (constant table) index that the two
+ * transforms above select for each u, computed by the same device code; for
+ * verifying the index step of Code 1 / Algorithm 1.  idx: device, n uint32.
+ * u_t: F32 or F64.  Errors: EINVAL, EDTYPE, EALIAS, EHIP. */
+aicdf_status approx_icdf_index(const aicdf_table* table, size_t n, const void* u, aicdf_dtype u_t,
+                               uint32_t* idx, void* stream);
+
+/* Exact inverse normal CDF Phi^-1 in FP64 (Section 3.1 describes the library
+ * routines this stands for): an initial value from Abramowitz & Stegun
+ * 26.2.23 refined by two Halley steps on Phi(z) - q with q = min(u, 1-u),
+ * Phi evaluated through erf (q >= 1/4) or erfc (q < 1/4).
+ * (u_t, z_t) in {(F64,F64), (F64,F32), (F32,F64), (F32,F32)}; u = 0 and
+ * u = 1 give -inf and +inf.  Errors: EINVAL, EDTYPE, EALIAS, EHIP. */
+aicdf_status exact_icdf(size_t n, const void* u, aicdf_dtype u_t, void* z, aicdf_dtype z_t,
+                        void* stream);
+
+/* Counter-based uniforms from Philox-4x32-10 (Salmon et al., SC'11).
+ * Key (lo32(seed), hi32(seed)); counter words 2,3 = (lo32(stream_id),
+ * hi32(stream_id)).
+ *  F32: element i uses 32-bit word g = offset + i, from counter block g/4,
+ *       word g mod 4; m = word >> 9; u = (m + 0.5) 2^-23 (odd multiples of
+ *       2^-24, exact in FP32, never 0 or 1).
+ *  F64: element i uses draw g = offset + i, counter block g/2, words
+ *       2(g mod 2) (hi) and 2(g mod 2)+1 (lo); k = (hi:lo) >> 11;
+ *       u = ((double)k + 0.5) 2^-53 rounded to nearest even, with the one
+ *       value that rounds to 1.0 replaced by 1 - 2^-53.
+ * u: device, n elements of u_t (F32 or F64).  Errors: EINVAL, EDTYPE, EHIP. */
+aicdf_status aicdf_uniform_fill(uint64_t seed, uint64_t stream_id, uint64_t offset, size_t n,
+                                void* u, aicdf_dtype u_t, void* stream);
+
+/* Plain HBM streaming kernels that measure the achievable bandwidth which
+ * bounds the transforms (the paper's "read and write" floor, Section 3.4).
+ * mode 0: copy n_bytes from src to dst; mode 1: read n_bytes from src (dst
+ * must hold 16 bytes and is written only in the impossible case that the
+ * data fold to a sentinel); mode 2: write n_bytes to dst (src unused, may be
+ * NULL).
+ * n_bytes must be a multiple of 16 and both pointers 16-byte aligned.
+ * Errors: EINVAL, EHIP. */
+aicdf_status aicdf_bw_probe(int32_t mode, size_t n_bytes, const void* src, void* dst,
+                            void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Nested multilevel Monte Carlo levels (Section 4, Section 5.2)             */
+/* ------------------------------------------------------------------------ */
+#define AICDF_KIND_EXACT 0      /* Y = P^_l - P^_(l-1), exact inverse        */
+#define AICDF_KIND_APPROX 1     /* Y = P~_l - P~_(l-1), approximation        */
+#define AICDF_KIND_CORRECTION 2 /* Y = P^_l - P^_(l-1) - P~_l + P~_(l-1)     */
+
+typedef struct {
+  double S0, r, sigma, T, K; /* dX = r X dt + sigma X dW, X_0 = S0, strike K */
+  int32_t scheme;            /* 0 Euler-Maruyama, 1 Milstein                 */
+  int32_t payoff;            /* 0 P = X_T, 1 P = exp(-rT) max(X_T - K, 0)    */
+} aicdf_gbm_params;
+
+typedef struct {
+  double v0, kappa, theta, xi, T; /* dv = kappa(theta - v)dt + xi sqrt(v) dW */
+  int32_t functional;             /* 0 P = v_T, 1 trapezoidal time average  */
+  int32_t reserved;               /* must be 0                              */
+} aicdf_cir_params;
+
+/* Compensated FP64 sums over the paths of one level call. */
+typedef struct {
+  double n;           /* number of paths                                     */
+  double sum[4];      /* sum of Y, Y^2, Y^3, Y^4                             */
+  double sum_pf;      /* sum of the fine functional (exact path for EXACT and
+                         CORRECTION, approximate path for APPROX)            */
+  double sum_pc;      /* sum of the coarse functional (0 at level 0)         */
+  double kernel_ms;   /* device time of the level kernel, HIP events         */
+  uint64_t fallbacks; /* CIR surrogate steps routed to the exact inverse     */
+  uint64_t reserved;
+} aicdf_level_sums;
+
+/* One MLMC level of geometric Brownian motion with the approximate normals
+ * fused into the coupled fine/coarse paths (Section 4: Euler-Maruyama and
+ * Milstein; the coarse Wiener increments are pairwise sums of the fine ones;
+ * exact and approximate normals of one step come from one uniform).
+ * level: 0..20 (2^level fine steps; no coarse path at level 0).
+ * kind: AICDF_KIND_*.  approx: dyadic or constant table, required unless
+ * kind == EXACT (ignored then).  Paths path_offset .. path_offset+n_paths-1
+ * of the stream (seed, level, kind) are simulated; any split of a path range
+ * over calls gives the same per-path values.
+ * Draws (Philox counter (block, lo32(path), hi32(path), level | kind << 8),
+ * key seed): APPROX takes one 32-bit word per fine step (u24 grid as in
+ * aicdf_uniform_fill F32); EXACT and CORRECTION take two words per step
+ * (u53 grid as in aicdf_uniform_fill F64, and for CORRECTION the u24 of
+ * the high word drives the approximate path).
+ * out: host, receives the sums.  path_out: optional device buffer of
+ * n_paths x 3 doubles (Y, P_f, P_c per path) or NULL.
+ * Synchronises `stream`.  Errors: EINVAL, ERANGE, EHIP, ENOMEM. */
+aicdf_status mlmc_level_gbm(const aicdf_gbm_params* params, uint32_t level, uint64_t n_paths,
+                            int32_t kind, const aicdf_table* approx, uint64_t seed,
+                            uint64_t path_offset, aicdf_level_sums* out, double* path_out,
+                            void* stream);
+
+typedef struct aicdf_surrogate aicdf_surrogate;
+
+/* One MLMC level of the CIR process with exact-in-law non-central chi-squared
+ * transitions (Section 5.2): with nu = 4 kappa theta / xi^2, per step of
+ * delta = T / 2^level,  c = xi^2 (1 - e^(-kappa delta)) / (4 kappa),
+ * lambda_n = v_n e^(-kappa delta) / c,  v_(n+1) = c C_nu^-1(U_n; lambda_n).
+ * The coarse path is the fine path observed at even steps.  kind:
+ *   EXACT       exact inverse (FP64), two-word u53 draws
+ *   APPROX      the surrogate network (required), one-word u24 draws; steps
+ *               whose log(lambda) lies outside the surrogate's range use the
+ *               exact inverse on the same u24 (counted in out->fallbacks)
+ *   CORRECTION  both on two-word draws (surrogate on the u24 of the high word)
+ * Stream kinds are 4 + kind in the counter tag.  level 0..12.  Other
+ * arguments as mlmc_level_gbm.  Errors: EINVAL, ERANGE, EHIP, ENOMEM. */
+aicdf_status mlmc_level_cir(const aicdf_cir_params* params, uint32_t level, uint64_t n_paths,
+                            int32_t kind, const aicdf_surrogate* approx, uint64_t seed,
+                            uint64_t path_offset, aicdf_level_sums* out, double* path_out,
+                            void* stream);
+
+/* Optimal allocation of the nested estimator at RMSE eps (Section 4.1):
+ *   T^ = 2 eps^-2 (sum_l sqrt(v^_l c^_l))^2,
+ *   T~ = 2 eps^-2 (sum_l sqrt(v~_l c~_l) + sqrt(V~_l C~_l))^2,
+ *   m^_l = eps^-1 sqrt(2 T^ v^_l / c^_l), m~_l = eps^-1 sqrt(2 T~ v~_l / c~_l),
+ *   M~_l = eps^-1 sqrt(2 T~ V~_l / C~_l).
+ * All arrays are host arrays of n_levels doubles; v_* >= 0, c_* > 0.  Any of
+ * the m outputs may be NULL.  Errors: EINVAL. */
+aicdf_status mlmc_allocate(uint32_t n_levels, double eps, const double* v_hat, const double* c_hat,
+                           const double* v2, const double* c2, const double* v4, const double* c4,
+                           double* m_hat, double* m2, double* m4, double* T_hat,
+                           double* T_tilde);
+
+/* ------------------------------------------------------------------------ */
+/* Non-central chi-squared (Section 5)                                       */
+/* ------------------------------------------------------------------------ */
+
+/* x[i] = C_nu^-1(u[i]; lambda[i]) in FP64: the CDF is the Poisson mixture of
+ * central chi-squared CDFs (Abramowitz & Stegun 26.4.25, which Section 5
+ * cites), summed outward from the Poisson mode with incomplete-gamma
+ * recurrences; the root is found by safeguarded Newton steps in log x on
+ * log C (u <= 1/2) or log(1 - C) (u > 1/2), inside a maintained bracket.
+ * u, lambda, x: device arrays of n doubles; nu > 0; lambda >= 0.
+ * u = 0 gives 0, u = 1 gives +inf.  Errors: EINVAL, EALIAS, EHIP. */
+aicdf_status ncx2_icdf_exact(double nu, size_t n, const double* u, const double* lambda,
+                             double* x, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Learned surrogate for the CIR transition (MLP on BF16 MFMA)               */
+/* ------------------------------------------------------------------------ */
+/* The surrogate approximates Section 5.1's rescaled inverse
+ *   P = (C_nu^-1(U; lambda) - lambda - nu) / (2 sqrt(lambda + nu))
+ * at a fixed nu for log(lambda) in [loglam_lo, loglam_hi]:
+ *   w  = D(U): the 16-row cubic dyadic approximation of Phi^-1 (FP32)
+ *   g  = 2 (log lambda - loglam_lo) / (loglam_hi - loglam_lo) - 1
+ *   h1 = silu(W1 [w, g] + b1)                 W1 64x2, FP32
+ *   h2 = silu(W2 bf16(h1) + b2)               W2 64x64 in BF16, FP32 sums (MFMA)
+ *   P~ = w + W3 . h2 + b3                     W3 64, FP32
+ * silu(t) = t / (1 + e^-t).  Parameters are a flat FP32 vector of
+ * AICDF_SURROGATE_NPARAMS values in the order W1 (row-major 64x2), b1, W2
+ * (row-major 64x64, out x in), b2, W3, b3. */
+#define AICDF_SURROGATE_HIDDEN 64
+#define AICDF_SURROGATE_NPARAMS 4417
+
+/* Creates a surrogate for degrees of freedom nu with a seeded uniform
+ * +-1/sqrt(fan_in) initialisation.  Errors: EINVAL, ENOMEM, EHIP. */
+aicdf_status aicdf_surrogate_create(double nu, double loglam_lo, double loglam_hi, uint64_t seed,
+                                    aicdf_surrogate** out);
+void aicdf_surrogate_destroy(aicdf_surrogate* s);
+
+/* Host copies of the FP32 parameter vector (layout above); set also refreshes
+ * the BF16 copy of W2 and resets the optimiser state.  Errors: EINVAL, EHIP. */
+aicdf_status aicdf_surrogate_set_params(aicdf_surrogate* s, const float* host_params, size_t n);
+aicdf_status aicdf_surrogate_get_params(const aicdf_surrogate* s, float* host_params, size_t n);
+
+/* P~ for n inputs (device arrays of floats: u, log lambda -> p).  Inputs
+ * outside the trained log-lambda range are evaluated anyway (no fallback).
+ * Errors: EINVAL, EALIAS, EHIP. */
+aicdf_status aicdf_surrogate_forward(const aicdf_surrogate* s, size_t n, const float* u,
+                                     const float* loglam, float* p, void* stream);
+
+/* Mean-squared-error loss against `target` (device) over n inputs and its
+ * gradient with respect to every parameter (host, AICDF_SURROGATE_NPARAMS
+ * floats), computed by the training kernels (BF16 layer-2 operands, FP32
+ * sums, straight-through rounding).  Synchronises.  Errors: EINVAL, EHIP. */
+aicdf_status aicdf_surrogate_loss_grad(const aicdf_surrogate* s, size_t n, const float* u,
+                                       const float* loglam, const float* target,
+                                       double* host_loss, float* host_grads, void* stream);
+
+/* Training set: n samples with u on the u24 grid (a quarter of them pushed
+ * into the tails by squaring, mirrored at random) and log lambda uniform on
+ * the surrogate's range, from Philox stream (seed, 0x5EED); targets P from
+ * the exact FP64 inverse.  Device arrays of n floats.  Errors: EINVAL, EHIP. */
+aicdf_status aicdf_surrogate_make_data(const aicdf_surrogate* s, uint64_t seed, size_t n,
+                                       float* u, float* loglam, float* target, void* stream);
+
+/* Adam training (FP32 master weights) on device data for `epochs` passes of
+ * mini-batches of `batch` samples (a multiple of 256, at most 65536) in a
+ * seeded shuffled order; cosine learning-rate decay from lr.  host_loss
+ * (optional) receives the mean loss of the last epoch.  Synchronises.
+ * Errors: EINVAL, ENOMEM, EHIP. */
+aicdf_status aicdf_surrogate_train(aicdf_surrogate* s, size_t n, const float* u,
+                                   const float* loglam, const float* target, uint32_t epochs,
+                                   uint32_t batch, float lr, uint64_t seed, double* host_loss,
+                                   void* stream);
+
+/* Range getters and persistence (little-endian header + FP32 parameters). */
+aicdf_status aicdf_surrogate_info(const aicdf_surrogate* s, double* nu, double* loglam_lo,
+                                  double* loglam_hi);
+aicdf_status aicdf_surrogate_save(const aicdf_surrogate* s, const char* path);
+aicdf_status aicdf_surrogate_load(const char* path, aicdf_surrogate** out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AICDF_H */

@@ -63,3 +63,34 @@ def dyadic_transform(tab, u):
         z = z * s + c[..., j]
     z = np.where(p, z, -z)
     return z, e
+
+
+def fma_f32(a, b, c):
+    """Single-precision fused multiply-add: the product of two FP32 values is
+    exact in FP64, so one FP64 add and one rounding to FP32 give fma(a, b, c)
+    except in the rare double-rounding case (the FP64 sum landing exactly
+    half-way between two FP32 values)."""
+    a = np.asarray(a, np.float32).astype(np.float64)
+    b = np.asarray(b, np.float32).astype(np.float64)
+    c = np.asarray(c, np.float32).astype(np.float64)
+    return (a * b + c).astype(np.float32)
+
+
+def dyadic_transform_f32(tab, u):
+    """Algorithm 1 carried out in single precision, as the paper's Code 2 does:
+    FP32 input, FP32 reflection (exact), s = u' 2^(e+1) (exact), Horner's rule
+    with FP32 fused multiply-adds over the (FP32) coefficients.  Returns
+    (z as float32, e)."""
+    tab = np.asarray(tab, dtype=np.float64).astype(np.float32)
+    u32 = np.asarray(u, dtype=np.float32)
+    T, d1 = tab.shape
+    e, p, ur = dyadic_index(T, u32.astype(np.float64))
+    s = np.ldexp(ur, e + 1).astype(np.float32)  # exact
+    c = tab[e]
+    z = c[..., d1 - 1]
+    for j in range(d1 - 2, -1, -1):
+        z = fma_f32(z, s, c[..., j])
+    if d1 == 1:
+        z = fma_f32(np.float32(0.0), s, z)  # NaN input propagates
+    z = np.where(p, z, -z).astype(np.float32)
+    return z, e

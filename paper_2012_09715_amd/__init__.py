@@ -1,0 +1,248 @@
+"""MI355X-native approximate inverse-CDF random variables and nested MLMC.
+
+Python face of libaicdf.so (include/aicdf.h).  Every function marshals torch
+tensors (device memory) and torch's current HIP stream into the C ABI; all
+computation happens in the library's HIP kernels.  See the header for the
+definitions, layouts and error behaviour of each call.
+"""
+import ctypes as C
+
+import torch
+
+from ._lib import (AicdfError, CirParams, GbmParams, LevelSums, check, lib)
+
+F64, F32, F16, BF16 = 0, 1, 2, 3
+KIND_EXACT, KIND_APPROX, KIND_CORRECTION = 0, 1, 2
+SURROGATE_NPARAMS = 4417
+
+_TORCH_TO_DT = {torch.float64: F64, torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
+_DT_TO_TORCH = {v: k for k, v in _TORCH_TO_DT.items()}
+
+
+def _dt(t):
+    try:
+        return _TORCH_TO_DT[t.dtype]
+    except KeyError:
+        raise AicdfError(-2, f"unsupported tensor dtype {t.dtype}") from None
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev(t, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise AicdfError(-1, f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise AicdfError(-1, f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+class Table:
+    """A coefficient table (library-owned; freed with the object)."""
+
+    def __init__(self, handle, kind):
+        self._h = handle
+        self.kind = kind
+
+    @property
+    def handle(self):
+        return self._h
+
+    @classmethod
+    def const(cls, n_intervals=1024, construction=0, coef_dtype=torch.float32):
+        h = C.c_void_p()
+        check(lib.aicdf_table_const_create(n_intervals, construction, _TORCH_TO_DT[coef_dtype], C.byref(h)))
+        return cls(h, "const")
+
+    @classmethod
+    def dyadic(cls, n_entries=16, degree=1, coef_dtype=torch.float32):
+        h = C.c_void_p()
+        check(lib.aicdf_table_dyadic_create(n_entries, degree, _TORCH_TO_DT[coef_dtype], C.byref(h)))
+        return cls(h, "dyadic")
+
+    def coeffs(self):
+        rows, cols = C.c_uint32(), C.c_uint32()
+        check(lib.aicdf_table_coeffs(self._h, None, 0, C.byref(rows), C.byref(cols)))
+        buf = (C.c_double * (rows.value * cols.value))()
+        check(lib.aicdf_table_coeffs(self._h, buf, len(buf), None, None))
+        return torch.tensor(list(buf), dtype=torch.float64).reshape(rows.value, cols.value)
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h:
+            lib.aicdf_table_destroy(h)
+
+
+def table_host_coeffs(kind, n, param, coef_dtype=torch.float32):
+    """Host-built coefficients (no device needed): kind "const" (param =
+    construction) or "dyadic" (param = degree); rows x cols float64 tensor."""
+    k = 0 if kind == "const" else 1
+    cols = 1 if k == 0 else param + 1
+    buf = (C.c_double * (n * cols))()
+    check(lib.aicdf_table_host_coeffs(k, n, param, _TORCH_TO_DT[coef_dtype], buf, len(buf)))
+    return torch.tensor(list(buf), dtype=torch.float64).reshape(n, cols)
+
+
+def _out(u, z, out_dtype):
+    if z is None:
+        z = torch.empty(u.shape, dtype=out_dtype, device=u.device)
+    return z
+
+
+def approx_icdf_const(table, u, z=None, out_dtype=torch.float32, stream=None):
+    z = _out(u, z, out_dtype)
+    check(lib.approx_icdf_const(table.handle, u.numel(), _dev(u, "u"), _dt(u), _dev(z, "z"), _dt(z),
+                                _stream(stream)))
+    return z
+
+
+def approx_icdf_linear(table, u, z=None, out_dtype=torch.float32, stream=None):
+    z = _out(u, z, out_dtype)
+    check(lib.approx_icdf_linear(table.handle, u.numel(), _dev(u, "u"), _dt(u), _dev(z, "z"), _dt(z),
+                                 _stream(stream)))
+    return z
+
+
+def approx_icdf_index(table, u, stream=None):
+    """Row/interval indices (int32 tensor holding the uint32 values)."""
+    idx = torch.empty(u.shape, dtype=torch.int32, device=u.device)
+    check(lib.approx_icdf_index(table.handle, u.numel(), _dev(u, "u"), _dt(u), _dev(idx, "idx"), _stream(stream)))
+    return idx
+
+
+def exact_icdf(u, z=None, out_dtype=torch.float64, stream=None):
+    z = _out(u, z, out_dtype)
+    check(lib.exact_icdf(u.numel(), _dev(u, "u"), _dt(u), _dev(z, "z"), _dt(z), _stream(stream)))
+    return z
+
+
+def uniform_fill(u, seed, stream_id=0, offset=0, stream=None):
+    check(lib.aicdf_uniform_fill(seed, stream_id, offset, u.numel(), _dev(u, "u"), _dt(u), _stream(stream)))
+    return u
+
+
+def bw_probe(mode, src, dst, n_bytes=None, stream=None):
+    nb = n_bytes if n_bytes is not None else (dst.numel() * dst.element_size() if mode != 1 else
+                                              src.numel() * src.element_size())
+    s_ptr = _dev(src, "src") if src is not None else None
+    check(lib.aicdf_bw_probe(mode, nb, s_ptr, _dev(dst, "dst"), _stream(stream)))
+
+
+def _sums_dict(s):
+    return {"n": s.n, "sum": list(s.sum), "sum_pf": s.sum_pf, "sum_pc": s.sum_pc,
+            "kernel_ms": s.kernel_ms, "fallbacks": s.fallbacks}
+
+
+def mlmc_level_gbm(params, level, n_paths, kind, table=None, seed=0, path_offset=0, path_out=None, stream=None):
+    p = GbmParams(params["S0"], params["r"], params["sigma"], params["T"], params.get("K", 1.0),
+                  int(params.get("scheme", 0)), int(params.get("payoff", 0)))
+    out = LevelSums()
+    po = _dev(path_out, "path_out") if path_out is not None else None
+    check(lib.mlmc_level_gbm(C.byref(p), level, n_paths, kind, table.handle if table is not None else None,
+                             seed, path_offset, C.byref(out), po, _stream(stream)))
+    return _sums_dict(out)
+
+
+def mlmc_level_cir(params, level, n_paths, kind, surrogate=None, seed=0, path_offset=0, path_out=None,
+                   stream=None):
+    p = CirParams(params["v0"], params["kappa"], params["theta"], params["xi"], params["T"],
+                  int(params.get("functional", 0)), 0)
+    out = LevelSums()
+    po = _dev(path_out, "path_out") if path_out is not None else None
+    check(lib.mlmc_level_cir(C.byref(p), level, n_paths, kind, surrogate.handle if surrogate is not None else None,
+                             seed, path_offset, C.byref(out), po, _stream(stream)))
+    return _sums_dict(out)
+
+
+def mlmc_allocate(eps, v_hat, c_hat, v2, c2, v4, c4):
+    n = len(v_hat)
+    arr = lambda xs: (C.c_double * n)(*[float(x) for x in xs])
+    mh, m2, m4 = (C.c_double * n)(), (C.c_double * n)(), (C.c_double * n)()
+    Th, Tt = C.c_double(), C.c_double()
+    check(lib.mlmc_allocate(n, eps, arr(v_hat), arr(c_hat), arr(v2), arr(c2), arr(v4), arr(c4), mh, m2, m4,
+                            C.byref(Th), C.byref(Tt)))
+    return {"m_hat": list(mh), "m_tilde": list(m2), "M_tilde": list(m4), "T_hat": Th.value, "T_tilde": Tt.value}
+
+
+def ncx2_icdf_exact(nu, u, lam, x=None, stream=None):
+    if x is None:
+        x = torch.empty_like(u)
+    check(lib.ncx2_icdf_exact(nu, u.numel(), _dev(u, "u"), _dev(lam, "lambda"), _dev(x, "x"), _stream(stream)))
+    return x
+
+
+class Surrogate:
+    """The MLP surrogate of the CIR transition (library-owned handle)."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @property
+    def handle(self):
+        return self._h
+
+    @classmethod
+    def create(cls, nu, loglam_lo, loglam_hi, seed=0):
+        h = C.c_void_p()
+        check(lib.aicdf_surrogate_create(nu, loglam_lo, loglam_hi, seed, C.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def load(cls, path):
+        h = C.c_void_p()
+        check(lib.aicdf_surrogate_load(str(path).encode(), C.byref(h)))
+        return cls(h)
+
+    def save(self, path):
+        check(lib.aicdf_surrogate_save(self._h, str(path).encode()))
+
+    def info(self):
+        a, b, c = C.c_double(), C.c_double(), C.c_double()
+        check(lib.aicdf_surrogate_info(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def get_params(self):
+        buf = (C.c_float * SURROGATE_NPARAMS)()
+        check(lib.aicdf_surrogate_get_params(self._h, buf, SURROGATE_NPARAMS))
+        return torch.tensor(list(buf), dtype=torch.float32)
+
+    def set_params(self, flat):
+        flat = [float(x) for x in flat]
+        buf = (C.c_float * len(flat))(*flat)
+        check(lib.aicdf_surrogate_set_params(self._h, buf, len(flat)))
+
+    def forward(self, u, loglam, p=None, stream=None):
+        if p is None:
+            p = torch.empty_like(u)
+        check(lib.aicdf_surrogate_forward(self._h, u.numel(), _dev(u, "u"), _dev(loglam, "loglam"), _dev(p, "p"),
+                                          _stream(stream)))
+        return p
+
+    def loss_grad(self, u, loglam, target, stream=None):
+        loss = C.c_double()
+        g = (C.c_float * SURROGATE_NPARAMS)()
+        check(lib.aicdf_surrogate_loss_grad(self._h, u.numel(), _dev(u, "u"), _dev(loglam, "loglam"),
+                                            _dev(target, "target"), C.byref(loss), g, _stream(stream)))
+        return loss.value, torch.tensor(list(g), dtype=torch.float32)
+
+    def make_data(self, n, seed, device="cuda", stream=None):
+        u = torch.empty(n, dtype=torch.float32, device=device)
+        g = torch.empty_like(u)
+        t = torch.empty_like(u)
+        check(lib.aicdf_surrogate_make_data(self._h, seed, n, _dev(u, "u"), _dev(g, "loglam"), _dev(t, "target"),
+                                            _stream(stream)))
+        return u, g, t
+
+    def train(self, u, loglam, target, epochs, batch=4096, lr=1e-3, seed=0, stream=None):
+        loss = C.c_double()
+        check(lib.aicdf_surrogate_train(self._h, u.numel(), _dev(u, "u"), _dev(loglam, "loglam"),
+                                        _dev(target, "target"), epochs, batch, lr, seed, C.byref(loss),
+                                        _stream(stream)))
+        return loss.value
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h:
+            lib.aicdf_surrogate_destroy(h)

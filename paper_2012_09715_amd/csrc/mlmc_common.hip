@@ -1,0 +1,116 @@
+// Per-device workspace, the deterministic final pass over the per-block level
+// partials, and the optimal allocation of the nested estimator.
+#include <cmath>
+#include <map>
+
+#include "mlmc_common.hpp"
+
+namespace aicdf {
+
+namespace {
+
+// One work-group: thread t sums partials t, t+256, ... in order (Neumaier),
+// then a fixed-order tree over the 256 values.  The result does not depend on
+// scheduling, so repeated calls are bit-identical.
+__global__ __launch_bounds__(kLevelBlock) void reduce_partials_kernel(const double* __restrict__ partials,
+                                                                      unsigned nblocks, double* __restrict__ out) {
+  __shared__ double red[kSums][kLevelBlock];
+  KSum k[kSums];
+  for (unsigned b = threadIdx.x; b < nblocks; b += kLevelBlock)
+#pragma unroll
+    for (int j = 0; j < kSums; ++j) k[j].add(partials[size_t(b) * kSums + j]);
+#pragma unroll
+  for (int j = 0; j < kSums; ++j) red[j][threadIdx.x] = k[j].value();
+  __syncthreads();
+  for (int o = kLevelBlock / 2; o > 0; o >>= 1) {
+    if (int(threadIdx.x) < o)
+#pragma unroll
+      for (int j = 0; j < kSums; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x < kSums) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+std::mutex g_ws_mutex;
+std::map<int, Workspace*> g_ws;
+
+}  // namespace
+
+std::mutex& level_mutex() {
+  static std::mutex m;
+  return m;
+}
+
+aicdf_status get_workspace(Workspace** out) {
+  int dev = 0;
+  AICDF_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_ws_mutex);
+  auto it = g_ws.find(dev);
+  if (it != g_ws.end()) {
+    *out = it->second;
+    return AICDF_OK;
+  }
+  auto* ws = new (std::nothrow) Workspace();
+  if (!ws) return fail(AICDF_ENOMEM, "host allocation failed");
+  if (hipMalloc(&ws->partials, sizeof(double) * kMaxLevelBlocks * kSums) != hipSuccess ||
+      hipMalloc(&ws->result, sizeof(double) * kSums) != hipSuccess ||
+      hipMalloc(&ws->counter, sizeof(unsigned long long)) != hipSuccess) {
+    delete ws;
+    return fail(AICDF_ENOMEM, "hipMalloc of the level workspace failed");
+  }
+  AICDF_HIP(hipEventCreate(&ws->ev0));
+  AICDF_HIP(hipEventCreate(&ws->ev1));
+  g_ws[dev] = ws;
+  *out = ws;
+  return AICDF_OK;
+}
+
+aicdf_status finish_level(Workspace* ws, unsigned nblocks, hipStream_t s, double n_paths,
+                          aicdf_level_sums* out) {
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kLevelBlock), 0, s, ws->partials, nblocks, ws->result);
+  AICDF_HIP(hipGetLastError());
+  AICDF_HIP(hipEventRecord(ws->ev1, s));
+  double res[kSums];
+  unsigned long long fb = 0;
+  AICDF_HIP(hipMemcpyAsync(res, ws->result, sizeof res, hipMemcpyDeviceToHost, s));
+  AICDF_HIP(hipMemcpyAsync(&fb, ws->counter, sizeof fb, hipMemcpyDeviceToHost, s));
+  AICDF_HIP(hipStreamSynchronize(s));
+  float ms = 0.0f;
+  AICDF_HIP(hipEventElapsedTime(&ms, ws->ev0, ws->ev1));
+  out->n = n_paths;
+  for (int j = 0; j < 4; ++j) out->sum[j] = res[j];
+  out->sum_pf = res[4];
+  out->sum_pc = res[5];
+  out->kernel_ms = ms;
+  out->fallbacks = fb;
+  out->reserved = 0;
+  return ok();
+}
+
+}  // namespace aicdf
+
+using namespace aicdf;
+
+extern "C" aicdf_status mlmc_allocate(uint32_t L, double eps, const double* vh, const double* ch, const double* v2,
+                                      const double* c2, const double* v4, const double* c4, double* mh, double* m2,
+                                      double* m4, double* T_hat, double* T_tilde) {
+  if (L == 0 || !(eps > 0.0)) return fail(AICDF_EINVAL, "need n_levels > 0 and eps > 0");
+  if (!vh || !ch || !v2 || !c2 || !v4 || !c4 || !T_hat || !T_tilde) return fail(AICDF_EINVAL, "NULL array");
+  double sh = 0.0, st = 0.0;
+  for (uint32_t l = 0; l < L; ++l) {
+    if (!(vh[l] >= 0.0 && v2[l] >= 0.0 && v4[l] >= 0.0) || !(ch[l] > 0.0 && c2[l] > 0.0 && c4[l] > 0.0))
+      return fail(AICDF_EINVAL, "level %u: variances must be >= 0 and costs > 0", l);
+    sh += std::sqrt(vh[l] * ch[l]);
+    st += std::sqrt(v2[l] * c2[l]) + std::sqrt(v4[l] * c4[l]);
+  }
+  const double Th = 2.0 / (eps * eps) * sh * sh;
+  const double Tt = 2.0 / (eps * eps) * st * st;
+  for (uint32_t l = 0; l < L; ++l) {
+    if (mh) mh[l] = std::sqrt(2.0 * Th * vh[l] / ch[l]) / eps;
+    if (m2) m2[l] = std::sqrt(2.0 * Tt * v2[l] / c2[l]) / eps;
+    if (m4) m4[l] = std::sqrt(2.0 * Tt * v4[l] / c4[l]) / eps;
+  }
+  *T_hat = Th;
+  *T_tilde = Tt;
+  return ok();
+}

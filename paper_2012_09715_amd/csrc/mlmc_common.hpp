@@ -1,0 +1,73 @@
+// Shared pieces of the fused MLMC level kernels: compensated FP64 level sums
+// (per-thread Neumaier accumulation, block tree reduction into per-block
+// partials, one deterministic pass over the partials), approximate-normal
+// tables staged in LDS, and the library's per-device workspace.
+#pragma once
+
+#include <mutex>
+
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace aicdf {
+
+constexpr int kSums = 6;  // Y, Y^2, Y^3, Y^4, P_f, P_c
+constexpr int kLevelBlock = 256;
+constexpr int kMaxLevelBlocks = 4096;
+
+// Neumaier compensated sum.
+struct KSum {
+  double s = 0.0, c = 0.0;
+  __device__ __forceinline__ void add(double x) {
+    const double t = s + x;
+    c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
+    s = t;
+  }
+  __device__ __forceinline__ double value() const { return s + c; }
+};
+
+struct LevelAcc {
+  KSum k[kSums];
+  __device__ __forceinline__ void add(double y, double pf, double pc) {
+    const double y2 = y * y;
+    k[0].add(y);
+    k[1].add(y2);
+    k[2].add(y2 * y);
+    k[3].add(y2 * y2);
+    k[4].add(pf);
+    k[5].add(pc);
+  }
+};
+
+// Block-wide tree reduction of the per-thread sums into partials[blockIdx.x].
+__device__ __forceinline__ void block_reduce_store(const LevelAcc& acc, double* __restrict__ partials) {
+  __shared__ double red[kSums][kLevelBlock];
+#pragma unroll
+  for (int j = 0; j < kSums; ++j) red[j][threadIdx.x] = acc.k[j].value();
+  __syncthreads();
+  for (int o = kLevelBlock / 2; o > 0; o >>= 1) {
+    if (int(threadIdx.x) < o) {
+#pragma unroll
+      for (int j = 0; j < kSums; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < kSums) partials[size_t(blockIdx.x) * kSums + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Host side: one workspace per device (grown on demand, freed at exit), and
+// the final pass over the partials.
+struct Workspace {
+  double* partials = nullptr;  // kMaxLevelBlocks * kSums doubles
+  double* result = nullptr;    // kSums doubles
+  unsigned long long* counter = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+aicdf_status get_workspace(Workspace** ws);
+std::mutex& level_mutex();
+
+aicdf_status finish_level(Workspace* ws, unsigned nblocks, hipStream_t s, double n_paths,
+                          aicdf_level_sums* out);
+
+}  // namespace aicdf

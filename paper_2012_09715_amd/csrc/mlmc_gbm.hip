@@ -1,0 +1,277 @@
+// Fused MLMC level of geometric Brownian motion (Section 4): counter-based
+// uniforms -> exact and/or approximate normals -> coupled fine (2^l steps)
+// and coarse (2^(l-1) steps, pairwise-summed Wiener increments) paths ->
+// payoff -> compensated FP64 level sums.  One path per thread and iteration
+// of a grid-stride loop; the path state lives in registers; the
+// approximation's table is staged once per work-group in LDS.
+//
+// The correction kind carries the approximate path X~ and the difference
+// e = X^ - X~ instead of two full paths, so that the four-way difference
+// D = (P^_f - P^_c) - (P~_f - P~_c) is formed without cancellation:
+//   X~' = X~ g(dW~),   e' = e g(dW^) + X~ (g(dW^) - g(dW~)),
+// with g(dW) = 1 + r h + sigma dW (+ sigma^2 (dW^2 - h)/2 for Milstein) and
+// g(dW^) - g(dW~) = sigma d (+ sigma^2 d (dW^ + dW~)/2), d = dW^ - dW~ taken
+// from the FP64 exact normal minus the FP32 approximate one.
+#include <cmath>
+
+#include "mlmc_common.hpp"
+
+using namespace aicdf;
+
+namespace {
+
+struct GbmArgs {
+  float S0, r_dt, r_2dt, sigma, sqrt_dt, dt, half_sig2, K, disc;
+  double sqrt_dt_d;
+  uint32_t level, nsteps;
+  uint64_t n_paths, path_offset;
+  uint32_t k0, k1, tag;
+  const float* table;  // dyadic: 64 rows x 4 floats; constant: rows floats
+  uint32_t rows;
+  int table_in_lds;
+};
+
+// Approximate normal from the staged table (Algorithm 1 / Code 1).  Dyadic
+// rows are zero-padded to four coefficients, so one cubic Horner pass gives
+// the exact result of every degree.
+template <int TAB>
+__device__ __forceinline__ float approx_normal(float u, const float* tab, uint32_t rows) {
+  if constexpr (TAB == 0) {
+    const bool p = u < 0.5f;
+    const float ur = p ? u : 1.0f - u;
+    const uint32_t e = min(126u - (__float_as_uint(ur) >> 23), rows - 1u);
+    const float s = ur * __uint_as_float((128u + e) << 23);
+    const f32x4 c = reinterpret_cast<const f32x4*>(tab)[e];
+    float z = fmaf(fmaf(fmaf(c[3], s, c[2]), s, c[1]), s, c[0]);
+    return p ? z : -z;
+  } else {
+    float x = fminf(fmaxf(u * float(rows), 0.0f), float(rows - 1));
+    return tab[uint32_t(x)];
+  }
+}
+
+// One scheme step X <- X (1 + inc) over h (= dt or 2 dt, r_h = r h):
+// inc = r h + sigma dW, plus sigma^2 (dW^2 - h) / 2 for Milstein.
+template <int SCHEME>
+__device__ __forceinline__ float increment(const GbmArgs& a, float dW, float h, float r_h) {
+  float inc = fmaf(a.sigma, dW, r_h);
+  if (SCHEME == 1) inc = fmaf(a.half_sig2, fmaf(dW, dW, -h), inc);
+  return inc;
+}
+
+template <int PAYOFF>
+__device__ __forceinline__ float payoff(const GbmArgs& a, float X) {
+  return PAYOFF == 0 ? X : a.disc * fmaxf(X - a.K, 0.0f);
+}
+
+// P(X~ + e) - P(X~) without cancellation.
+template <int PAYOFF>
+__device__ __forceinline__ float payoff_diff(const GbmArgs& a, float Xt, float e) {
+  if (PAYOFF == 0) return e;
+  const float m = Xt - a.K;
+  if (m >= 0.0f && m + e >= 0.0f) return a.disc * e;
+  if (m < 0.0f && m + e < 0.0f) return 0.0f;
+  return a.disc * (fmaxf(m + e, 0.0f) - fmaxf(m, 0.0f));
+}
+
+template <int KIND, int SCHEME, int PAYOFF, int TAB>
+__global__ __launch_bounds__(kLevelBlock) void gbm_level_kernel(GbmArgs a, double* __restrict__ partials,
+                                                               double* __restrict__ path_out) {
+  extern __shared__ f32x4 lds4[];
+  const float* tab = a.table;
+  if (KIND != AICDF_KIND_EXACT && a.table_in_lds) {
+    float* l = reinterpret_cast<float*>(lds4);
+    const uint32_t nf = TAB == 0 ? 64u * 4u : a.rows;
+    for (uint32_t i = threadIdx.x; i < nf; i += kLevelBlock) l[i] = a.table[i];
+    __syncthreads();
+    tab = l;
+  }
+  LevelAcc acc;
+  const uint32_t nf = a.nsteps;
+  const uint64_t stride = uint64_t(gridDim.x) * kLevelBlock;
+  for (uint64_t i = uint64_t(blockIdx.x) * kLevelBlock + threadIdx.x; i < a.n_paths; i += stride) {
+    const uint64_t P = a.path_offset + i;
+    const uint32_t plo = uint32_t(P), phi = uint32_t(P >> 32);
+    float Y, Pf, Pc;
+    if constexpr (KIND == AICDF_KIND_APPROX) {
+      float Xf = a.S0, Xc = a.S0, dWprev = 0.0f;
+      for (uint32_t b = 0; b * 4 < nf; ++b) {
+        const u32x4 w = philox4x32_10(b, plo, phi, a.tag, a.k0, a.k1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (b * 4 + q < nf) {
+            const float dW = a.sqrt_dt * approx_normal<TAB>(u24_from_word(w[q]), tab, a.rows);
+            Xf = fmaf(Xf, increment<SCHEME>(a, dW, a.dt, a.r_dt), Xf);
+            if (q & 1) {
+              Xc = fmaf(Xc, increment<SCHEME>(a, dWprev + dW, 2.0f * a.dt, a.r_2dt), Xc);
+            } else {
+              dWprev = dW;
+            }
+          }
+        }
+      }
+      Pf = payoff<PAYOFF>(a, Xf);
+      Pc = a.level ? payoff<PAYOFF>(a, Xc) : 0.0f;
+      Y = Pf - Pc;
+    } else if constexpr (KIND == AICDF_KIND_EXACT) {
+      float Xf = a.S0, Xc = a.S0;
+      for (uint32_t b = 0; b * 2 < nf; ++b) {
+        const u32x4 w = philox4x32_10(b, plo, phi, a.tag, a.k0, a.k1);
+        const float dW0 = float(exact_phi_inv(u53_from_words(w[0], w[1])) * a.sqrt_dt_d);
+        Xf = fmaf(Xf, increment<SCHEME>(a, dW0, a.dt, a.r_dt), Xf);
+        if (nf > 1) {
+          const float dW1 = float(exact_phi_inv(u53_from_words(w[2], w[3])) * a.sqrt_dt_d);
+          Xf = fmaf(Xf, increment<SCHEME>(a, dW1, a.dt, a.r_dt), Xf);
+          Xc = fmaf(Xc, increment<SCHEME>(a, dW0 + dW1, 2.0f * a.dt, a.r_2dt), Xc);
+        }
+      }
+      Pf = payoff<PAYOFF>(a, Xf);
+      Pc = a.level ? payoff<PAYOFF>(a, Xc) : 0.0f;
+      Y = Pf - Pc;
+    } else {
+      // correction: approximate path + difference state, fine and coarse
+      float Xf = a.S0, ef = 0.0f, Xc = a.S0, ec = 0.0f;
+      for (uint32_t b = 0; b * 2 < nf; ++b) {
+        const u32x4 w = philox4x32_10(b, plo, phi, a.tag, a.k0, a.k1);
+        float sh = 0.0f, st = 0.0f, sd = 0.0f;  // coarse sums of dW^, dW~, d
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if (b * 2 + h < nf) {
+            const double Z = exact_phi_inv(u53_from_words(w[2 * h], w[2 * h + 1]));
+            const float Zt = approx_normal<TAB>(u24_from_word(w[2 * h]), tab, a.rows);
+            const float dWh = float(Z * a.sqrt_dt_d);
+            const float dWt = a.sqrt_dt * Zt;
+            const float d = float((Z - double(Zt)) * a.sqrt_dt_d);
+            const float gh = increment<SCHEME>(a, dWh, a.dt, a.r_dt);
+            float dg = a.sigma * d;
+            if (SCHEME == 1) dg = fmaf(a.half_sig2 * d, dWh + dWt, dg);
+            ef = fmaf(Xf, dg, fmaf(ef, gh, ef));
+            Xf = fmaf(Xf, increment<SCHEME>(a, dWt, a.dt, a.r_dt), Xf);
+            sh += dWh;
+            st += dWt;
+            sd += d;
+          }
+        }
+        if (nf > 1) {
+          const float h2 = 2.0f * a.dt;
+          const float gh = increment<SCHEME>(a, sh, h2, a.r_2dt);
+          float dg = a.sigma * sd;
+          if (SCHEME == 1) dg = fmaf(a.half_sig2 * sd, sh + st, dg);
+          ec = fmaf(Xc, dg, fmaf(ec, gh, ec));
+          Xc = fmaf(Xc, increment<SCHEME>(a, st, h2, a.r_2dt), Xc);
+        }
+      }
+      const float df = payoff_diff<PAYOFF>(a, Xf, ef);
+      const float dc = a.level ? payoff_diff<PAYOFF>(a, Xc, ec) : 0.0f;
+      Y = df - dc;
+      Pf = payoff<PAYOFF>(a, Xf + ef);
+      Pc = a.level ? payoff<PAYOFF>(a, Xc + ec) : 0.0f;
+    }
+    acc.add(double(Y), double(Pf), double(Pc));
+    if (path_out) {
+      path_out[3 * i] = double(Y);
+      path_out[3 * i + 1] = double(Pf);
+      path_out[3 * i + 2] = double(Pc);
+    }
+  }
+  block_reduce_store(acc, partials);
+}
+
+template <int KIND, int SCHEME, int PAYOFF, int TAB>
+void launch(const GbmArgs& a, unsigned grid, size_t lds, hipStream_t s, double* partials, double* path_out) {
+  hipLaunchKernelGGL((gbm_level_kernel<KIND, SCHEME, PAYOFF, TAB>), dim3(grid), dim3(kLevelBlock), lds, s, a,
+                     partials, path_out);
+}
+
+template <int KIND, int SCHEME, int PAYOFF>
+void launch_tab(int tab, const GbmArgs& a, unsigned grid, size_t lds, hipStream_t s, double* p, double* po) {
+  if (tab == 0)
+    launch<KIND, SCHEME, PAYOFF, 0>(a, grid, lds, s, p, po);
+  else
+    launch<KIND, SCHEME, PAYOFF, 1>(a, grid, lds, s, p, po);
+}
+
+template <int KIND>
+void launch_kind(int scheme, int payoff, int tab, const GbmArgs& a, unsigned grid, size_t lds, hipStream_t s,
+                 double* p, double* po) {
+  if (scheme == 0 && payoff == 0) launch_tab<KIND, 0, 0>(tab, a, grid, lds, s, p, po);
+  if (scheme == 0 && payoff == 1) launch_tab<KIND, 0, 1>(tab, a, grid, lds, s, p, po);
+  if (scheme == 1 && payoff == 0) launch_tab<KIND, 1, 0>(tab, a, grid, lds, s, p, po);
+  if (scheme == 1 && payoff == 1) launch_tab<KIND, 1, 1>(tab, a, grid, lds, s, p, po);
+}
+
+}  // namespace
+
+extern "C" aicdf_status mlmc_level_gbm(const aicdf_gbm_params* prm, uint32_t level, uint64_t n_paths, int32_t kind,
+                                       const aicdf_table* approx, uint64_t seed, uint64_t path_offset,
+                                       aicdf_level_sums* out, double* path_out, void* stream) {
+  if (!prm || !out) return fail(AICDF_EINVAL, "params and out must be non-NULL");
+  if (level > 20) return fail(AICDF_ERANGE, "level %u > 20", level);
+  if (kind < 0 || kind > 2) return fail(AICDF_EINVAL, "kind must be 0, 1 or 2");
+  if (prm->scheme < 0 || prm->scheme > 1 || prm->payoff < 0 || prm->payoff > 1)
+    return fail(AICDF_EINVAL, "scheme and payoff must be 0 or 1");
+  if (!(prm->T > 0.0) || !(prm->sigma >= 0.0) || !std::isfinite(prm->S0) || !std::isfinite(prm->r))
+    return fail(AICDF_EINVAL, "need T > 0, sigma >= 0, finite S0 and r");
+  if (kind != AICDF_KIND_EXACT && !approx) return fail(AICDF_EINVAL, "the approximate kinds need a table");
+  if (n_paths == 0) {
+    *out = aicdf_level_sums{};
+    return ok();
+  }
+  if (n_paths > (uint64_t(1) << 40)) return fail(AICDF_ERANGE, "n_paths > 2^40");
+  if (path_offset + n_paths < path_offset) return fail(AICDF_ERANGE, "path_offset + n_paths overflows");
+  int dev = 0;
+  AICDF_HIP(hipGetDevice(&dev));
+  if (approx && kind != AICDF_KIND_EXACT && approx->device != dev)
+    return fail(AICDF_EINVAL, "table lives on device %d, current device is %d", approx->device, dev);
+
+  const uint32_t nf = 1u << level;
+  const double dt = prm->T / nf;
+  GbmArgs a{};
+  a.S0 = float(prm->S0);
+  a.r_dt = float(prm->r * dt);
+  a.r_2dt = float(prm->r * 2.0 * dt);
+  a.sigma = float(prm->sigma);
+  a.sqrt_dt = float(std::sqrt(dt));
+  a.dt = float(dt);
+  a.half_sig2 = float(0.5 * prm->sigma * prm->sigma);
+  a.K = float(prm->K);
+  a.disc = float(std::exp(-prm->r * prm->T));
+  a.sqrt_dt_d = std::sqrt(dt);
+  a.level = level;
+  a.nsteps = nf;
+  a.n_paths = n_paths;
+  a.path_offset = path_offset;
+  a.k0 = uint32_t(seed);
+  a.k1 = uint32_t(seed >> 32);
+  a.tag = level | (uint32_t(kind) << 8);
+  int tab = 0;
+  size_t lds = 0;
+  if (kind != AICDF_KIND_EXACT) {
+    tab = approx->kind == 1 ? 0 : 1;
+    if (tab == 1 && approx->coef_t == AICDF_F64)
+      return fail(AICDF_EDTYPE, "the fused levels use FP32 arithmetic: the constant table must not be F64");
+    a.table = static_cast<const float*>(approx->dev);
+    a.rows = approx->rows;
+    const size_t bytes = tab == 0 ? 64 * 16 : size_t(approx->rows) * 4;
+    a.table_in_lds = bytes <= 64 * 1024;
+    lds = a.table_in_lds ? bytes : 0;
+  }
+  const uint64_t need = (n_paths + kLevelBlock - 1) / kLevelBlock;
+  const unsigned grid = unsigned(need < uint64_t(kMaxLevelBlocks) ? need : kMaxLevelBlocks);
+
+  std::lock_guard<std::mutex> lock(level_mutex());
+  Workspace* ws = nullptr;
+  aicdf_status st = get_workspace(&ws);
+  if (st != AICDF_OK) return st;
+  auto s = static_cast<hipStream_t>(stream);
+  AICDF_HIP(hipMemsetAsync(ws->counter, 0, sizeof(unsigned long long), s));
+  AICDF_HIP(hipEventRecord(ws->ev0, s));
+  if (kind == AICDF_KIND_EXACT)
+    launch_kind<AICDF_KIND_EXACT>(prm->scheme, prm->payoff, 0, a, grid, 0, s, ws->partials, path_out);
+  else if (kind == AICDF_KIND_APPROX)
+    launch_kind<AICDF_KIND_APPROX>(prm->scheme, prm->payoff, tab, a, grid, lds, s, ws->partials, path_out);
+  else
+    launch_kind<AICDF_KIND_CORRECTION>(prm->scheme, prm->payoff, tab, a, grid, lds, s, ws->partials, path_out);
+  AICDF_HIP(hipGetLastError());
+  return finish_level(ws, grid, s, double(n_paths), out);
+}

@@ -1,0 +1,163 @@
+"""Nested multilevel Monte Carlo driver (Section 4.1) over the fused level
+kernels of libaicdf.
+
+The regular estimator uses the EXACT kind on every level; the nested one
+uses the APPROX kind (two-way differences with approximate normals, or the
+surrogate for CIR) plus the CORRECTION kind (four-way differences).  Per
+level the driver
+  1. runs pilot calls of every kind and reads the variance v of Y and the
+     device time c per path (HIP events around the level kernel),
+  2. asks the library for the optimal allocation at RMSE eps
+     (mlmc_allocate: T^, T~, m^_l, m~_l, M~_l),
+  3. runs the allocated path counts (continuing each stream after the pilot
+     paths) and forms the estimators and their measured device times.
+The speed-up is reported two ways: T^/T~ from the cost formula with the
+measured (v, c), and the ratio of the measured device times of the two
+estimators at the same target RMSE.
+"""
+import math
+
+import paper_2012_09715_amd as A
+
+GBM_CALL = dict(S0=1.0, r=0.05, sigma=0.2, T=1.0, K=1.0, scheme=0, payoff=1)
+CIR_PARAMS = dict(v0=0.04, kappa=0.5, theta=0.04, xi=0.3, T=1.0, functional=1)
+
+KINDS = (A.KIND_EXACT, A.KIND_APPROX, A.KIND_CORRECTION)
+
+
+def level_call(model, params, level, n, kind, approx, seed, offset=0):
+    if model == "gbm":
+        return A.mlmc_level_gbm(params, level, n, kind, approx, seed, offset)
+    return A.mlmc_level_cir(params, level, n, kind, approx, seed, offset)
+
+
+class Acc:
+    """Running totals of one (level, kind) over several calls."""
+
+    def __init__(self):
+        self.n = 0.0
+        self.s1 = 0.0
+        self.s2 = 0.0
+        self.ms = 0.0
+        self.fallbacks = 0
+
+    def add(self, s):
+        self.n += s["n"]
+        self.s1 += s["sum"][0]
+        self.s2 += s["sum"][1]
+        self.ms += s["kernel_ms"]
+        self.fallbacks += s["fallbacks"]
+
+    @property
+    def mean(self):
+        return self.s1 / self.n if self.n else 0.0
+
+    @property
+    def var(self):
+        if self.n < 2:
+            return 0.0
+        m = self.mean
+        return max(self.s2 / self.n - m * m, 0.0) * self.n / (self.n - 1)
+
+    @property
+    def cost(self):
+        """device seconds per path"""
+        return self.ms * 1e-3 / self.n if self.n else 0.0
+
+
+def cost_paths(level, steps_budget=1 << 26, floor=1 << 18):
+    """Paths per cost measurement: enough path-steps (2^26) to fill the GPU
+    and amortise the per-call overhead."""
+    return max(steps_budget >> level, floor)
+
+
+def pilot(model, params, L, approx, seed, n_pilot, steps_budget=1 << 26):
+    """Per level and kind: variance from n_pilot paths, cost per path from a
+    call large enough to fill the GPU (cost_paths)."""
+    accs = [[Acc() for _ in KINDS] for _ in range(L + 1)]
+    costs = [[0.0 for _ in KINDS] for _ in range(L + 1)]
+    for l in range(L + 1):
+        for k in KINDS:
+            a = accs[l][k]
+            a.add(level_call(model, params, l, n_pilot, k, approx, seed, 0))
+            nc = cost_paths(l, steps_budget)
+            # warm launch, then a timed one on fresh paths (not used in sums)
+            level_call(model, params, l, min(nc, 4096), k, approx, seed + 7919, 0)
+            s = level_call(model, params, l, nc, k, approx, seed + 7919, 1 << 36)
+            costs[l][k] = s["kernel_ms"] * 1e-3 / nc
+    return accs, costs
+
+
+def allocate(eps, accs, costs):
+    vh = [a[A.KIND_EXACT].var for a in accs]
+    v2 = [a[A.KIND_APPROX].var for a in accs]
+    v4 = [max(a[A.KIND_CORRECTION].var, 1e-300) for a in accs]
+    ch = [c[A.KIND_EXACT] for c in costs]
+    c2 = [c[A.KIND_APPROX] for c in costs]
+    c4 = [c[A.KIND_CORRECTION] for c in costs]
+    vh = [max(v, 1e-300) for v in vh]
+    v2 = [max(v, 1e-300) for v in v2]
+    r = A.mlmc_allocate(eps, vh, ch, v2, c2, v4, c4)
+    r.update(v_hat=vh, v2=v2, v4=v4, c_hat=ch, c2=c2, c4=c4)
+    return r
+
+
+def run_estimators(model, params, L, eps, approx, seed, accs, alloc):
+    """Tops every (level, kind) up to its allocated path count and returns the
+    two estimators, their standard errors and their measured device times
+    (pilot paths included in both the estimate and the time)."""
+    out = {}
+    plan = {A.KIND_EXACT: alloc["m_hat"], A.KIND_APPROX: alloc["m_tilde"], A.KIND_CORRECTION: alloc["M_tilde"]}
+    time_ms = {k: 0.0 for k in KINDS}
+    for l in range(L + 1):
+        for k in KINDS:
+            a = accs[l][k]
+            want = int(math.ceil(plan[k][l]))
+            extra = max(want - int(a.n), 0)
+            if extra:
+                a.add(level_call(model, params, l, extra, k, approx, seed, int(a.n)))
+            time_ms[k] += a.ms
+    theta_hat = sum(accs[l][A.KIND_EXACT].mean for l in range(L + 1))
+    var_hat = sum(accs[l][A.KIND_EXACT].var / accs[l][A.KIND_EXACT].n for l in range(L + 1))
+    theta_tilde = sum(accs[l][A.KIND_APPROX].mean + accs[l][A.KIND_CORRECTION].mean for l in range(L + 1))
+    var_tilde = sum(accs[l][A.KIND_APPROX].var / accs[l][A.KIND_APPROX].n
+                    + accs[l][A.KIND_CORRECTION].var / accs[l][A.KIND_CORRECTION].n for l in range(L + 1))
+    t_hat = time_ms[A.KIND_EXACT]
+    t_tilde = time_ms[A.KIND_APPROX] + time_ms[A.KIND_CORRECTION]
+    out.update(theta_hat=theta_hat, se_hat=math.sqrt(var_hat), theta_tilde=theta_tilde,
+               se_tilde=math.sqrt(var_tilde), device_ms_hat=t_hat, device_ms_tilde=t_tilde,
+               measured_speedup=t_hat / t_tilde if t_tilde > 0 else None,
+               fallbacks=sum(accs[l][k].fallbacks for l in range(L + 1) for k in KINDS))
+    return out
+
+
+def nested_mlmc(model, params, L, eps, approx, seed, n_pilot=1 << 16, steps_budget=1 << 26):
+    accs, costs = pilot(model, params, L, approx, seed, n_pilot, steps_budget)
+    alloc = allocate(eps, accs, costs)
+    est = run_estimators(model, params, L, eps, approx, seed, accs, alloc)
+    per_level = []
+    for l in range(L + 1):
+        per_level.append({
+            "level": l,
+            "v_hat": alloc["v_hat"][l], "v2": alloc["v2"][l], "v4": alloc["v4"][l],
+            "c_hat_ns": alloc["c_hat"][l] * 1e9, "c2_ns": alloc["c2"][l] * 1e9, "c4_ns": alloc["c4"][l] * 1e9,
+            "log2_v4_over_vhat": math.log2(alloc["v4"][l] / alloc["v_hat"][l]) if alloc["v_hat"][l] > 1e-299 else None,
+            "m_hat": alloc["m_hat"][l], "m_tilde": alloc["m_tilde"][l], "M_tilde": alloc["M_tilde"][l],
+        })
+    return {"eps": eps, "levels": L, "T_hat_s": alloc["T_hat"], "T_tilde_s": alloc["T_tilde"],
+            "formula_speedup": alloc["T_hat"] / alloc["T_tilde"], **est, "per_level": per_level}
+
+
+def bench_summary(log=print, seed=20201217):
+    """Nested MLMC at RMSE 1e-3: GBM (EM, call, levels 0..8, linear-16 FP32
+    table) and GBM Milstein (levels 0..10)."""
+    res = {}
+    lin16 = A.Table.dyadic(16, 1)
+    log("mlmc: GBM Euler-Maruyama, levels 0..8")
+    res["gbm_em"] = nested_mlmc("gbm", GBM_CALL, 8, 1e-3, lin16, seed)
+    log(f"  formula speedup {res['gbm_em']['formula_speedup']:.3f}, measured {res['gbm_em']['measured_speedup']:.3f}")
+    log("mlmc: GBM Milstein, levels 0..10")
+    res["gbm_milstein"] = nested_mlmc("gbm", dict(GBM_CALL, scheme=1), 10, 1e-3, lin16, seed + 1)
+    log(f"  formula speedup {res['gbm_milstein']['formula_speedup']:.3f}, "
+        f"measured {res['gbm_milstein']['measured_speedup']:.3f}")
+    return res
