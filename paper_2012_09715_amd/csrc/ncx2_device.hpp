@@ -1,0 +1,274 @@
+// Exact non-central chi-squared CDF and inverse CDF in FP64 on the device
+// (Section 5: the inverse is found by root finding on the CDF, which is the
+// Poisson mixture of central chi-squared CDFs, Abramowitz & Stegun 26.4.25).
+//
+// With y = x/2, a = nu/2, mu = lambda/2, Poisson weights
+// w_j = e^-mu mu^j / j! and regularised incomplete gamma functions P, Q:
+//   C(x)     = sum_j w_j P(a+j, y)          1 - C(x) = sum_j w_j Q(a+j, y)
+//   pdf(x)   = sum_j w_j (1/2) y^(a+j-1) e^-y / Gamma(a+j).
+// With t_j = y^(a+j) e^-y / Gamma(a+j+1) and c_j = w_j t_j:
+//   P(a+j) = P(a+j+1) + t_j      (additive going down in j)
+//   Q(a+j+1) = Q(a+j) + t_j      (additive going up in j)
+//   pdf term j = c_j (a+j) / (2y).
+// C is therefore summed in ONE downward sweep and 1 - C in ONE upward sweep,
+// each using only additions of positive terms (the opposite directions
+// subtract and lose all relative accuracy in the far tails).  A sweep starts
+// beyond both the peak of c_j ((j+1)(a+j+1) = mu y) and the Poisson peak
+// (j = mu), 12 standard deviations plus 40 terms out, from P or Q given by the
+// power series (y < a+j+1) or the Lentz continued fraction, and stops once
+// the remaining head or tail is below 1e-17 of the sum.  The terms are carried
+// as products w_j P_j (or w_j Q_j) and c_j on a running scale (below), so that
+// no factor underflows or overflows on the way.
+#pragma once
+
+#include "device_common.hpp"
+
+namespace aicdf {
+
+struct Ncx2Val {
+  double cdf, sf, pdf;
+};
+
+// P(A, y) and Q(A, y) with t = y^A e^-y / Gamma(A+1) given (A > 0, y > 0).
+__host__ __device__ inline void inc_gamma_pq(double A, double y, double t, double& P, double& Q) {
+  if (y < A + 1.0) {
+    // P = t * sum_k y^k / ((A+1)...(A+k))
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 100000; ++k) {
+      term *= y / (A + k);
+      sum += term;
+      if (term < sum * 1e-17) break;
+    }
+    P = t * sum;
+    Q = 1.0 - P;
+  } else {
+    // Q = t A h, h the continued fraction 1/(y+1-A- 1(1-A)/(y+3-A- ...)) (Lentz)
+    const double tiny = 1e-300;
+    double b = y + 1.0 - A, c = 1.0 / tiny, d = 1.0 / b, h = d;
+    for (int k = 1; k < 100000; ++k) {
+      const double an = -k * (k - A);
+      b += 2.0;
+      d = an * d + b;
+      if (fabs(d) < tiny) d = tiny;
+      c = b + an / c;
+      if (fabs(c) < tiny) c = tiny;
+      d = 1.0 / d;
+      const double del = d * c;
+      h *= del;
+      if (fabs(del - 1.0) < 1e-16) break;
+    }
+    Q = t * A * h;
+    P = 1.0 - Q;
+  }
+}
+
+// Sweep bounds [jb, je] covering the c_j peak and the Poisson peak.
+__host__ __device__ inline void ncx2_sweep_range(double y, double a, double mu, double& jb, double& je) {
+  double js = 0.0;
+  if (mu > 0.0) js = fmax(0.0, floor(0.5 * (sqrt(a * a + 4.0 * mu * y) - (a + 2.0)) + 0.5));
+  const double lo = fmin(js, mu), hi = fmax(js, mu);
+  jb = fmax(0.0, floor(lo - 12.0 * sqrt(lo + 1.0) - 40.0));
+  je = ceil(hi + 12.0 * sqrt(hi + 1.0) + 40.0);
+  if (mu == 0.0) jb = je = 0.0;
+}
+
+// log w_j and log t_j.
+__host__ __device__ inline double ncx2_logw(double j, double mu) {
+  return mu > 0.0 ? -mu + j * log(mu) - lgamma(j + 1.0) : (j == 0.0 ? 0.0 : -1e308);
+}
+__host__ __device__ inline double ncx2_logt(double A, double y, double ly) { return A * ly - y - lgamma(A + 1.0); }
+
+// The carried terms start at O(1) (scaled by e^-L); whenever one exceeds
+// 2^600 every carried value and partial sum is multiplied by 2^-600 and the
+// count k of such rescalings grows; the result is sum e^(L + 600 k log 2).  The Poisson weight w_j, needed only for the stopping
+// bound, is carried on its own scale e^-Lw.
+constexpr double kNcx2Big = 0x1p600;
+constexpr double kNcx2Small = 0x1p-600;
+
+// C(x) and pdf(x) by the downward sweep.
+__host__ __device__ inline Ncx2Val ncx2_cdf(double x, double nu, double lam) {
+  if (!(x > 0.0)) return Ncx2Val{0.0, 1.0, 0.0};
+  if (x > 1.7976931348623157e308) return Ncx2Val{1.0, 0.0, 0.0};
+  const double y = 0.5 * x, a = 0.5 * nu, mu = 0.5 * lam, ly = log(y);
+  double jb, je;
+  ncx2_sweep_range(y, a, mu, jb, je);
+  const double A = a + je;
+  const double lw = ncx2_logw(je, mu), lt = ncx2_logt(A, y, ly);
+  double P, Q;
+  inc_gamma_pq(A, y, 1.0, P, Q);  // with t = 1: P holds S = P/t (series) or Q holds A h = Q/t
+  const double lc = lw + lt;
+  const double lD = (y < A + 1.0) ? lc + log(P) : lw + log(fmax(1.0 - Q * exp(lt), 1e-300));
+  const double L = fmax(lD, lc);
+  double D = exp(lD - L), c = exp(lc - L), w = 1.0;
+  double cdf = 0.0, pdf = 0.0;
+  int k = 0;
+  for (int j = int(je);; --j) {
+    const double Aj = a + j;
+    cdf += D;
+    pdf += c * Aj / (2.0 * y);
+    if (j == 0) break;
+    // step to j - 1: D_(j-1) = (j/mu) D_j + c_(j-1),  c_(j-1) = c_j (j/mu) ((a+j)/y)
+    const double rw = j / mu;
+    c = c * rw * (Aj / y);
+    w = w * rw;
+    D = D * rw + c;
+    if (D > kNcx2Big || c > kNcx2Big) {
+      D *= kNcx2Small;
+      c *= kNcx2Small;
+      cdf *= kNcx2Small;
+      pdf *= kNcx2Small;
+      ++k;
+    }
+    if (j - 1 < mu && j - 1 < jb + 1.0) {
+      // remaining head: sum_(k<j-1) w_k P_k <= w_(j-1) r/(1-r), r = (j-1)/mu;
+      // sum of the remaining c_k <= c_(j-1) rc/(1-rc)
+      const double r = (j - 1) / mu;
+      const double rc = r * ((a + j - 1) / y);
+      if (r < 1.0 && rc < 1.0) {
+        const double log_head = log(w) + lw - L - k * 415.88830833596718 + log(r / (1.0 - r));
+        if (log_head <= log(1e-17 * cdf) && D <= 1e-17 * cdf && c * rc / (1.0 - rc) <= 1e-17 * pdf * y) {
+          cdf += D;
+          pdf += c * (a + j - 1) / (2.0 * y);
+          break;
+        }
+      }
+    }
+  }
+  const double e = exp(L + k * 415.88830833596718);  // e^L 2^(600 k)
+  const double C = cdf * e, f = pdf * e;
+  return Ncx2Val{fmin(C, 1.0), fmax(1.0 - C, 0.0), f};
+}
+
+// 1 - C(x) and pdf(x) by the upward sweep.
+__host__ __device__ inline Ncx2Val ncx2_sf(double x, double nu, double lam) {
+  if (!(x > 0.0)) return Ncx2Val{0.0, 1.0, 0.0};
+  if (x > 1.7976931348623157e308) return Ncx2Val{1.0, 0.0, 0.0};
+  const double y = 0.5 * x, a = 0.5 * nu, mu = 0.5 * lam, ly = log(y);
+  double jb, je;
+  ncx2_sweep_range(y, a, mu, jb, je);
+  const double A = a + jb;
+  const double lw = ncx2_logw(jb, mu), lt = ncx2_logt(A, y, ly);
+  double P, Q;
+  inc_gamma_pq(A, y, 1.0, P, Q);
+  const double lc = lw + lt;
+  const double lG = (y < A + 1.0) ? lw + log(fmax(1.0 - P * exp(lt), 1e-300)) : lc + log(Q);
+  const double L = fmax(lG, lc);
+  double G = exp(lG - L), c = exp(lc - L), w = 1.0;
+  double sf = 0.0, pdf = 0.0;
+  int k = 0;
+  for (int j = int(jb); j < int(jb) + 400000; ++j) {
+    const double Aj = a + j;
+    sf += G;
+    pdf += c * Aj / (2.0 * y);
+    if (mu == 0.0) break;
+    // step to j + 1: G_(j+1) = (mu/(j+1)) (G_j + c_j),  c_(j+1) = c_j (mu/(j+1)) (y/(a+j+1))
+    const double rw = mu / (j + 1.0);
+    G = rw * (G + c);
+    c = c * rw * (y / (Aj + 1.0));
+    w = w * rw;
+    if (G > kNcx2Big || c > kNcx2Big) {
+      G *= kNcx2Small;
+      c *= kNcx2Small;
+      sf *= kNcx2Small;
+      pdf *= kNcx2Small;
+      ++k;
+    }
+    if (j + 1 > mu && j + 1 > je - 1.0) {
+      // remaining tail: sum_(k>j+1) w_k Q_k <= w_(j+1) rw'/(1-rw'), rw' = mu/(j+2)
+      const double r = mu / (j + 2.0);
+      const double rc = r * (y / (Aj + 2.0));
+      if (rc < 1.0) {
+        const double log_tail = log(w) + lw - L - k * 415.88830833596718 + log(r / (1.0 - r));
+        if (log_tail <= log(1e-17 * sf) && G <= 1e-17 * sf && c * rc / (1.0 - rc) <= 1e-17 * pdf * y) break;
+      }
+    }
+  }
+  const double e = exp(L + k * 415.88830833596718);  // e^L 2^(600 k)
+  const double S = sf * e, f = pdf * e;
+  return Ncx2Val{fmax(1.0 - S, 0.0), fmin(S, 1.0), f};
+}
+
+// Quick initial value: Patnaik's scaled central chi-squared with the
+// Wilson-Hilferty cube-root normal approximation; z from A&S 26.2.23.
+__host__ __device__ inline double ncx2_guess(double u, double nu, double lam) {
+  const double q = u < 0.5 ? u : 1.0 - u;
+  const double tt = sqrt(-2.0 * log(q));
+  double z = tt - (2.515517 + tt * (0.802853 + tt * 0.010328)) /
+                      (1.0 + tt * (1.432788 + tt * (0.189269 + tt * 0.001308)));
+  z = u < 0.5 ? -z : z;
+  const double s = nu + lam, s2 = nu + 2.0 * lam;
+  const double rho = s2 / s, k = s * s / s2;
+  const double c = 2.0 / (9.0 * k);
+  const double b = 1.0 - c + z * sqrt(c);
+  return rho * k * b * b * b;
+}
+
+// Inverse CDF by safeguarded Newton steps, inside a bracket that is valid
+// before any evaluation:
+//   lower: C(x) <= P(a, x/2) <= (x/2)^a / Gamma(a+1), so
+//          x_lo = 2 (u Gamma(a+1))^(1/a) has C(x_lo) <= u;
+//   upper: the Chernoff bound 1 - C(x) <= 2^(nu/2) e^(lambda/2) e^(-x/4)
+//          (moment generating function at s = 1/4), so
+//          x_hi = 2 nu log 2 + 2 lambda - 4 log(1-u) has 1 - C(x_hi) <= 1-u.
+// u <= 1/2: g(w) = log C(e^w) - log u in w = log x (the lower tail of C is
+//           close to a power of x, so g is close to linear in w);
+// u > 1/2:  g(x) = log(1-u) - log(1 - C(x)) in x (close to linear in x in
+//           the upper tail).
+// Steps that leave the bracket are replaced by bisection (geometric while the
+// bracket spans more than a factor of two).  `iters` receives the number of
+// CDF evaluations.
+__host__ __device__ inline double ncx2_icdf(double u, double nu, double lam, int* iters = nullptr) {
+  if (!(u > 0.0)) return u == 0.0 ? 0.0 : __builtin_nan("");
+  if (!(u < 1.0)) return u == 1.0 ? __builtin_inf() : __builtin_nan("");
+  const bool upper = u > 0.5;
+  const double a = 0.5 * nu;
+  double xlo = 2.0 * exp((log(u) + lgamma(a + 1.0)) / a);
+  double xhi = 2.0 * nu * 0.69314718055994531 + 2.0 * lam - 4.0 * log1p(-u);
+  if (!(xhi > xlo * 1.001)) xhi = xlo * 1.001 + 1e-300;
+  double x = ncx2_guess(u, nu, lam);
+  if (!(x > xlo && x < xhi)) x = sqrt(xlo) * sqrt(xhi);
+  int it = 0;
+  if (!upper) {
+    const double lu = log(u);
+    double wlo = log(xlo), whi = log(xhi), w = log(x);
+    for (; it < 100; ++it) {
+      const double xx = exp(w);
+      const Ncx2Val v = ncx2_cdf(xx, nu, lam);
+      const double g = v.cdf > 0.0 ? log(v.cdf) - lu : -1e300;
+      const double dg = v.cdf > 0.0 ? xx * v.pdf / v.cdf : 0.0;
+      if (g == 0.0) break;
+      if (g < 0.0) wlo = w; else whi = w;
+      const double tol = 2e-15 * fmax(1.0, fabs(w));
+      double wn = (dg > 0.0 && g > -1e300) ? w - g / dg : 0.5 * (wlo + whi);
+      if (fabs(wn - w) <= tol) {  // converged (may sit on the bracket end)
+        w = wn;
+        break;
+      }
+      if (!(wn > wlo && wn < whi)) wn = 0.5 * (wlo + whi);
+      w = wn;
+      if (whi - wlo <= tol) break;
+    }
+    x = exp(w);
+  } else {
+    const double lq = log1p(-u);
+    for (; it < 100; ++it) {
+      const Ncx2Val v = ncx2_sf(x, nu, lam);
+      const double g = v.sf > 0.0 ? lq - log(v.sf) : 1e300;
+      const double dg = v.sf > 0.0 ? v.pdf / v.sf : 0.0;
+      if (g == 0.0) break;
+      if (g < 0.0) xlo = x; else xhi = x;
+      double xn = (dg > 0.0 && g < 1e300) ? x - g / dg : -1.0;
+      if (xn > 0.0 && fabs(xn - x) <= 2e-15 * x) {  // converged (may sit on the bracket end)
+        x = xn;
+        break;
+      }
+      if (!(xn > xlo && xn < xhi)) xn = (xhi > 2.0 * xlo) ? sqrt(xlo) * sqrt(xhi) : 0.5 * (xlo + xhi);
+      x = xn;
+      if (xhi - xlo <= 2e-15 * x) break;
+    }
+  }
+  if (iters) *iters = it + 1;
+  return x;
+}
+
+}  // namespace aicdf

@@ -8,9 +8,6 @@ using namespace aicdf;
 extern "C" {
 aicdf_status mlmc_level_cir(const aicdf_cir_params*, uint32_t, uint64_t, int32_t, const aicdf_surrogate*,
                             uint64_t, uint64_t, aicdf_level_sums*, double*, void*) { PENDING(mlmc_level_cir); }
-aicdf_status ncx2_icdf_exact(double, size_t, const double*, const double*, double*, void*) {
-  PENDING(ncx2_icdf_exact);
-}
 aicdf_status aicdf_surrogate_create(double, double, double, uint64_t, aicdf_surrogate**) {
   PENDING(aicdf_surrogate_create);
 }

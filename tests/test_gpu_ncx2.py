@@ -1,0 +1,86 @@
+"""GPU parity of the exact non-central chi-squared inverse (Section 5)
+against the oracle's bisection on the Poisson-mixture CDF.
+
+Tolerance |x - x_oracle| <= 5e-11 x_oracle: both sides carry ~1e-12 relative
+error in C (log-form weights and gamma terms with exponents of size up to
+|a log y| ~ 1e4); in the lower tail d log C / d log x -> nu/2, which
+amplifies it by 2/nu (4x at nu = 0.5).
+"""
+import numpy as np
+import pytest
+import torch
+from scipy import stats
+
+import paper_2012_09715_amd as A
+from oracle import ncx2
+from tests.inputs import random_uniforms
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+NU_CIR = 4 * 0.5 * 0.04 / 0.3 ** 2
+
+
+def gpu_icdf(nu, u, lam):
+    ug = torch.from_numpy(np.ascontiguousarray(u, dtype=np.float64)).to(DEV)
+    lg = torch.from_numpy(np.ascontiguousarray(lam, dtype=np.float64)).to(DEV)
+    return A.ncx2_icdf_exact(nu, ug, lg).cpu().numpy()
+
+
+@pytest.mark.parametrize("nu,seed", [(NU_CIR, 1), (0.5, 2), (1.0, 3), (5.0, 4)])
+def test_parity_with_oracle(nu, seed):
+    rng = np.random.default_rng(seed)
+    n = 300
+    u = random_uniforms(n, seed)
+    u = np.clip(u, 1e-16, 1 - 1e-16)
+    lam = np.exp(rng.uniform(-12, 8, n))
+    x = gpu_icdf(nu, u, lam)
+    xo = ncx2.icdf(u, nu, lam)
+    rel = np.abs(x - xo) / xo
+    assert rel.max() <= 5e-11, (rel.max(), u[np.argmax(rel)], lam[np.argmax(rel)])
+
+
+def test_cir_levels_lambda_range():
+    # the non-centralities the CIR levels visit: lambda(v0) from 1.37 (l=0) to 1820 (l=10)
+    rng = np.random.default_rng(5)
+    u = np.concatenate([rng.random(40), [1e-16, 2.0 ** -54, 0.5, 1 - 2.0 ** -53]])
+    for lam0 in (1.37022, 113.334, 1820.0):
+        lam = np.full(len(u), lam0)
+        x = gpu_icdf(NU_CIR, u, lam)
+        xo = ncx2.icdf(u, NU_CIR, lam)
+        assert np.all(np.abs(x - xo) <= 5e-11 * xo)
+
+
+def test_closed_forms():
+    u = np.array([0.3, 1e-10, 0.999999, 0.5])
+    # nu = 2, lambda = 0: x = -2 log(1 - u)
+    assert np.allclose(gpu_icdf(2.0, u, np.zeros(4)), -2 * np.log1p(-u), rtol=1e-12)
+    # lambda = 0: central chi-squared
+    assert np.allclose(gpu_icdf(NU_CIR, u, np.zeros(4)), stats.chi2.ppf(u, NU_CIR), rtol=1e-10)
+    # nu = 1: C(x) = Phi(sqrt x - sqrt lam) - Phi(-sqrt x - sqrt lam)
+    lam = np.array([0.5, 3.0, 40.0, 7.0])
+    x = gpu_icdf(1.0, u, lam)
+    from oracle.normal import Phi
+    c = Phi(np.sqrt(x) - np.sqrt(lam)) - Phi(-np.sqrt(x) - np.sqrt(lam))
+    assert np.allclose(c[[0, 3]], u[[0, 3]], rtol=1e-12)
+
+
+def test_edges_and_errors():
+    x = gpu_icdf(NU_CIR, np.array([0.0, 1.0]), np.array([5.0, 5.0]))
+    assert x[0] == 0.0 and np.isinf(x[1])
+    u = torch.rand(10, dtype=torch.float64, device=DEV)
+    with pytest.raises(A.AicdfError, match="EALIAS"):
+        A.ncx2_icdf_exact(1.0, u, u.clone(), x=u)
+    with pytest.raises(A.AicdfError, match="EINVAL"):
+        A.ncx2_icdf_exact(-1.0, u, u.clone())
+
+
+def test_large_batch_monotone_and_mean():
+    # 2^20 inverses at one lambda: sorted u gives sorted x, and the sample mean
+    # of x matches nu + lambda
+    n = 1 << 20
+    lam = 20.0
+    u = np.sort(np.random.default_rng(7).random(n))
+    x = gpu_icdf(NU_CIR, u, np.full(n, lam))
+    assert np.all(np.diff(x) >= 0)
+    sd = np.sqrt(2 * (NU_CIR + 2 * lam))
+    assert abs(x.mean() - (NU_CIR + lam)) < 5 * sd / np.sqrt(n)
