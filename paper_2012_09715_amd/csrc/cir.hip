@@ -1,0 +1,248 @@
+// Fused MLMC level of the CIR process with exact-in-law non-central
+// chi-squared transitions (Section 5.2).  One path per thread; per step n:
+//   lambda_n = v_n e^(-kappa delta) / c,  v_(n+1) = c C_nu^-1(U_n; lambda_n),
+// with C_nu^-1 the exact FP64 inverse (EXACT), the surrogate network
+// (APPROX: P~ = MLP(D(U), g(log lambda)), x = lambda + nu + 2 sqrt(lambda+nu)
+// P~, clamped at 0), or both on one draw (CORRECTION).  The surrogate call is
+// a wave-wide matrix-core routine, so all 64 lanes step together; a lane whose
+// log lambda lies outside the trained range takes the exact inverse on the
+// same u24 instead (counted).  The coarse path of level l is the fine path
+// observed at even steps (exact in law), so only the functional differs:
+//   FUNC 0  P = v_T
+//   FUNC 1  P = trapezoidal time average on the level's grid.
+#include <cmath>
+
+#include "mlmc_common.hpp"
+#include "mlp_device.hpp"
+#include "ncx2_device.hpp"
+
+using namespace aicdf;
+
+namespace {
+
+struct CirArgs {
+  double nu, c, decay, v0;
+  float nuf, cf, decayf, v0f, lo, hi, inv_span2;
+  uint32_t level, nsteps;
+  uint64_t n_paths, path_offset;
+  uint32_t k0, k1, tag;
+};
+
+__device__ __forceinline__ float dyadic_w16(float u, const f32x4* __restrict__ tab) {
+  const bool p = u < 0.5f;
+  const float ur = p ? u : 1.0f - u;
+  const uint32_t e = min(126u - (__float_as_uint(ur) >> 23), 15u);
+  const float s = ur * __uint_as_float((128u + e) << 23);
+  const f32x4 c = tab[e];
+  const float z = fmaf(fmaf(fmaf(c[3], s, c[2]), s, c[1]), s, c[0]);
+  return p ? z : -z;
+}
+
+// Trapezoidal sums of one path: fine over every node, coarse over even nodes.
+struct FuncAcc {
+  double fine = 0.0, coarse = 0.0;
+  __device__ __forceinline__ void node(uint32_t k, uint32_t N, double v) {
+    const double wt = (k == 0 || k == N) ? 0.5 : 1.0;
+    fine += wt * v;
+    if ((k & 1u) == 0) coarse += wt * v;
+  }
+  template <int FUNC>
+  __device__ __forceinline__ void result(uint32_t level, uint32_t N, double vN, double& Pf, double& Pc) const {
+    if (FUNC == 0) {
+      Pf = vN;
+      Pc = level ? vN : 0.0;
+    } else {
+      Pf = fine / N;
+      Pc = level ? coarse / (N / 2) : 0.0;
+    }
+  }
+};
+
+template <int KIND, int FUNC>
+__global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const float* __restrict__ params,
+                                                               const uint16_t* __restrict__ w2b,
+                                                               const f32x4* __restrict__ wtab,
+                                                               double* __restrict__ partials,
+                                                               double* __restrict__ path_out,
+                                                               unsigned long long* __restrict__ fallbacks) {
+  constexpr bool kExact = KIND != AICDF_KIND_APPROX;
+  constexpr bool kSurr = KIND != AICDF_KIND_EXACT;
+  __shared__ MlpLds L;
+  __shared__ f32x4 tab[16];
+  bf16x8 A[2][4];
+  if (kSurr) {
+    mlp_stage_params(L, params, threadIdx.x, kLevelBlock);
+    if (threadIdx.x < 16) tab[threadIdx.x] = wtab[threadIdx.x];
+    __syncthreads();
+    mlp_load_w2(w2b, A);
+  }
+  LevelAcc acc;
+  unsigned long long fb = 0;
+  const uint32_t N = a.nsteps;
+  for (uint64_t base = uint64_t(blockIdx.x) * kLevelBlock; base < a.n_paths;
+       base += uint64_t(gridDim.x) * kLevelBlock) {
+    const uint64_t i = base + threadIdx.x;
+    const bool act = i < a.n_paths;
+    const uint64_t P = a.path_offset + i;
+    const uint32_t plo = uint32_t(P), phi = uint32_t(P >> 32);
+    double ve = a.v0;
+    float vs = a.v0f;
+    FuncAcc fe, fs;
+    if (FUNC == 1) {
+      fe.node(0, N, ve);
+      fs.node(0, N, double(vs));
+    }
+    u32x4 w{};
+    for (uint32_t n = 0; n < N; ++n) {
+      double u53 = 0.5;
+      float u24 = 0.5f;
+      if (KIND == AICDF_KIND_APPROX) {
+        if ((n & 3u) == 0) w = philox4x32_10(n >> 2, plo, phi, a.tag, a.k0, a.k1);
+        u24 = u24_from_word(w[n & 3u]);
+      } else {
+        if ((n & 1u) == 0) w = philox4x32_10(n >> 1, plo, phi, a.tag, a.k0, a.k1);
+        const uint32_t hi = (n & 1u) ? w[2] : w[0], lo = (n & 1u) ? w[3] : w[1];
+        u53 = u53_from_words(hi, lo);
+        u24 = u24_from_word(hi);
+      }
+      if (kExact) {
+        const double lam = ve * a.decay / a.c;
+        ve = a.c * ncx2_icdf(u53, a.nu, lam);
+        if (FUNC == 1) fe.node(n + 1, N, ve);
+      }
+      if (kSurr) {
+        const float lam = vs * a.decayf / a.cf;
+        const float ll = lam > 0.0f ? __logf(lam) : -1e30f;
+        const bool inr = ll >= a.lo && ll <= a.hi;
+        const float g = inr ? mlp_g(ll, a.lo, a.inv_span2) : 0.0f;
+        const float Pt = mlp_wave_forward(L, A, dyadic_w16(u24, tab), g);  // all lanes
+        float x;
+        if (inr) {
+          const float s = lam + a.nuf;
+          x = fmaxf(fmaf(2.0f * sqrtf(s), Pt, s), 0.0f);
+        } else {
+          x = float(ncx2_icdf(double(u24), a.nu, double(lam)));
+          fb += act ? 1 : 0;
+        }
+        vs = a.cf * x;
+        if (FUNC == 1) fs.node(n + 1, N, double(vs));
+      }
+    }
+    double Y = 0.0, Pf = 0.0, Pc = 0.0;
+    if (KIND == AICDF_KIND_APPROX) {
+      fs.template result<FUNC>(a.level, N, double(vs), Pf, Pc);
+      Y = Pf - Pc;
+    } else {
+      fe.template result<FUNC>(a.level, N, ve, Pf, Pc);
+      Y = Pf - Pc;
+      if (KIND == AICDF_KIND_CORRECTION) {
+        double Qf, Qc;
+        fs.template result<FUNC>(a.level, N, double(vs), Qf, Qc);
+        Y -= Qf - Qc;
+      }
+    }
+    if (act) {
+      acc.add(Y, Pf, Pc);
+      if (path_out) {
+        path_out[3 * i] = Y;
+        path_out[3 * i + 1] = Pf;
+        path_out[3 * i + 2] = Pc;
+      }
+    }
+  }
+  block_reduce_store(acc, partials);
+  if (kSurr) {
+    __shared__ unsigned long long fbs[kLevelBlock];
+    fbs[threadIdx.x] = fb;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long t = 0;
+      for (int k = 0; k < kLevelBlock; ++k) t += fbs[k];
+      if (t) atomicAdd(fallbacks, t);
+    }
+  }
+}
+
+template <int KIND>
+void launch_func(int func, const CirArgs& a, unsigned grid, hipStream_t s, const float* p, const uint16_t* w2,
+                 const f32x4* wt, double* part, double* po, unsigned long long* fb) {
+  if (func == 0)
+    hipLaunchKernelGGL((cir_level_kernel<KIND, 0>), dim3(grid), dim3(kLevelBlock), 0, s, a, p, w2, wt, part, po, fb);
+  else
+    hipLaunchKernelGGL((cir_level_kernel<KIND, 1>), dim3(grid), dim3(kLevelBlock), 0, s, a, p, w2, wt, part, po, fb);
+}
+
+}  // namespace
+
+extern "C" aicdf_status mlmc_level_cir(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths, int32_t kind,
+                                       const aicdf_surrogate* sur, uint64_t seed, uint64_t path_offset,
+                                       aicdf_level_sums* out, double* path_out, void* stream) {
+  if (!prm || !out) return fail(AICDF_EINVAL, "params and out must be non-NULL");
+  if (level > 12) return fail(AICDF_ERANGE, "level %u > 12", level);
+  if (kind < 0 || kind > 2) return fail(AICDF_EINVAL, "kind must be 0, 1 or 2");
+  if (prm->functional < 0 || prm->functional > 1 || prm->reserved != 0)
+    return fail(AICDF_EINVAL, "functional must be 0 or 1 and reserved 0");
+  if (!(prm->kappa > 0.0) || !(prm->theta > 0.0) || !(prm->xi > 0.0) || !(prm->T > 0.0) || !(prm->v0 >= 0.0))
+    return fail(AICDF_EINVAL, "need kappa, theta, xi, T > 0 and v0 >= 0");
+  if (kind != AICDF_KIND_EXACT && !sur) return fail(AICDF_EINVAL, "the approximate kinds need a surrogate");
+  if (n_paths == 0) {
+    *out = aicdf_level_sums{};
+    return ok();
+  }
+  if (n_paths > (uint64_t(1) << 40)) return fail(AICDF_ERANGE, "n_paths > 2^40");
+  if (path_offset + n_paths < path_offset) return fail(AICDF_ERANGE, "path_offset + n_paths overflows");
+  const double nu = 4.0 * prm->kappa * prm->theta / (prm->xi * prm->xi);
+  double snu = nu, lo = 0.0, hi = 0.0;
+  int sdev = 0, dev = 0;
+  AICDF_HIP(hipGetDevice(&dev));
+  if (sur) {
+    surrogate_range(sur, &snu, &lo, &hi, &sdev);
+    if (kind != AICDF_KIND_EXACT) {
+      if (sdev != dev) return fail(AICDF_EINVAL, "surrogate lives on device %d, current device is %d", sdev, dev);
+      if (std::fabs(snu - nu) > 1e-12 * nu)
+        return fail(AICDF_EINVAL, "surrogate was built for nu = %.17g, the process has nu = %.17g", snu, nu);
+    }
+  }
+  const uint32_t N = 1u << level;
+  const double dt = prm->T / N;
+  CirArgs a{};
+  a.nu = nu;
+  a.decay = std::exp(-prm->kappa * dt);
+  a.c = prm->xi * prm->xi * (1.0 - a.decay) / (4.0 * prm->kappa);
+  a.v0 = prm->v0;
+  a.nuf = float(nu);
+  a.cf = float(a.c);
+  a.decayf = float(a.decay);
+  a.v0f = float(prm->v0);
+  a.lo = float(lo);
+  a.hi = float(hi);
+  a.inv_span2 = sur ? float(2.0 / (hi - lo)) : 0.0f;
+  a.level = level;
+  a.nsteps = N;
+  a.n_paths = n_paths;
+  a.path_offset = path_offset;
+  a.k0 = uint32_t(seed);
+  a.k1 = uint32_t(seed >> 32);
+  a.tag = level | (uint32_t(4 + kind) << 8);
+  const uint64_t need = (n_paths + kLevelBlock - 1) / kLevelBlock;
+  const unsigned grid = unsigned(need < uint64_t(kMaxLevelBlocks) ? need : kMaxLevelBlocks);
+
+  std::lock_guard<std::mutex> lock(level_mutex());
+  Workspace* ws = nullptr;
+  aicdf_status st = get_workspace(&ws);
+  if (st != AICDF_OK) return st;
+  auto s = static_cast<hipStream_t>(stream);
+  const float* p = sur ? surrogate_params(sur) : nullptr;
+  const uint16_t* w2 = sur ? surrogate_w2b(sur) : nullptr;
+  const f32x4* wt = sur ? reinterpret_cast<const f32x4*>(surrogate_wtab(sur)) : nullptr;
+  AICDF_HIP(hipMemsetAsync(ws->counter, 0, sizeof(unsigned long long), s));
+  AICDF_HIP(hipEventRecord(ws->ev0, s));
+  if (kind == AICDF_KIND_EXACT)
+    launch_func<AICDF_KIND_EXACT>(prm->functional, a, grid, s, p, w2, wt, ws->partials, path_out, ws->counter);
+  else if (kind == AICDF_KIND_APPROX)
+    launch_func<AICDF_KIND_APPROX>(prm->functional, a, grid, s, p, w2, wt, ws->partials, path_out, ws->counter);
+  else
+    launch_func<AICDF_KIND_CORRECTION>(prm->functional, a, grid, s, p, w2, wt, ws->partials, path_out, ws->counter);
+  AICDF_HIP(hipGetLastError());
+  return finish_level(ws, grid, s, double(n_paths), out);
+}

@@ -54,6 +54,12 @@ std::vector<double> build_const_table(uint32_t n, int construction);
 std::vector<double> build_dyadic_table(uint32_t n_entries, uint32_t degree);
 double round_to_dtype(double x, aicdf_dtype t);
 
+// Surrogate internals used by the CIR level (surrogate.hip).
+const float* surrogate_params(const aicdf_surrogate* s);
+const uint16_t* surrogate_w2b(const aicdf_surrogate* s);
+const float* surrogate_wtab(const aicdf_surrogate* s);
+void surrogate_range(const aicdf_surrogate* s, double* nu, double* lo, double* hi, int* dev);
+
 }  // namespace aicdf
 
 // A coefficient table: host FP64 copy of the stored (dtype-rounded) values

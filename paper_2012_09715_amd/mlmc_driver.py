@@ -148,9 +148,40 @@ def nested_mlmc(model, params, L, eps, approx, seed, n_pilot=1 << 16, steps_budg
             "formula_speedup": alloc["T_hat"] / alloc["T_tilde"], **est, "per_level": per_level}
 
 
+NU_CIR = 4 * CIR_PARAMS["kappa"] * CIR_PARAMS["theta"] / CIR_PARAMS["xi"] ** 2
+SURROGATE_RANGE = (-8.0, 10.0)
+
+
+def train_surrogate(n_train=10_000_000, epochs=8, batch=4096, lr=3e-3, seed=20201217, n_eval=1 << 18, log=print):
+    """Builds and trains the CIR surrogate on n_train exact FP64 targets;
+    returns (surrogate, report) with the held-out RMSE against exact targets."""
+    import time
+    import torch
+    s = A.Surrogate.create(NU_CIR, *SURROGATE_RANGE, seed=seed)
+    t0 = time.perf_counter()
+    u, ll, t = s.make_data(n_train, seed)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ue, lle, te = s.make_data(n_eval, seed + 1)
+    before = float(torch.sqrt(((s.forward(ue, lle) - te) ** 2).mean()))
+    loss = s.train(u, ll, t, epochs=epochs, batch=batch, lr=lr, seed=seed)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    err = (s.forward(ue, lle) - te).double()
+    rep = {"n_train": n_train, "epochs": epochs, "batch": batch, "lr": lr,
+           "data_seconds": t1 - t0, "train_seconds": t2 - t1, "final_train_mse": loss,
+           "holdout_rmse_before": before, "holdout_rmse": float(torch.sqrt((err ** 2).mean())),
+           "holdout_max_abs": float(err.abs().max()), "nu": NU_CIR, "loglam_range": SURROGATE_RANGE}
+    log(f"surrogate: held-out RMSE {rep['holdout_rmse']:.3e} (untrained {before:.3e}), "
+        f"data {rep['data_seconds']:.2f} s, training {rep['train_seconds']:.2f} s")
+    del u, ll, t
+    return s, rep
+
+
 def bench_summary(log=print, seed=20201217):
     """Nested MLMC at RMSE 1e-3: GBM (EM, call, levels 0..8, linear-16 FP32
-    table) and GBM Milstein (levels 0..10)."""
+    table), GBM Milstein (levels 0..10) and CIR (time average, levels 0..6,
+    trained surrogate)."""
     res = {}
     lin16 = A.Table.dyadic(16, 1)
     log("mlmc: GBM Euler-Maruyama, levels 0..8")
@@ -160,4 +191,9 @@ def bench_summary(log=print, seed=20201217):
     res["gbm_milstein"] = nested_mlmc("gbm", dict(GBM_CALL, scheme=1), 10, 1e-3, lin16, seed + 1)
     log(f"  formula speedup {res['gbm_milstein']['formula_speedup']:.3f}, "
         f"measured {res['gbm_milstein']['measured_speedup']:.3f}")
+    sur, rep = train_surrogate(seed=seed, log=log)
+    res["surrogate"] = rep
+    log("mlmc: CIR time average, levels 0..6, surrogate")
+    res["cir"] = nested_mlmc("cir", CIR_PARAMS, 6, 1e-3, sur, seed + 2, steps_budget=1 << 24)
+    log(f"  formula speedup {res['cir']['formula_speedup']:.3f}, measured {res['cir']['measured_speedup']:.3f}")
     return res

@@ -1,0 +1,144 @@
+"""GPU parity of the fused CIR level (Section 5.2) against the oracle's
+per-path replay, and its statistical pins.
+
+The surrogate used here has seeded weights with a damped output layer (so
+that x~ stays close to the Gaussian approximation lambda + nu +
+2 sqrt(lambda + nu) D(U)); the same weights drive the oracle's FP64 forward.
+Tolerances: EXACT paths are FP64 on both sides (|d| <= 1e-9 relative to the
+path's scale); surrogate paths are FP32 on the device (|d| <= 2e-4 N relative).
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2012_09715_amd as A
+from oracle import cir, mlp, ncx2, tables
+from oracle.dtypes import round_f32
+from oracle.transform import dyadic_transform_f32
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+CIR = dict(v0=0.04, kappa=0.5, theta=0.04, xi=0.3, T=1.0, functional=0)
+NU = 4 * 0.5 * 0.04 / 0.3 ** 2
+LO, HI = -8.0, 10.0
+CUBIC = round_f32(tables.dyadic_table(16, 3))
+
+
+def flat(p):
+    return np.concatenate([np.asarray(p[k], float).ravel() for k in mlp.PARAM_ORDER]).astype(np.float32)
+
+
+@pytest.fixture(scope="module")
+def damped():
+    p = mlp.init_params(21)
+    p["W3"] = p["W3"] * 0.05
+    p["b3"] = np.array(0.0)
+    v = flat(p)
+    s = A.Surrogate.create(NU, LO, HI, seed=1)
+    s.set_params(v)
+    # the oracle uses the same FP32-rounded parameters
+    q, o = {}, 0
+    for k in mlp.PARAM_ORDER:
+        n = int(np.prod(mlp.PARAM_SHAPES[k])) if mlp.PARAM_SHAPES[k] else 1
+        q[k] = v[o:o + n].astype(np.float64).reshape(mlp.PARAM_SHAPES[k])
+        o += n
+    return s, q
+
+
+def oracle_surrogate_x(q):
+    def f(u, lam):
+        u = np.asarray(u, float)
+        lam = np.asarray(lam, float)
+        with np.errstate(divide="ignore"):
+            ll = np.where(lam > 0, np.log(np.where(lam > 0, lam, 1.0)), -np.inf)
+        inr = (ll >= LO) & (ll <= HI)
+        w = dyadic_transform_f32(CUBIC, u.astype(np.float32))[0].astype(np.float64)
+        P = mlp.forward(q, w, np.where(inr, mlp.g_feature(np.where(inr, ll, 0.0), LO, HI), 0.0), bf16=True)
+        s = lam + NU
+        x = np.maximum(s + 2 * np.sqrt(s) * P, 0.0)
+        out = x.copy()
+        if (~inr).any():
+            out[~inr] = ncx2.icdf(u[~inr], NU, lam[~inr])
+        return out
+    return f
+
+
+def run(params, level, n, kind, sur, seed, offset=0):
+    out = torch.zeros(n * 3, dtype=torch.float64, device=DEV)
+    s = A.mlmc_level_cir(params, level, n, kind, sur, seed, offset, path_out=out)
+    return s, out.cpu().numpy().reshape(n, 3)
+
+
+@pytest.mark.parametrize("functional", [0, 1])
+@pytest.mark.parametrize("level", [0, 2])
+def test_exact_kind_parity(functional, level):
+    p = dict(CIR, functional=functional)
+    n, seed, off = 48, 11 + level, 1000
+    _, got = run(p, level, n, 0, None, seed, off)
+    ref = cir.level_replay(p, level, 0, seed, off + np.arange(n))
+    scale = np.maximum(np.abs(ref[1]), 1e-3)
+    for j in range(3):
+        assert np.all(np.abs(got[:, j] - ref[j]) <= 1e-9 * scale), j
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("level", [0, 3])
+def test_surrogate_kinds_parity(damped, kind, level):
+    s, q = damped
+    p = dict(CIR, functional=1)
+    n, seed = 64, 31 + level
+    st, got = run(p, level, n, kind, s, seed)
+    ref = cir.level_replay(p, level, kind, seed, np.arange(n), surrogate_x=oracle_surrogate_x(q))
+    N = 1 << level
+    scale = np.maximum(np.abs(ref[1]), 1e-3)
+    assert np.all(np.abs(got[:, 1] - ref[1]) <= 2e-4 * N * scale)
+    assert np.all(np.abs(got[:, 0] - ref[0]) <= 2e-4 * N * scale)
+
+
+def test_split_determinism_and_fallbacks(damped):
+    s, _ = damped
+    p = dict(CIR, functional=1)
+    st, whole = run(p, 2, 3000, 2, s, 5)
+    _, a = run(p, 2, 1000, 2, s, 5, 0)
+    _, b = run(p, 2, 2000, 2, s, 5, 1000)
+    assert np.array_equal(whole, np.concatenate([a, b]))
+    st2 = A.mlmc_level_cir(p, 2, 3000, 2, s, 5)
+    assert st["sum"] == st2["sum"] and st["fallbacks"] == st2["fallbacks"]
+    # a surrogate whose range excludes every lambda falls back on every step
+    narrow = A.Surrogate.create(NU, 50.0, 51.0, seed=2)
+    sn = A.mlmc_level_cir(p, 2, 1000, 1, narrow, 5)
+    assert sn["fallbacks"] == 1000 * 4
+
+
+def test_exact_mean_and_variance():
+    # E v_T = 0.04, Var v_T = 0.0022756340 (level 0: one exact transition)
+    n = 1 << 18
+    s = A.mlmc_level_cir(CIR, 0, n, 0, None, 9)
+    m = s["sum"][0] / n
+    var = s["sum"][1] / n - m * m
+    assert abs(m - 0.04) < 5 * np.sqrt(0.0022756340 / n)
+    assert abs(var - 0.0022756340) < 0.05 * 0.0022756340
+    # E v_T does not depend on the number of exact steps
+    s3 = A.mlmc_level_cir(dict(CIR, functional=0), 3, 1 << 16, 0, None, 10)
+    assert abs(s3["sum_pf"] / (1 << 16) - 0.04) < 5 * np.sqrt(0.0023 / (1 << 16))
+    assert s3["sum"][0] == 0.0  # P_l - P_(l-1) = 0 for v_T
+
+
+def test_time_average_mean():
+    p = dict(CIR, functional=1)
+    n = 1 << 16
+    for level in (0, 2):
+        s = A.mlmc_level_cir(p, level, n, 0, None, 40 + level)
+        m = s["sum_pf"] / n
+        assert abs(m - cir.mean_time_average(p, level)) < 5 * 0.05 / np.sqrt(n)
+
+
+def test_errors(damped):
+    s, _ = damped
+    with pytest.raises(A.AicdfError, match="EINVAL"):
+        A.mlmc_level_cir(CIR, 2, 10, 1, None, 0)
+    other = A.Surrogate.create(2.0, LO, HI, seed=0)
+    with pytest.raises(A.AicdfError, match="nu"):
+        A.mlmc_level_cir(CIR, 2, 10, 1, other, 0)
+    with pytest.raises(A.AicdfError, match="ERANGE"):
+        A.mlmc_level_cir(CIR, 13, 10, 0, None, 0)

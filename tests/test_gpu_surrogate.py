@@ -1,0 +1,134 @@
+"""GPU parity of the surrogate network (inference, loss gradient, training
+targets) against the oracle's FP64 forward/backward.
+
+Tolerances
+  forward    |dP| <= 2e-4 max(1, |P|): the oracle rounds h1 and W2 to BF16
+             like the kernels, but its FP64 silu may place an h1 value on the
+             other side of a BF16 rounding boundary (one BF16 ulp of h1, about
+             4e-3 relative, reaching P through W2 and W3)
+  gradient   relative norm error <= 2e-2 per parameter block (the kernels
+             also round da2 to BF16 for the two backward matrix products)
+  targets    |dP| <= 4e-7 max(1, |P|) (FP32 storage of an exact FP64 value)
+Trained weights are parity unpinned (learned); training is checked by its
+loss and by the held-out error against exact targets.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2012_09715_amd as A
+from oracle import mlp, ncx2, tables
+from oracle.dtypes import round_f32
+from oracle.transform import dyadic_transform_f32
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+NU = 4 * 0.5 * 0.04 / 0.3 ** 2
+LO, HI = -8.0, 10.0
+
+
+def flat(p):
+    return np.concatenate([np.asarray(p[k], float).ravel() for k in mlp.PARAM_ORDER]).astype(np.float32)
+
+
+def unflat(v):
+    out, o = {}, 0
+    for k in mlp.PARAM_ORDER:
+        n = int(np.prod(mlp.PARAM_SHAPES[k])) if mlp.PARAM_SHAPES[k] else 1
+        out[k] = np.asarray(v[o:o + n], float).reshape(mlp.PARAM_SHAPES[k])
+        o += n
+    return out
+
+
+CUBIC = round_f32(tables.dyadic_table(16, 3))
+
+
+def w_feature(u):
+    return dyadic_transform_f32(CUBIC, np.asarray(u, np.float32))[0].astype(np.float64)
+
+
+def inputs(n, seed):
+    rng = np.random.default_rng(seed)
+    u = ((rng.integers(0, 1 << 23, n) + 0.5) * 2.0 ** -23).astype(np.float32)
+    ll = rng.uniform(LO, HI, n).astype(np.float32)
+    return u, ll
+
+
+@pytest.fixture(scope="module")
+def sur():
+    s = A.Surrogate.create(NU, LO, HI, seed=3)
+    p = mlp.init_params(11)
+    s.set_params(flat(p))
+    return s, unflat(flat(p))
+
+
+def test_params_round_trip(sur):
+    s, p = sur
+    assert np.array_equal(s.get_params().numpy(), flat(p))
+    assert s.info() == pytest.approx((NU, LO, HI))
+
+
+def test_forward_parity(sur):
+    s, p = sur
+    u, ll = inputs(50_001, 1)
+    got = s.forward(torch.from_numpy(u).to(DEV), torch.from_numpy(ll).to(DEV)).cpu().numpy().astype(np.float64)
+    ref = mlp.forward(p, w_feature(u), mlp.g_feature(ll.astype(np.float64), LO, HI), bf16=True)
+    err = np.abs(got - ref) / np.maximum(1.0, np.abs(ref))
+    assert err.max() <= 2e-4, err.max()
+    assert np.median(err) <= 5e-6
+
+
+def test_loss_grad_parity(sur):
+    s, p = sur
+    n = 4096
+    u, ll = inputs(n, 2)
+    t = np.random.default_rng(4).normal(size=n).astype(np.float32)
+    loss, g = s.loss_grad(torch.from_numpy(u).to(DEV), torch.from_numpy(ll).to(DEV), torch.from_numpy(t).to(DEV))
+    L, gr = mlp.loss_and_grads(p, w_feature(u), mlp.g_feature(ll.astype(np.float64), LO, HI), t.astype(np.float64),
+                               bf16=True)
+    assert loss == pytest.approx(L, rel=1e-4)
+    gg = unflat(g.numpy())
+    for k in mlp.PARAM_ORDER:
+        a, b = np.atleast_1d(gg[k]).ravel(), np.atleast_1d(gr[k]).ravel()
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        assert rel <= 2e-2, (k, rel)
+
+
+def test_loss_grad_ragged_batch(sur):
+    s, p = sur
+    n = 1000  # not a multiple of the 64-sample wave
+    u, ll = inputs(n, 5)
+    t = np.zeros(n, np.float32)
+    loss, g = s.loss_grad(torch.from_numpy(u).to(DEV), torch.from_numpy(ll).to(DEV), torch.from_numpy(t).to(DEV))
+    L, gr = mlp.loss_and_grads(p, w_feature(u), mlp.g_feature(ll.astype(np.float64), LO, HI), t.astype(np.float64))
+    assert loss == pytest.approx(L, rel=1e-4)
+    gg = unflat(g.numpy())
+    assert np.linalg.norm(gg["W2"] - gr["W2"]) <= 2e-2 * np.linalg.norm(gr["W2"])
+
+
+def test_training_targets_are_exact(sur):
+    s, _ = sur
+    n = 1 << 16
+    u, ll, t = s.make_data(n, seed=77)
+    u, ll, t = (x.cpu().numpy().astype(np.float64) for x in (u, ll, t))
+    assert np.all((u > 0) & (u < 1)) and np.all((ll >= LO) & (ll <= HI))
+    assert np.mean(u < 1e-3) > 0.01  # tail-weighted eighth present
+    idx = np.random.default_rng(0).choice(n, 200, replace=False)
+    lam = np.exp(ll[idx])
+    P = ncx2.P_from_x(ncx2.icdf(u[idx], NU, lam), NU, lam)
+    assert np.all(np.abs(t[idx] - P) <= 4e-7 * np.maximum(1.0, np.abs(P)))
+
+
+def test_training_reduces_error_and_save_load(tmp_path):
+    s = A.Surrogate.create(NU, LO, HI, seed=5)
+    u, ll, t = s.make_data(1 << 20, seed=8)
+    ue, lle, te = s.make_data(1 << 14, seed=9)
+    before = float(((s.forward(ue, lle) - te) ** 2).mean())
+    loss = s.train(u, ll, t, epochs=8, batch=2048, lr=3e-3, seed=1)
+    after = float(((s.forward(ue, lle) - te) ** 2).mean())
+    assert after < 0.01 * before and after < 1e-2, (before, after, loss)
+    f = tmp_path / "s.bin"
+    s.save(f)
+    s2 = A.Surrogate.load(f)
+    assert np.array_equal(s2.get_params().numpy(), s.get_params().numpy())
+    assert torch.equal(s2.forward(ue, lle), s.forward(ue, lle))
