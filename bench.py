@@ -14,8 +14,10 @@ steps.  The JSON line also carries
                 table): samples/s, GB/s and the exact RMSE/max error against
                 FP64 Phi^-1 over the whole u24 input grid
   bandwidth     the plain copy kernel on the same byte count
-  mlmc          nested-MLMC results (GBM and CIR) when run with --mlmc
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only-main] [--mlmc]
+  mlmc          nested-MLMC speed-ups over the exact inverse at fixed RMSE:
+                GBM (Euler-Maruyama, Milstein) with the linear-16 table and
+                CIR with the trained BF16 surrogate (skip with --no-mlmc)
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only-main] [--no-mlmc]
 """
 import argparse
 import json
@@ -41,7 +43,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--only-main", action="store_true",
                     help="time the main transform and the copy probe only (for profiler runs)")
-    ap.add_argument("--mlmc", action="store_true", help="also run the nested MLMC measurements")
+    ap.add_argument("--no-mlmc", action="store_true", help="skip the nested MLMC measurements")
+    ap.add_argument("--detail", default=None, help="write the full per-level MLMC results to this JSON file")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
 
@@ -211,9 +214,13 @@ def main():
     torch.cuda.empty_cache()
 
     # ---------------------------------------------------------- MLMC
-    if args.mlmc:
+    if not args.no_mlmc:
         from paper_2012_09715_amd import mlmc_driver
-        result["mlmc"] = mlmc_driver.bench_summary(log=log)
+        full = mlmc_driver.bench_summary(log=log)
+        if args.detail:
+            with open(args.detail, "w") as f:
+                json.dump(full, f, indent=1)
+        result["mlmc"] = {k: (v if k == "surrogate" else mlmc_driver._short(v)) for k, v in full.items()}
 
     # ---------------------------------------------------------- CPU baseline
     log("cpu baseline (oracle) ...")
