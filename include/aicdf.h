@@ -10,7 +10,7 @@
  *  - Pointers named "device" are HIP device pointers on the current device;
  *    pointers named "host" are host memory.  The caller owns every buffer it
  *    passes; the library never frees caller memory.
- *  - Opaque handles (aicdf_table, aicdf_surrogate) are library-owned and are
+ *  - Opaque handles (aicdf_table, aicdf_chi2_table, aicdf_surrogate) are library-owned and are
  *    released with their destroy call; destroy(NULL) is a no-op.  A handle is
  *    bound to the device that was current when it was created.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
@@ -246,6 +246,21 @@ aicdf_status mlmc_level_cir(const aicdf_cir_params* params, uint32_t level, uint
                             uint64_t path_offset, aicdf_level_sums* out, double* path_out,
                             void* stream);
 
+typedef struct aicdf_chi2_table aicdf_chi2_table;
+
+/* As mlmc_level_cir with Section 5.1's piecewise-polynomial approximation in
+ * place of the surrogate (the paper's own approximate CIR transition, Table 7
+ * and Figure 4b): APPROX steps take x~ = max(C~^-1(u24; lambda), 0) in FP32
+ * with no fallback (the knots cover every lambda >= 0); CORRECTION pairs it
+ * with the exact FP64 inverse on the same draw.  `approx` must be built for
+ * the process's nu = 4 kappa theta / xi^2 (relative difference <= 1e-12),
+ * and is required unless kind == EXACT.  Draws and streams are those of
+ * mlmc_level_cir.  Errors: EINVAL, ERANGE, EHIP, ENOMEM. */
+aicdf_status mlmc_level_cir_table(const aicdf_cir_params* params, uint32_t level, uint64_t n_paths,
+                                  int32_t kind, const aicdf_chi2_table* approx, uint64_t seed,
+                                  uint64_t path_offset, aicdf_level_sums* out, double* path_out,
+                                  void* stream);
+
 /* Optimal allocation of the nested estimator at RMSE eps (Section 4.1):
  *   T^ = 2 eps^-2 (sum_l sqrt(v^_l c^_l))^2,
  *   T~ = 2 eps^-2 (sum_l sqrt(v~_l c~_l) + sqrt(V~_l C~_l))^2,
@@ -271,6 +286,43 @@ aicdf_status mlmc_allocate(uint32_t n_levels, double eps, const double* v_hat, c
  * u = 0 gives 0, u = 1 gives +inf.  Errors: EINVAL, EALIAS, EHIP. */
 aicdf_status ncx2_icdf_exact(double nu, size_t n, const double* u, const double* lambda,
                              double* x, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Piecewise-polynomial chi-squared approximation (Section 5.1)              */
+/* ------------------------------------------------------------------------ */
+/* At a fixed nu, C_nu^-1(U; lambda) = lambda + nu + 2 sqrt(lambda + nu) P(U; y)
+ * with y = nu / (lambda + nu) in (0, 1].  The approximation P~ holds, at
+ * n_knots knots equally spaced in sqrt(y) (sqrt(y_i) = i / (n_knots - 1);
+ * y = 0 is the Gaussian limit Phi^-1, y = 1 the central chi-squared), two
+ * dyadic piecewise polynomials of `degree` (1 or 3): one on U in (0, 1/2] in
+ * t = U and one on U in (1/2, 1) in t = 1 - U, each with n_intervals
+ * intervals [2^-(k+1), 2^-k), k = 1..n_intervals-1, and the singular
+ * (0, 2^-n_intervals), fitted in L2 in s = t 2^(k+1).  Between knots P~ is
+ * interpolated linearly in sqrt(y).  The paper's Table 6 uses 16 knots and
+ * 15 intervals per half (the 16-entry layout of the normal tables).
+ * Coefficient layout (FP64, host): [knot][half (0 lower, 1 upper)]
+ * [interval k-1][degree+1], c_0 first.  The device copy is FP32.
+ * Limits: nu in (0, 1e4], n_knots 2..64, n_intervals 2..30.  Building takes
+ * 2 * n_knots * ~900 exact FP64 inversions on host threads (~0.1-1 s).
+ * Errors: EINVAL, ENOMEM, EHIP. */
+aicdf_status aicdf_chi2_table_create(double nu, uint32_t degree, uint32_t n_knots,
+                                     uint32_t n_intervals, aicdf_chi2_table** out);
+/* FP64 coefficients into host_out (cap doubles); *n_written (may be NULL)
+ * receives the count; host_out == NULL only queries the count. */
+aicdf_status aicdf_chi2_table_coeffs(const aicdf_chi2_table* t, double* host_out, size_t cap,
+                                     size_t* n_written);
+void aicdf_chi2_table_destroy(aicdf_chi2_table* t);
+/* The same FP64 coefficients built on the host only (no device needed). */
+aicdf_status aicdf_chi2_host_coeffs(double nu, uint32_t degree, uint32_t n_knots,
+                                    uint32_t n_intervals, double* host_out, size_t cap);
+
+/* x[i] = C~_nu^-1(u[i]; lambda[i]) in FP32 (u, lambda, x: device arrays of n
+ * floats; x may not overlap an input).  lambda < 0 or NaN gives NaN; u
+ * outside [0, 1] gives finite or NaN values without error; the formula
+ * value is returned without clamping at 0.  Enqueues on `stream`.
+ * Errors: EINVAL, EALIAS, EHIP. */
+aicdf_status approx_ncx2_icdf(const aicdf_chi2_table* t, size_t n, const float* u,
+                              const float* lambda, float* x, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Learned surrogate for the CIR transition (MLP on BF16 MFMA)               */

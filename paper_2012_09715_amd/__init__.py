@@ -147,12 +147,27 @@ def mlmc_level_gbm(params, level, n_paths, kind, table=None, seed=0, path_offset
 
 def mlmc_level_cir(params, level, n_paths, kind, surrogate=None, seed=0, path_offset=0, path_out=None,
                    stream=None):
-    p = CirParams(params["v0"], params["kappa"], params["theta"], params["xi"], params["T"],
-                  int(params.get("functional", 0)), 0)
+    p = _cir_params(params)
     out = LevelSums()
     po = _dev(path_out, "path_out") if path_out is not None else None
     check(lib.mlmc_level_cir(C.byref(p), level, n_paths, kind, surrogate.handle if surrogate is not None else None,
                              seed, path_offset, C.byref(out), po, _stream(stream)))
+    return _sums_dict(out)
+
+
+def _cir_params(params):
+    return CirParams(params["v0"], params["kappa"], params["theta"], params["xi"], params["T"],
+                     int(params.get("functional", 0)), 0)
+
+
+def mlmc_level_cir_table(params, level, n_paths, kind, table=None, seed=0, path_offset=0, path_out=None,
+                         stream=None):
+    """mlmc_level_cir with the piecewise-polynomial chi-squared table (Chi2Table) as the approximation."""
+    p = _cir_params(params)
+    out = LevelSums()
+    po = _dev(path_out, "path_out") if path_out is not None else None
+    check(lib.mlmc_level_cir_table(C.byref(p), level, n_paths, kind, table.handle if table is not None else None,
+                                   seed, path_offset, C.byref(out), po, _stream(stream)))
     return _sums_dict(out)
 
 
@@ -170,6 +185,62 @@ def ncx2_icdf_exact(nu, u, lam, x=None, stream=None):
     if x is None:
         x = torch.empty_like(u)
     check(lib.ncx2_icdf_exact(nu, u.numel(), _dev(u, "u"), _dev(lam, "lambda"), _dev(x, "x"), _stream(stream)))
+    return x
+
+
+class Chi2Table:
+    """Piecewise-polynomial approximation of the non-central chi-squared
+    inverse CDF at a fixed nu (library-owned handle)."""
+
+    def __init__(self, handle, nu, degree, n_knots, n_intervals):
+        self._h = handle
+        self.nu, self.degree, self.n_knots, self.n_intervals = nu, degree, n_knots, n_intervals
+
+    @property
+    def handle(self):
+        return self._h
+
+    @classmethod
+    def create(cls, nu, degree=1, n_knots=16, n_intervals=15):
+        h = C.c_void_p()
+        check(lib.aicdf_chi2_table_create(nu, degree, n_knots, n_intervals, C.byref(h)))
+        return cls(h, nu, degree, n_knots, n_intervals)
+
+    def coeffs(self):
+        """FP64 coefficients, shape (n_knots, 2, n_intervals, degree + 1)."""
+        n = C.c_size_t()
+        check(lib.aicdf_chi2_table_coeffs(self._h, None, 0, C.byref(n)))
+        buf = (C.c_double * n.value)()
+        check(lib.aicdf_chi2_table_coeffs(self._h, buf, n.value, None))
+        return torch.tensor(list(buf), dtype=torch.float64).reshape(self.n_knots, 2, self.n_intervals,
+                                                                    self.degree + 1)
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h:
+            lib.aicdf_chi2_table_destroy(h)
+
+
+def chi2_host_coeffs(nu, degree=1, n_knots=16, n_intervals=15):
+    """The FP64 coefficients built on the host only (no device)."""
+    n = n_knots * 2 * n_intervals * (degree + 1)
+    buf = (C.c_double * n)()
+    check(lib.aicdf_chi2_host_coeffs(nu, degree, n_knots, n_intervals, buf, n))
+    return torch.tensor(list(buf), dtype=torch.float64).reshape(n_knots, 2, n_intervals, degree + 1)
+
+
+def approx_ncx2_icdf(table, u, lam, x=None, stream=None):
+    """x~ = C~^-1(u; lambda) in FP32 (u, lambda: float32 device tensors)."""
+    if u.dtype != torch.float32 or lam.dtype != torch.float32:
+        raise AicdfError(-2, "u and lambda must be float32")
+    if u.numel() != lam.numel():
+        raise AicdfError(-1, "u and lambda must have the same number of elements")
+    if x is None:
+        x = torch.empty_like(u)
+    elif x.dtype != torch.float32 or x.numel() != u.numel():
+        raise AicdfError(-2, "x must be float32 with as many elements as u")
+    check(lib.approx_ncx2_icdf(table.handle, u.numel(), _dev(u, "u"), _dev(lam, "lambda"), _dev(x, "x"),
+                               _stream(stream)))
     return x
 
 

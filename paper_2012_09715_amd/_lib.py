@@ -56,6 +56,13 @@ _PROTOS = {
     "mlmc_allocate": (status, [u32, dbl, dptr, dptr, dptr, dptr, dptr, dptr, dptr, dptr, dptr,
                                dptr, dptr]),
     "ncx2_icdf_exact": (status, [dbl, sz, vp, vp, vp, vp]),
+    "aicdf_chi2_table_create": (status, [dbl, u32, u32, u32, C.POINTER(vp)]),
+    "aicdf_chi2_table_coeffs": (status, [vp, dptr, sz, C.POINTER(sz)]),
+    "aicdf_chi2_table_destroy": (None, [vp]),
+    "aicdf_chi2_host_coeffs": (status, [dbl, u32, u32, u32, dptr, sz]),
+    "approx_ncx2_icdf": (status, [vp, sz, vp, vp, vp, vp]),
+    "mlmc_level_cir_table": (status, [C.POINTER(CirParams), u32, u64, i32, vp, u64, u64,
+                                      C.POINTER(LevelSums), vp, vp]),
     "aicdf_surrogate_create": (status, [dbl, dbl, dbl, u64, C.POINTER(vp)]),
     "aicdf_surrogate_destroy": (None, [vp]),
     "aicdf_surrogate_set_params": (status, [vp, fptr, sz]),

@@ -1,17 +1,24 @@
 // Fused MLMC level of the CIR process with exact-in-law non-central
 // chi-squared transitions (Section 5.2).  One path per thread; per step n:
 //   lambda_n = v_n e^(-kappa delta) / c,  v_(n+1) = c C_nu^-1(U_n; lambda_n),
-// with C_nu^-1 the exact FP64 inverse (EXACT), the surrogate network
-// (APPROX: P~ = MLP(D(U), g(log lambda)), x = lambda + nu + 2 sqrt(lambda+nu)
-// P~, clamped at 0), or both on one draw (CORRECTION).  The surrogate call is
-// a wave-wide matrix-core routine, so all 64 lanes step together; a lane whose
-// log lambda lies outside the trained range takes the exact inverse on the
-// same u24 instead (counted).  The coarse path of level l is the fine path
+// with C_nu^-1 the exact FP64 inverse (EXACT), an FP32 approximation
+// (APPROX), or both on one draw (CORRECTION).  Two approximations:
+//   APX_SURROGATE  P~ = MLP(D(U), g(log lambda)), x = lambda + nu +
+//                  2 sqrt(lambda+nu) P~, clamped at 0.  The network call is a
+//                  wave-wide matrix-core routine, so all 64 lanes step
+//                  together; a lane whose log lambda lies outside the trained
+//                  range takes the exact inverse on the same u24 instead
+//                  (counted).
+//   APX_POLY1/3    Section 5.1's piecewise-polynomial approximation (two
+//                  dyadic half tables per knot, linear interpolation in
+//                  sqrt(y)), clamped at 0; the table is staged in LDS.
+// The coarse path of level l is the fine path
 // observed at even steps (exact in law), so only the functional differs:
 //   FUNC 0  P = v_T
 //   FUNC 1  P = trapezoidal time average on the level's grid.
 #include <cmath>
 
+#include "chi2_device.hpp"
 #include "mlmc_common.hpp"
 #include "mlp_device.hpp"
 #include "ncx2_device.hpp"
@@ -20,12 +27,17 @@ using namespace aicdf;
 
 namespace {
 
+constexpr int APX_SURROGATE = 0, APX_POLY1 = 1, APX_POLY3 = 3;
+constexpr uint32_t kMaxLdsRows = 2048;  // 32 KiB of chi-squared table rows
+
 struct CirArgs {
   double nu, c, decay, v0;
   float nuf, cf, decayf, v0f, lo, hi, inv_span2;
   uint32_t level, nsteps;
   uint64_t n_paths, path_offset;
   uint32_t k0, k1, tag;
+  Chi2Geom geo;         // APX_POLY*: table geometry
+  uint32_t table_rows;  // APX_POLY*: rows staged in LDS
 };
 
 __device__ __forceinline__ float dyadic_w16(float u, const f32x4* __restrict__ tab) {
@@ -58,7 +70,7 @@ struct FuncAcc {
   }
 };
 
-template <int KIND, int FUNC>
+template <int KIND, int FUNC, int APX>
 __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const float* __restrict__ params,
                                                                const uint16_t* __restrict__ w2b,
                                                                const f32x4* __restrict__ wtab,
@@ -66,15 +78,22 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
                                                                double* __restrict__ path_out,
                                                                unsigned long long* __restrict__ fallbacks) {
   constexpr bool kExact = KIND != AICDF_KIND_APPROX;
-  constexpr bool kSurr = KIND != AICDF_KIND_EXACT;
+  constexpr bool kApx = KIND != AICDF_KIND_EXACT;
+  constexpr bool kSurr = kApx && APX == APX_SURROGATE;
+  constexpr bool kPoly = kApx && APX != APX_SURROGATE;
   __shared__ MlpLds L;
   __shared__ f32x4 tab[16];
+  extern __shared__ f32x4 ctab[];  // APX_POLY*: the chi-squared table (dynamic LDS)
   bf16x8 A[2][4];
   if (kSurr) {
     mlp_stage_params(L, params, threadIdx.x, kLevelBlock);
     if (threadIdx.x < 16) tab[threadIdx.x] = wtab[threadIdx.x];
     __syncthreads();
     mlp_load_w2(w2b, A);
+  }
+  if (kPoly) {
+    for (uint32_t r = threadIdx.x; r < a.table_rows; r += kLevelBlock) ctab[r] = wtab[r];
+    __syncthreads();
   }
   LevelAcc acc;
   unsigned long long fb = 0;
@@ -127,6 +146,11 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
         vs = a.cf * x;
         if (FUNC == 1) fs.node(n + 1, N, double(vs));
       }
+      if (kPoly) {
+        const float lam = vs * a.decayf / a.cf;
+        vs = a.cf * fmaxf(chi2_approx_x<APX>(u24, lam, ctab, a.geo), 0.0f);
+        if (FUNC == 1) fs.node(n + 1, N, double(vs));
+      }
     }
     double Y = 0.0, Pf = 0.0, Pc = 0.0;
     if (KIND == AICDF_KIND_APPROX) {
@@ -163,20 +187,31 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
   }
 }
 
-template <int KIND>
-void launch_func(int func, const CirArgs& a, unsigned grid, hipStream_t s, const float* p, const uint16_t* w2,
-                 const f32x4* wt, double* part, double* po, unsigned long long* fb) {
+template <int KIND, int APX>
+void launch_func(int func, const CirArgs& a, unsigned grid, size_t lds, hipStream_t s, const float* p,
+                 const uint16_t* w2, const f32x4* wt, double* part, double* po, unsigned long long* fb) {
   if (func == 0)
-    hipLaunchKernelGGL((cir_level_kernel<KIND, 0>), dim3(grid), dim3(kLevelBlock), 0, s, a, p, w2, wt, part, po, fb);
+    hipLaunchKernelGGL((cir_level_kernel<KIND, 0, APX>), dim3(grid), dim3(kLevelBlock), lds, s, a, p, w2, wt, part,
+                       po, fb);
   else
-    hipLaunchKernelGGL((cir_level_kernel<KIND, 1>), dim3(grid), dim3(kLevelBlock), 0, s, a, p, w2, wt, part, po, fb);
+    hipLaunchKernelGGL((cir_level_kernel<KIND, 1, APX>), dim3(grid), dim3(kLevelBlock), lds, s, a, p, w2, wt, part,
+                       po, fb);
 }
 
-}  // namespace
+template <int APX>
+void launch_kind(int kind, int func, const CirArgs& a, unsigned grid, size_t lds, hipStream_t s, const float* p,
+                 const uint16_t* w2, const f32x4* wt, double* part, double* po, unsigned long long* fb) {
+  if (kind == AICDF_KIND_EXACT)
+    launch_func<AICDF_KIND_EXACT, APX_SURROGATE>(func, a, grid, 0, s, p, w2, wt, part, po, fb);
+  else if (kind == AICDF_KIND_APPROX)
+    launch_func<AICDF_KIND_APPROX, APX>(func, a, grid, lds, s, p, w2, wt, part, po, fb);
+  else
+    launch_func<AICDF_KIND_CORRECTION, APX>(func, a, grid, lds, s, p, w2, wt, part, po, fb);
+}
 
-extern "C" aicdf_status mlmc_level_cir(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths, int32_t kind,
-                                       const aicdf_surrogate* sur, uint64_t seed, uint64_t path_offset,
-                                       aicdf_level_sums* out, double* path_out, void* stream) {
+// Checks shared by both approximations; fills the common arguments.
+aicdf_status cir_setup(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths, int32_t kind, uint64_t seed,
+                       uint64_t path_offset, aicdf_level_sums* out, CirArgs& a, unsigned& grid) {
   if (!prm || !out) return fail(AICDF_EINVAL, "params and out must be non-NULL");
   if (level > 12) return fail(AICDF_ERANGE, "level %u > 12", level);
   if (kind < 0 || kind > 2) return fail(AICDF_EINVAL, "kind must be 0, 1 or 2");
@@ -184,28 +219,12 @@ extern "C" aicdf_status mlmc_level_cir(const aicdf_cir_params* prm, uint32_t lev
     return fail(AICDF_EINVAL, "functional must be 0 or 1 and reserved 0");
   if (!(prm->kappa > 0.0) || !(prm->theta > 0.0) || !(prm->xi > 0.0) || !(prm->T > 0.0) || !(prm->v0 >= 0.0))
     return fail(AICDF_EINVAL, "need kappa, theta, xi, T > 0 and v0 >= 0");
-  if (kind != AICDF_KIND_EXACT && !sur) return fail(AICDF_EINVAL, "the approximate kinds need a surrogate");
-  if (n_paths == 0) {
-    *out = aicdf_level_sums{};
-    return ok();
-  }
   if (n_paths > (uint64_t(1) << 40)) return fail(AICDF_ERANGE, "n_paths > 2^40");
   if (path_offset + n_paths < path_offset) return fail(AICDF_ERANGE, "path_offset + n_paths overflows");
   const double nu = 4.0 * prm->kappa * prm->theta / (prm->xi * prm->xi);
-  double snu = nu, lo = 0.0, hi = 0.0;
-  int sdev = 0, dev = 0;
-  AICDF_HIP(hipGetDevice(&dev));
-  if (sur) {
-    surrogate_range(sur, &snu, &lo, &hi, &sdev);
-    if (kind != AICDF_KIND_EXACT) {
-      if (sdev != dev) return fail(AICDF_EINVAL, "surrogate lives on device %d, current device is %d", sdev, dev);
-      if (std::fabs(snu - nu) > 1e-12 * nu)
-        return fail(AICDF_EINVAL, "surrogate was built for nu = %.17g, the process has nu = %.17g", snu, nu);
-    }
-  }
   const uint32_t N = 1u << level;
   const double dt = prm->T / N;
-  CirArgs a{};
+  a = CirArgs{};
   a.nu = nu;
   a.decay = std::exp(-prm->kappa * dt);
   a.c = prm->xi * prm->xi * (1.0 - a.decay) / (4.0 * prm->kappa);
@@ -214,9 +233,6 @@ extern "C" aicdf_status mlmc_level_cir(const aicdf_cir_params* prm, uint32_t lev
   a.cf = float(a.c);
   a.decayf = float(a.decay);
   a.v0f = float(prm->v0);
-  a.lo = float(lo);
-  a.hi = float(hi);
-  a.inv_span2 = sur ? float(2.0 / (hi - lo)) : 0.0f;
   a.level = level;
   a.nsteps = N;
   a.n_paths = n_paths;
@@ -225,11 +241,42 @@ extern "C" aicdf_status mlmc_level_cir(const aicdf_cir_params* prm, uint32_t lev
   a.k1 = uint32_t(seed >> 32);
   a.tag = level | (uint32_t(4 + kind) << 8);
   const uint64_t need = (n_paths + kLevelBlock - 1) / kLevelBlock;
-  const unsigned grid = unsigned(need < uint64_t(kMaxLevelBlocks) ? need : kMaxLevelBlocks);
+  grid = unsigned(need < uint64_t(kMaxLevelBlocks) ? need : kMaxLevelBlocks);
+  return AICDF_OK;
+}
+
+}  // namespace
+
+extern "C" aicdf_status mlmc_level_cir(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths, int32_t kind,
+                                       const aicdf_surrogate* sur, uint64_t seed, uint64_t path_offset,
+                                       aicdf_level_sums* out, double* path_out, void* stream) {
+  CirArgs a;
+  unsigned grid = 0;
+  aicdf_status st = cir_setup(prm, level, n_paths, kind, seed, path_offset, out, a, grid);
+  if (st != AICDF_OK) return st;
+  if (kind != AICDF_KIND_EXACT && !sur) return fail(AICDF_EINVAL, "the approximate kinds need a surrogate");
+  if (n_paths == 0) {
+    *out = aicdf_level_sums{};
+    return ok();
+  }
+  double snu = a.nu, lo = 0.0, hi = 0.0;
+  int sdev = 0, dev = 0;
+  AICDF_HIP(hipGetDevice(&dev));
+  if (sur) {
+    surrogate_range(sur, &snu, &lo, &hi, &sdev);
+    if (kind != AICDF_KIND_EXACT) {
+      if (sdev != dev) return fail(AICDF_EINVAL, "surrogate lives on device %d, current device is %d", sdev, dev);
+      if (std::fabs(snu - a.nu) > 1e-12 * a.nu)
+        return fail(AICDF_EINVAL, "surrogate was built for nu = %.17g, the process has nu = %.17g", snu, a.nu);
+    }
+  }
+  a.lo = float(lo);
+  a.hi = float(hi);
+  a.inv_span2 = sur ? float(2.0 / (hi - lo)) : 0.0f;
 
   std::lock_guard<std::mutex> lock(level_mutex());
   Workspace* ws = nullptr;
-  aicdf_status st = get_workspace(&ws);
+  st = get_workspace(&ws);
   if (st != AICDF_OK) return st;
   auto s = static_cast<hipStream_t>(stream);
   const float* p = sur ? surrogate_params(sur) : nullptr;
@@ -237,12 +284,55 @@ extern "C" aicdf_status mlmc_level_cir(const aicdf_cir_params* prm, uint32_t lev
   const f32x4* wt = sur ? reinterpret_cast<const f32x4*>(surrogate_wtab(sur)) : nullptr;
   AICDF_HIP(hipMemsetAsync(ws->counter, 0, sizeof(unsigned long long), s));
   AICDF_HIP(hipEventRecord(ws->ev0, s));
-  if (kind == AICDF_KIND_EXACT)
-    launch_func<AICDF_KIND_EXACT>(prm->functional, a, grid, s, p, w2, wt, ws->partials, path_out, ws->counter);
-  else if (kind == AICDF_KIND_APPROX)
-    launch_func<AICDF_KIND_APPROX>(prm->functional, a, grid, s, p, w2, wt, ws->partials, path_out, ws->counter);
+  launch_kind<APX_SURROGATE>(kind, prm->functional, a, grid, 0, s, p, w2, wt, ws->partials, path_out, ws->counter);
+  AICDF_HIP(hipGetLastError());
+  return finish_level(ws, grid, s, double(n_paths), out);
+}
+
+extern "C" aicdf_status mlmc_level_cir_table(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths,
+                                             int32_t kind, const aicdf_chi2_table* tab, uint64_t seed,
+                                             uint64_t path_offset, aicdf_level_sums* out, double* path_out,
+                                             void* stream) {
+  CirArgs a;
+  unsigned grid = 0;
+  aicdf_status st = cir_setup(prm, level, n_paths, kind, seed, path_offset, out, a, grid);
+  if (st != AICDF_OK) return st;
+  if (kind != AICDF_KIND_EXACT && !tab) return fail(AICDF_EINVAL, "the approximate kinds need a table");
+  if (n_paths == 0) {
+    *out = aicdf_level_sums{};
+    return ok();
+  }
+  int dev = 0;
+  AICDF_HIP(hipGetDevice(&dev));
+  Chi2Info ti{};
+  size_t lds = 0;
+  if (tab && kind != AICDF_KIND_EXACT) {
+    ti = chi2_info(tab);
+    if (ti.device != dev) return fail(AICDF_EINVAL, "table lives on device %d, current device is %d", ti.device, dev);
+    if (std::fabs(ti.nu - a.nu) > 1e-12 * a.nu)
+      return fail(AICDF_EINVAL, "table was built for nu = %.17g, the process has nu = %.17g", ti.nu, a.nu);
+    a.geo = Chi2Geom{float(ti.nu), float(std::sqrt(ti.nu)), float(ti.n_knots - 1), ti.n_knots - 2, ti.n_intervals};
+    a.table_rows = ti.n_knots * 2 * ti.n_intervals;
+    if (a.table_rows > kMaxLdsRows)
+      return fail(AICDF_EINVAL, "table has %u rows; the CIR level stages at most %u in LDS", a.table_rows,
+                  kMaxLdsRows);
+    lds = size_t(a.table_rows) * sizeof(f32x4);
+  }
+
+  std::lock_guard<std::mutex> lock(level_mutex());
+  Workspace* ws = nullptr;
+  st = get_workspace(&ws);
+  if (st != AICDF_OK) return st;
+  auto s = static_cast<hipStream_t>(stream);
+  const auto* wt = static_cast<const f32x4*>(ti.dev_rows);
+  AICDF_HIP(hipMemsetAsync(ws->counter, 0, sizeof(unsigned long long), s));
+  AICDF_HIP(hipEventRecord(ws->ev0, s));
+  if (kind == AICDF_KIND_EXACT || ti.degree == 1)
+    launch_kind<APX_POLY1>(kind, prm->functional, a, grid, lds, s, nullptr, nullptr, wt, ws->partials, path_out,
+                           ws->counter);
   else
-    launch_func<AICDF_KIND_CORRECTION>(prm->functional, a, grid, s, p, w2, wt, ws->partials, path_out, ws->counter);
+    launch_kind<APX_POLY3>(kind, prm->functional, a, grid, lds, s, nullptr, nullptr, wt, ws->partials, path_out,
+                           ws->counter);
   AICDF_HIP(hipGetLastError());
   return finish_level(ws, grid, s, double(n_paths), out);
 }

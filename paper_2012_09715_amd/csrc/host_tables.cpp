@@ -67,7 +67,7 @@ double host_Phi_inv(double u) {
 }
 
 // n-point Gauss-Legendre nodes/weights on [-1, 1] by Newton on P_n.
-static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
   x.assign(n, 0.0);
   w.assign(n, 0.0);
   for (int i = 0; i < (n + 1) / 2; ++i) {
@@ -139,7 +139,7 @@ std::vector<double> build_const_table(uint32_t N, int construction) {
 }
 
 // Small dense solve with partial pivoting (at most 4 x 4).
-static void solve_small(int n, double* A, double* b) {
+void solve_small(int n, double* A, double* b) {
   for (int c = 0; c < n; ++c) {
     int p = c;
     for (int r = c + 1; r < n; ++r)

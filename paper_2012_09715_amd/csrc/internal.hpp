@@ -53,12 +53,24 @@ double host_Phi_inv(double u);
 std::vector<double> build_const_table(uint32_t n, int construction);
 std::vector<double> build_dyadic_table(uint32_t n_entries, uint32_t degree);
 double round_to_dtype(double x, aicdf_dtype t);
+// n-point Gauss-Legendre rule on [-1, 1]; small dense solve (n <= 4, A and b overwritten, b := A^-1 b).
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+void solve_small(int n, double* A, double* b);
 
 // Surrogate internals used by the CIR level (surrogate.hip).
 const float* surrogate_params(const aicdf_surrogate* s);
 const uint16_t* surrogate_w2b(const aicdf_surrogate* s);
 const float* surrogate_wtab(const aicdf_surrogate* s);
 void surrogate_range(const aicdf_surrogate* s, double* nu, double* lo, double* hi, int* dev);
+
+// Chi-squared table internals used by the CIR level (chi2_table.hip).
+struct Chi2Info {
+  double nu;
+  uint32_t degree, n_knots, n_intervals;
+  int device;
+  const void* dev_rows;  // n_knots * 2 * n_intervals FP32 rows of four
+};
+Chi2Info chi2_info(const aicdf_chi2_table* t);
 
 }  // namespace aicdf
 

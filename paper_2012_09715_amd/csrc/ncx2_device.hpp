@@ -189,13 +189,13 @@ __host__ __device__ inline Ncx2Val ncx2_sf(double x, double nu, double lam) {
 }
 
 // Quick initial value: Patnaik's scaled central chi-squared with the
-// Wilson-Hilferty cube-root normal approximation; z from A&S 26.2.23.
-__host__ __device__ inline double ncx2_guess(double u, double nu, double lam) {
-  const double q = u < 0.5 ? u : 1.0 - u;
-  const double tt = sqrt(-2.0 * log(q));
+// Wilson-Hilferty cube-root normal approximation; z from A&S 26.2.23 at the
+// tail probability t (lower tail, or upper tail when `upper`).
+__host__ __device__ inline double ncx2_guess(double t, bool upper, double nu, double lam) {
+  const double tt = sqrt(-2.0 * log(t));
   double z = tt - (2.515517 + tt * (0.802853 + tt * 0.010328)) /
                       (1.0 + tt * (1.432788 + tt * (0.189269 + tt * 0.001308)));
-  z = u < 0.5 ? -z : z;
+  z = upper ? z : -z;
   const double s = nu + lam, s2 = nu + 2.0 * lam;
   const double rho = s2 / s, k = s * s / s2;
   const double c = 2.0 / (9.0 * k);
@@ -210,26 +210,28 @@ __host__ __device__ inline double ncx2_guess(double u, double nu, double lam) {
 //   upper: the Chernoff bound 1 - C(x) <= 2^(nu/2) e^(lambda/2) e^(-x/4)
 //          (moment generating function at s = 1/4), so
 //          x_hi = 2 nu log 2 + 2 lambda - 4 log(1-u) has 1 - C(x_hi) <= 1-u.
-// u <= 1/2: g(w) = log C(e^w) - log u in w = log x (the lower tail of C is
-//           close to a power of x, so g is close to linear in w);
-// u > 1/2:  g(x) = log(1-u) - log(1 - C(x)) in x (close to linear in x in
-//           the upper tail).
+// The target is given as a tail probability t in (0, 1/2]: u = t (lower
+// tail, upper = false) or 1 - u = t (upper tail, upper = true), so that
+// upper-tail targets below the FP64 spacing near 1 keep full precision.
+// lower: g(w) = log C(e^w) - log t in w = log x (the lower tail of C is
+//        close to a power of x, so g is close to linear in w);
+// upper: g(x) = log t - log(1 - C(x)) in x (close to linear in x in the
+//        upper tail).
 // Steps that leave the bracket are replaced by bisection (geometric while the
 // bracket spans more than a factor of two).  `iters` receives the number of
 // CDF evaluations.
-__host__ __device__ inline double ncx2_icdf(double u, double nu, double lam, int* iters = nullptr) {
-  if (!(u > 0.0)) return u == 0.0 ? 0.0 : __builtin_nan("");
-  if (!(u < 1.0)) return u == 1.0 ? __builtin_inf() : __builtin_nan("");
-  const bool upper = u > 0.5;
+__host__ __device__ inline double ncx2_icdf_tail(double t, bool upper, double nu, double lam,
+                                                 int* iters = nullptr) {
   const double a = 0.5 * nu;
-  double xlo = 2.0 * exp((log(u) + lgamma(a + 1.0)) / a);
-  double xhi = 2.0 * nu * 0.69314718055994531 + 2.0 * lam - 4.0 * log1p(-u);
+  const double lu = upper ? log1p(-t) : log(t);    // log u
+  const double lq = upper ? log(t) : log1p(-t);    // log (1 - u)
+  double xlo = 2.0 * exp((lu + lgamma(a + 1.0)) / a);
+  double xhi = 2.0 * nu * 0.69314718055994531 + 2.0 * lam - 4.0 * lq;
   if (!(xhi > xlo * 1.001)) xhi = xlo * 1.001 + 1e-300;
-  double x = ncx2_guess(u, nu, lam);
+  double x = ncx2_guess(t, upper, nu, lam);
   if (!(x > xlo && x < xhi)) x = sqrt(xlo) * sqrt(xhi);
   int it = 0;
   if (!upper) {
-    const double lu = log(u);
     double wlo = log(xlo), whi = log(xhi), w = log(x);
     for (; it < 100; ++it) {
       const double xx = exp(w);
@@ -250,7 +252,6 @@ __host__ __device__ inline double ncx2_icdf(double u, double nu, double lam, int
     }
     x = exp(w);
   } else {
-    const double lq = log1p(-u);
     for (; it < 100; ++it) {
       const Ncx2Val v = ncx2_sf(x, nu, lam);
       const double g = v.sf > 0.0 ? lq - log(v.sf) : 1e300;
@@ -269,6 +270,14 @@ __host__ __device__ inline double ncx2_icdf(double u, double nu, double lam, int
   }
   if (iters) *iters = it + 1;
   return x;
+}
+
+// C_nu^-1(u; lambda) for u in [0, 1]: 0 at u = 0, +inf at u = 1, NaN outside.
+__host__ __device__ inline double ncx2_icdf(double u, double nu, double lam, int* iters = nullptr) {
+  if (!(u > 0.0)) return u == 0.0 ? 0.0 : __builtin_nan("");
+  if (!(u < 1.0)) return u == 1.0 ? __builtin_inf() : __builtin_nan("");
+  const bool upper = u > 0.5;
+  return ncx2_icdf_tail(upper ? 1.0 - u : u, upper, nu, lam, iters);
 }
 
 }  // namespace aicdf

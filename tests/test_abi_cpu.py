@@ -106,3 +106,29 @@ def test_mlmc_allocate_table3_row():
     assert round(r["T_hat"] / r["T_tilde"], 2) == 6.70
     with pytest.raises(A.AicdfError, match="EINVAL"):
         A.mlmc_allocate(1e-3, [1.0], [0.0], [1.0], [1.0], [1.0], [1.0])
+
+
+@pytest.mark.parametrize("nu,degree", [(1.0, 1), (0.8888888888888888, 1), (5.0, 3), (100.0, 3), (0.3, 3)])
+def test_host_chi2_table_matches_oracle(nu, degree):
+    # The library's chi-squared tables (its own quadrature and exact inverse)
+    # against the oracle's (Section 5.1): the cubic normal equations amplify
+    # quadrature differences to ~1e-9, far below FP32 resolution.
+    from oracle import chi2table
+    got = A.chi2_host_coeffs(nu, degree).numpy()
+    ref = chi2table.build(nu, degree)
+    assert got.shape == ref.shape == (16, 2, 15, degree + 1)
+    tol = 1e-11 if degree == 1 else 5e-9
+    assert np.allclose(got, ref, rtol=0, atol=tol)
+
+
+def test_host_chi2_table_shapes_and_errors():
+    from oracle import chi2table
+    got = A.chi2_host_coeffs(2.0, 1, n_knots=5, n_intervals=7).numpy()
+    ref = chi2table.build(2.0, 1, n_knots=5, n_int=7)
+    assert np.allclose(got, ref, rtol=0, atol=1e-11)
+    buf = (C.c_double * 4)()
+    for args in ((0.0, 1, 16, 15), (1.0, 2, 16, 15), (1.0, 1, 1, 15), (1.0, 1, 65, 15), (1.0, 1, 16, 1),
+                 (1.0, 1, 16, 31), (float("nan"), 1, 16, 15)):
+        assert lib.aicdf_chi2_host_coeffs(*args, buf, 4) == -1, args
+    assert lib.aicdf_chi2_host_coeffs(1.0, 1, 2, 2, buf, 4) == -1  # needs 16 doubles
+    assert lib.aicdf_chi2_host_coeffs(1.0, 1, 2, 2, None, 16) == -1
