@@ -101,6 +101,47 @@ def exact_error_on_grid(A, torch, tab, out_dtype, kind):
     return float(torch.sqrt(torch.mean(d * d)).item()), float(d.abs().max().item())
 
 
+NU_CIR = 4 * 0.5 * 0.04 / 0.3 ** 2
+
+
+def chi2_sweep(A, torch, u, stream):
+    """Section 5.1's chi-squared approximation: (u, lambda) -> x~ on 2^28
+    device-resident pairs (u from the benchmark stream, log lambda uniform on
+    [-8, 10], the range the CIR levels visit), 12 algorithmic bytes per
+    sample; the exact FP64 inverse on 2^20 of the same pairs for the cost
+    ratio; the L2 error against the exact inverse over the midpoints of 2^20
+    cells of (0, 1) at lambda in {1, 10, 100} (Table 6 measure)."""
+    out = []
+    n = 1 << 28
+    g = torch.Generator(device="cuda")
+    g.manual_seed(SEED)
+    lam = torch.exp(torch.rand(n, device="cuda", generator=g) * 18.0 - 8.0)
+    uu = u[:n]
+    x = torch.empty(n, dtype=torch.float32, device="cuda")
+    ne = 1 << 20
+    ue, le = uu[:ne].double(), lam[:ne].double()
+    ms_ex = time_kernel(lambda: A.ncx2_icdf_exact(NU_CIR, ue, le), 2, stream)
+    m = 1 << 20
+    ug = ((torch.arange(m, device="cuda", dtype=torch.float64) + 0.5) / m).float()
+    for deg in (1, 3):
+        tab = A.Chi2Table.create(NU_CIR, deg)
+        ms = time_kernel(lambda: A.approx_ncx2_icdf(tab, uu, lam, x=x), 5, stream)
+        rm = {}
+        for lv in (1.0, 10.0, 100.0):
+            lg = torch.full((m,), lv, dtype=torch.float32, device="cuda")
+            d = A.approx_ncx2_icdf(tab, ug, lg).double() - A.ncx2_icdf_exact(NU_CIR, ug.double(), lg.double())
+            rm[str(lv)] = float(torch.sqrt(torch.mean(d * d)).item())
+        rate = n / (ms * 1e-3)
+        out.append({"table": f"chi2_poly{deg}", "nu": NU_CIR, "knots": 16, "intervals_per_half": 15,
+                    "samples_per_s": rate, "GBs": 12 * rate / 1e9, "hbm_frac": 12 * rate / 1e9 / HBM_PEAK_GBS,
+                    "ms": ms, "rmse_vs_exact_by_lambda": rm,
+                    "exact_fp64_samples_per_s": ne / (ms_ex * 1e-3),
+                    "exact_over_approx_cost": rate / (ne / (ms_ex * 1e-3))})
+        log(f"sweep {out[-1]}")
+    del lam, x
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -206,6 +247,7 @@ def main():
     ms = time_kernel(lambda: A.exact_icdf(u, z=z), 3, stream)
     sweep.append({"table": "exact_fp64", "out": "f32", "samples_per_s": N_MAIN / (ms * 1e-3), "ms": ms,
                   "GBs": 8 * N_MAIN / (ms * 1e-3) / 1e9})
+    sweep += chi2_sweep(A, torch, u, stream)
     ms = time_kernel(lambda: A.uniform_fill(u, SEED, 3, 0), 3, stream)
     sweep.append({"table": "uniform_fill_f32", "samples_per_s": N_MAIN / (ms * 1e-3), "ms": ms,
                   "GBs": 4 * N_MAIN / (ms * 1e-3) / 1e9})

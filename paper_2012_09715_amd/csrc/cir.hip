@@ -12,6 +12,11 @@
 //   APX_POLY1/3    Section 5.1's piecewise-polynomial approximation (two
 //                  dyadic half tables per knot, linear interpolation in
 //                  sqrt(y)), clamped at 0; the table is staged in LDS.
+// Launch shape.  Calls with exact inversions and few paths (the high levels
+// of an MLMC allocation, where a level's time is the serial time of one
+// path) run one path per wavefront (lane 0), so that no path waits for the
+// Newton iterations and sweep branches of 63 others; every other call runs
+// one path per thread.
 // The coarse path of level l is the fine path
 // observed at even steps (exact in law), so only the functional differs:
 //   FUNC 0  P = v_T
@@ -38,7 +43,12 @@ struct CirArgs {
   uint32_t k0, k1, tag;
   Chi2Geom geo;         // APX_POLY*: table geometry
   uint32_t table_rows;  // APX_POLY*: rows staged in LDS
+  uint32_t sparse;      // 1: one path per wavefront (lane 0)
 };
+
+// Largest path count that runs one path per wavefront: every path then has a
+// SIMD slot of its own (256 CUs x 4 SIMDs, two or more waves each).
+constexpr uint64_t kSparseMaxPaths = 2048;
 
 __device__ __forceinline__ float dyadic_w16(float u, const f32x4* __restrict__ tab) {
   const bool p = u < 0.5f;
@@ -98,10 +108,14 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
   LevelAcc acc;
   unsigned long long fb = 0;
   const uint32_t N = a.nsteps;
-  for (uint64_t base = uint64_t(blockIdx.x) * kLevelBlock; base < a.n_paths;
-       base += uint64_t(gridDim.x) * kLevelBlock) {
-    const uint64_t i = base + threadIdx.x;
-    const bool act = i < a.n_paths;
+  const uint32_t per_block = a.sparse ? kLevelBlock / 64 : kLevelBlock;
+  const uint32_t slot = a.sparse ? threadIdx.x / 64 : threadIdx.x;
+  const bool lead = a.sparse ? (threadIdx.x % 64) == 0 : true;
+  for (uint64_t base = uint64_t(blockIdx.x) * per_block; base < a.n_paths;
+       base += uint64_t(gridDim.x) * per_block) {
+    const uint64_t i = base + slot;
+    const bool act = lead && i < a.n_paths;
+    const bool work = a.sparse ? act : true;  // lanes that run the exact inverse
     const uint64_t P = a.path_offset + i;
     const uint32_t plo = uint32_t(P), phi = uint32_t(P >> 32);
     double ve = a.v0;
@@ -124,7 +138,7 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
         u53 = u53_from_words(hi, lo);
         u24 = u24_from_word(hi);
       }
-      if (kExact) {
+      if (kExact && work) {
         const double lam = ve * a.decay / a.c;
         ve = a.c * ncx2_icdf(u53, a.nu, lam);
         if (FUNC == 1) fe.node(n + 1, N, ve);
@@ -140,7 +154,7 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
           const float s = lam + a.nuf;
           x = fmaxf(fmaf(2.0f * sqrtf(s), Pt, s), 0.0f);
         } else {
-          x = float(ncx2_icdf(double(u24), a.nu, double(lam)));
+          x = work ? float(ncx2_icdf(double(u24), a.nu, double(lam))) : 0.0f;
           fb += act ? 1 : 0;
         }
         vs = a.cf * x;
@@ -240,7 +254,9 @@ aicdf_status cir_setup(const aicdf_cir_params* prm, uint32_t level, uint64_t n_p
   a.k0 = uint32_t(seed);
   a.k1 = uint32_t(seed >> 32);
   a.tag = level | (uint32_t(4 + kind) << 8);
-  const uint64_t need = (n_paths + kLevelBlock - 1) / kLevelBlock;
+  a.sparse = (kind != AICDF_KIND_APPROX && n_paths <= kSparseMaxPaths) ? 1u : 0u;
+  const uint64_t per_block = a.sparse ? kLevelBlock / 64 : kLevelBlock;
+  const uint64_t need = (n_paths + per_block - 1) / per_block;
   grid = unsigned(need < uint64_t(kMaxLevelBlocks) ? need : kMaxLevelBlocks);
   return AICDF_OK;
 }

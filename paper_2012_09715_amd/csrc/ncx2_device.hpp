@@ -14,11 +14,15 @@
 // each using only additions of positive terms (the opposite directions
 // subtract and lose all relative accuracy in the far tails).  A sweep starts
 // beyond both the peak of c_j ((j+1)(a+j+1) = mu y) and the Poisson peak
-// (j = mu), 12 standard deviations plus 40 terms out, from P or Q given by the
-// power series (y < a+j+1) or the Lentz continued fraction, and stops once
-// the remaining head or tail is below 1e-17 of the sum.  The terms are carried
-// as products w_j P_j (or w_j Q_j) and c_j on a running scale (below), so that
-// no factor underflows or overflows on the way.
+// (j = mu), 9 standard deviations plus 16 terms out (the Poisson mass beyond
+// is below 1e-17 by the Chernoff bound), from P or Q given by the power
+// series (y < a+j+1) or the Lentz continued fraction, and stops once the
+// remaining head or tail is below 1e-17 of the sum.  The terms are carried as
+// products w_j P_j (or w_j Q_j) and c_j on a running scale (below), so that
+// no factor underflows or overflows on the way.  The sweeps divide at most
+// once per term (the downward one not at all), and both are kept out of line
+// on the device so that the Newton driver around them stays small in
+// registers.
 #pragma once
 
 #include "device_common.hpp"
@@ -67,8 +71,8 @@ __host__ __device__ inline void ncx2_sweep_range(double y, double a, double mu, 
   double js = 0.0;
   if (mu > 0.0) js = fmax(0.0, floor(0.5 * (sqrt(a * a + 4.0 * mu * y) - (a + 2.0)) + 0.5));
   const double lo = fmin(js, mu), hi = fmax(js, mu);
-  jb = fmax(0.0, floor(lo - 12.0 * sqrt(lo + 1.0) - 40.0));
-  je = ceil(hi + 12.0 * sqrt(hi + 1.0) + 40.0);
+  jb = fmax(0.0, floor(lo - 9.0 * sqrt(lo + 1.0) - 16.0));
+  je = ceil(hi + 9.0 * sqrt(hi + 1.0) + 16.0);
   if (mu == 0.0) jb = je = 0.0;
 }
 
@@ -86,7 +90,7 @@ constexpr double kNcx2Big = 0x1p600;
 constexpr double kNcx2Small = 0x1p-600;
 
 // C(x) and pdf(x) by the downward sweep.
-__host__ __device__ inline Ncx2Val ncx2_cdf(double x, double nu, double lam) {
+__host__ __device__ inline __noinline__ Ncx2Val ncx2_cdf(double x, double nu, double lam) {
   if (!(x > 0.0)) return Ncx2Val{0.0, 1.0, 0.0};
   if (x > 1.7976931348623157e308) return Ncx2Val{1.0, 0.0, 0.0};
   const double y = 0.5 * x, a = 0.5 * nu, mu = 0.5 * lam, ly = log(y);
@@ -100,47 +104,49 @@ __host__ __device__ inline Ncx2Val ncx2_cdf(double x, double nu, double lam) {
   const double lD = (y < A + 1.0) ? lc + log(P) : lw + log(fmax(1.0 - Q * exp(lt), 1e-300));
   const double L = fmax(lD, lc);
   double D = exp(lD - L), c = exp(lc - L), w = 1.0;
-  double cdf = 0.0, pdf = 0.0;
+  // mu = 0 ends the sweep at j = 0 before inv_mu is used
+  const double inv_mu = 1.0 / mu, inv_y = 1.0 / y;
+  double cdf = 0.0, pa = 0.0;  // pa = sum c_j (a + j), pdf = pa / (2y)
   int k = 0;
   for (int j = int(je);; --j) {
     const double Aj = a + j;
     cdf += D;
-    pdf += c * Aj / (2.0 * y);
+    pa = fma(c, Aj, pa);
     if (j == 0) break;
     // step to j - 1: D_(j-1) = (j/mu) D_j + c_(j-1),  c_(j-1) = c_j (j/mu) ((a+j)/y)
-    const double rw = j / mu;
-    c = c * rw * (Aj / y);
+    const double rw = j * inv_mu;
+    c = c * rw * (Aj * inv_y);
     w = w * rw;
-    D = D * rw + c;
+    D = fma(D, rw, c);
     if (D > kNcx2Big || c > kNcx2Big) {
       D *= kNcx2Small;
       c *= kNcx2Small;
       cdf *= kNcx2Small;
-      pdf *= kNcx2Small;
+      pa *= kNcx2Small;
       ++k;
     }
     if (j - 1 < mu && j - 1 < jb + 1.0) {
       // remaining head: sum_(k<j-1) w_k P_k <= w_(j-1) r/(1-r), r = (j-1)/mu;
       // sum of the remaining c_k <= c_(j-1) rc/(1-rc)
-      const double r = (j - 1) / mu;
-      const double rc = r * ((a + j - 1) / y);
+      const double r = (j - 1) * inv_mu;
+      const double rc = r * ((a + j - 1) * inv_y);
       if (r < 1.0 && rc < 1.0) {
         const double log_head = log(w) + lw - L - k * 415.88830833596718 + log(r / (1.0 - r));
-        if (log_head <= log(1e-17 * cdf) && D <= 1e-17 * cdf && c * rc / (1.0 - rc) <= 1e-17 * pdf * y) {
+        if (log_head <= log(1e-17 * cdf) && D <= 1e-17 * cdf && c * rc / (1.0 - rc) <= 0.5e-17 * pa) {
           cdf += D;
-          pdf += c * (a + j - 1) / (2.0 * y);
+          pa = fma(c, a + j - 1, pa);
           break;
         }
       }
     }
   }
   const double e = exp(L + k * 415.88830833596718);  // e^L 2^(600 k)
-  const double C = cdf * e, f = pdf * e;
+  const double C = cdf * e, f = pa * (0.5 * inv_y) * e;
   return Ncx2Val{fmin(C, 1.0), fmax(1.0 - C, 0.0), f};
 }
 
 // 1 - C(x) and pdf(x) by the upward sweep.
-__host__ __device__ inline Ncx2Val ncx2_sf(double x, double nu, double lam) {
+__host__ __device__ inline __noinline__ Ncx2Val ncx2_sf(double x, double nu, double lam) {
   if (!(x > 0.0)) return Ncx2Val{0.0, 1.0, 0.0};
   if (x > 1.7976931348623157e308) return Ncx2Val{1.0, 0.0, 0.0};
   const double y = 0.5 * x, a = 0.5 * nu, mu = 0.5 * lam, ly = log(y);
@@ -154,23 +160,26 @@ __host__ __device__ inline Ncx2Val ncx2_sf(double x, double nu, double lam) {
   const double lG = (y < A + 1.0) ? lw + log(fmax(1.0 - P * exp(lt), 1e-300)) : lc + log(Q);
   const double L = fmax(lG, lc);
   double G = exp(lG - L), c = exp(lc - L), w = 1.0;
-  double sf = 0.0, pdf = 0.0;
+  const double muy = mu * y;
+  double sf = 0.0, pa = 0.0;  // pa = sum c_j (a + j), pdf = pa / (2y)
   int k = 0;
   for (int j = int(jb); j < int(jb) + 400000; ++j) {
     const double Aj = a + j;
     sf += G;
-    pdf += c * Aj / (2.0 * y);
+    pa = fma(c, Aj, pa);
     if (mu == 0.0) break;
-    // step to j + 1: G_(j+1) = (mu/(j+1)) (G_j + c_j),  c_(j+1) = c_j (mu/(j+1)) (y/(a+j+1))
-    const double rw = mu / (j + 1.0);
+    // step to j + 1: G_(j+1) = (mu/(j+1)) (G_j + c_j),  c_(j+1) = c_j (mu/(j+1)) (y/(a+j+1)),
+    // with one division: d = 1 / ((j+1)(a+j+1))
+    const double d = 1.0 / ((j + 1.0) * (Aj + 1.0));
+    const double rw = mu * (Aj + 1.0) * d;
     G = rw * (G + c);
-    c = c * rw * (y / (Aj + 1.0));
+    c = c * (muy * d);
     w = w * rw;
     if (G > kNcx2Big || c > kNcx2Big) {
       G *= kNcx2Small;
       c *= kNcx2Small;
       sf *= kNcx2Small;
-      pdf *= kNcx2Small;
+      pa *= kNcx2Small;
       ++k;
     }
     if (j + 1 > mu && j + 1 > je - 1.0) {
@@ -179,19 +188,19 @@ __host__ __device__ inline Ncx2Val ncx2_sf(double x, double nu, double lam) {
       const double rc = r * (y / (Aj + 2.0));
       if (rc < 1.0) {
         const double log_tail = log(w) + lw - L - k * 415.88830833596718 + log(r / (1.0 - r));
-        if (log_tail <= log(1e-17 * sf) && G <= 1e-17 * sf && c * rc / (1.0 - rc) <= 1e-17 * pdf * y) break;
+        if (log_tail <= log(1e-17 * sf) && G <= 1e-17 * sf && c * rc / (1.0 - rc) <= 0.5e-17 * pa) break;
       }
     }
   }
   const double e = exp(L + k * 415.88830833596718);  // e^L 2^(600 k)
-  const double S = sf * e, f = pdf * e;
+  const double S = sf * e, f = pa * (0.5 / y) * e;
   return Ncx2Val{fmax(1.0 - S, 0.0), fmin(S, 1.0), f};
 }
 
 // Quick initial value: Patnaik's scaled central chi-squared with the
 // Wilson-Hilferty cube-root normal approximation; z from A&S 26.2.23 at the
 // tail probability t (lower tail, or upper tail when `upper`).
-__host__ __device__ inline double ncx2_guess(double t, bool upper, double nu, double lam) {
+__host__ __device__ inline __noinline__ double ncx2_guess(double t, bool upper, double nu, double lam) {
   const double tt = sqrt(-2.0 * log(t));
   double z = tt - (2.515517 + tt * (0.802853 + tt * 0.010328)) /
                       (1.0 + tt * (1.432788 + tt * (0.189269 + tt * 0.001308)));
@@ -220,12 +229,13 @@ __host__ __device__ inline double ncx2_guess(double t, bool upper, double nu, do
 // Steps that leave the bracket are replaced by bisection (geometric while the
 // bracket spans more than a factor of two).  `iters` receives the number of
 // CDF evaluations.
+__host__ __device__ inline __noinline__ double ncx2_lgamma(double x) { return lgamma(x); }
 __host__ __device__ inline double ncx2_icdf_tail(double t, bool upper, double nu, double lam,
                                                  int* iters = nullptr) {
   const double a = 0.5 * nu;
   const double lu = upper ? log1p(-t) : log(t);    // log u
   const double lq = upper ? log(t) : log1p(-t);    // log (1 - u)
-  double xlo = 2.0 * exp((lu + lgamma(a + 1.0)) / a);
+  double xlo = 2.0 * exp((lu + ncx2_lgamma(a + 1.0)) / a);
   double xhi = 2.0 * nu * 0.69314718055994531 + 2.0 * lam - 4.0 * lq;
   if (!(xhi > xlo * 1.001)) xhi = xlo * 1.001 + 1e-300;
   double x = ncx2_guess(t, upper, nu, lam);

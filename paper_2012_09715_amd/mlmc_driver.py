@@ -2,8 +2,9 @@
 kernels of libaicdf.
 
 The regular estimator uses the EXACT kind on every level; the nested one
-uses the APPROX kind (two-way differences with approximate normals, or the
-surrogate for CIR) plus the CORRECTION kind (four-way differences).  Per
+uses the APPROX kind (two-way differences with approximate normals; for CIR
+the trained surrogate or Section 5.1's piecewise-polynomial chi-squared
+table) plus the CORRECTION kind (four-way differences).  Per
 level the driver
   1. runs pilot calls of every kind and reads the variance v of Y and the
      device time c per path (HIP events around the level kernel),
@@ -28,6 +29,8 @@ KINDS = (A.KIND_EXACT, A.KIND_APPROX, A.KIND_CORRECTION)
 def level_call(model, params, level, n, kind, approx, seed, offset=0):
     if model == "gbm":
         return A.mlmc_level_gbm(params, level, n, kind, approx, seed, offset)
+    if isinstance(approx, A.Chi2Table):
+        return A.mlmc_level_cir_table(params, level, n, kind, approx, seed, offset)
     return A.mlmc_level_cir(params, level, n, kind, approx, seed, offset)
 
 
@@ -203,6 +206,8 @@ def bench_summary(log=print, seed=20201217, large_paths=1e8):
                      16-row linear dyadic table (FP32)
       gbm_milstein   the same with the Milstein scheme, levels 0..10
       cir            CIR time average, levels 0..6, trained BF16 surrogate
+      cir_poly1/3    the same with Section 5.1's piecewise linear / cubic
+                     chi-squared tables (16 knots, 15 intervals per half)
     At the RMSE for which the regular estimator allocates ~1e8 paths (both
     estimators then fill the GPU and the device-time ratio is meaningful):
       gbm_milstein_1e8 (levels 0..10), cir_1e8 (levels 0..10)."""
@@ -225,6 +230,12 @@ def bench_summary(log=print, seed=20201217, large_paths=1e8):
     log("mlmc: CIR time average, levels 0..6, surrogate")
     res["cir"] = nested_mlmc("cir", CIR_PARAMS, 6, 1e-3, sur, seed + 2, steps_budget=1 << 24)
     log(f"  formula speedup {res['cir']['formula_speedup']:.3f}")
+    for deg in (1, 3):
+        tab = A.Chi2Table.create(NU_CIR, deg)
+        key = f"cir_poly{deg}"
+        log(f"mlmc: CIR time average, levels 0..6, chi-squared table degree {deg}")
+        res[key] = nested_mlmc("cir", CIR_PARAMS, 6, 1e-3, tab, seed + 2, steps_budget=1 << 24)
+        log(f"  formula speedup {res[key]['formula_speedup']:.3f}")
     log("mlmc: CIR time average, levels 0..10, surrogate, ~1e8 paths")
     res["cir_1e8"] = nested_mlmc("cir", CIR_PARAMS, 10, 1e-3, sur, seed + 4, n_pilot=1 << 14,
                                  steps_budget=1 << 24, target_paths=large_paths)
