@@ -213,7 +213,12 @@ typedef struct {
  * kind: AICDF_KIND_*.  approx: dyadic or constant table, required unless
  * kind == EXACT (ignored then).  Paths path_offset .. path_offset+n_paths-1
  * of the stream (seed, level, kind) are simulated; any split of a path range
- * over calls gives the same per-path values.
+ * over calls gives the same per-path values, except that calls of at most
+ * 8192 paths with 2^level >= 128 run one path per wavefront (each lane
+ * multiplies the linear step maps of 2^level/64 consecutive steps, and an
+ * ordered shuffle tree multiplies the lane products), whose FP32 products
+ * round in another order: their per-path values agree with the other launch
+ * shape to FP32 rounding.
  * Draws (Philox counter (block, lo32(path), hi32(path), level | kind << 8),
  * key seed): APPROX takes one 32-bit word per fine step (u24 grid as in
  * aicdf_uniform_fill F32); EXACT and CORRECTION take two words per step
@@ -240,7 +245,14 @@ typedef struct aicdf_surrogate aicdf_surrogate;
  *               exact inverse on the same u24 (counted in out->fallbacks)
  *   CORRECTION  both on two-word draws (surrogate on the u24 of the high word)
  * Stream kinds are 4 + kind in the counter tag.  level 0..12.  Other
- * arguments as mlmc_level_gbm.  Errors: EINVAL, ERANGE, EHIP, ENOMEM. */
+ * arguments as mlmc_level_gbm, with one qualification of split invariance:
+ * EXACT and CORRECTION calls of fewer than 2^17 paths (too few to fill the
+ * GPU one path per thread), and of at most 2^20 paths when the level's
+ * typical lambda = max(v0, theta) e^(-kappa delta) / c is 600 or more, run
+ * one path per wavefront with a wave-cooperative exact inverse that sums in
+ * another order; their per-path values agree with those of other launch
+ * shapes to FP64 rounding (1e-12 relative) and are bit-identical between
+ * calls of the same launch shape.  Errors: EINVAL, ERANGE, EHIP, ENOMEM. */
 aicdf_status mlmc_level_cir(const aicdf_cir_params* params, uint32_t level, uint64_t n_paths,
                             int32_t kind, const aicdf_surrogate* approx, uint64_t seed,
                             uint64_t path_offset, aicdf_level_sums* out, double* path_out,

@@ -14,9 +14,10 @@
 //                  sqrt(y)), clamped at 0; the table is staged in LDS.
 // Launch shape.  Calls with exact inversions and few paths (the high levels
 // of an MLMC allocation, where a level's time is the serial time of one
-// path) run one path per wavefront (lane 0), so that no path waits for the
-// Newton iterations and sweep branches of 63 others; every other call runs
-// one path per thread.
+// path) run one path per wavefront: all 64 lanes follow the same path and
+// evaluate each exact inverse together (ncx2_wave.hpp), and lane 0 keeps the
+// sums; no path waits for the Newton iterations of 63 others.  Every other
+// call runs one path per thread.
 // The coarse path of level l is the fine path
 // observed at even steps (exact in law), so only the functional differs:
 //   FUNC 0  P = v_T
@@ -27,6 +28,7 @@
 #include "mlmc_common.hpp"
 #include "mlp_device.hpp"
 #include "ncx2_device.hpp"
+#include "ncx2_wave.hpp"
 
 using namespace aicdf;
 
@@ -43,12 +45,18 @@ struct CirArgs {
   uint32_t k0, k1, tag;
   Chi2Geom geo;         // APX_POLY*: table geometry
   uint32_t table_rows;  // APX_POLY*: rows staged in LDS
-  uint32_t sparse;      // 1: one path per wavefront (lane 0)
+  uint32_t sparse;      // 1: one path per wavefront
 };
 
-// Largest path count that runs one path per wavefront: every path then has a
-// SIMD slot of its own (256 CUs x 4 SIMDs, two or more waves each).
-constexpr uint64_t kSparseMaxPaths = 2048;
+// One path per wavefront when one path per thread would not fill the GPU
+// (fewer than 2^17 paths = 256 CUs x 4 SIMDs x 2 waves x 64 lanes), and up
+// to 2^20 paths when the exact sweeps are long (typical non-centrality
+// lambda = max(v0, theta) e^(-kappa delta) / c of 600 or more, about 450
+// terms per evaluation), where spreading a sweep over a wavefront beats
+// running 64 divergent sweeps in one.
+constexpr uint64_t kDenseFillPaths = uint64_t(1) << 17;
+constexpr uint64_t kSparseLongMaxPaths = uint64_t(1) << 20;
+constexpr double kSparseLambda = 600.0;
 
 __device__ __forceinline__ float dyadic_w16(float u, const f32x4* __restrict__ tab) {
   const bool p = u < 0.5f;
@@ -80,7 +88,7 @@ struct FuncAcc {
   }
 };
 
-template <int KIND, int FUNC, int APX>
+template <int KIND, int FUNC, int APX, bool SPARSE>
 __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const float* __restrict__ params,
                                                                const uint16_t* __restrict__ w2b,
                                                                const f32x4* __restrict__ wtab,
@@ -108,14 +116,14 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
   LevelAcc acc;
   unsigned long long fb = 0;
   const uint32_t N = a.nsteps;
-  const uint32_t per_block = a.sparse ? kLevelBlock / 64 : kLevelBlock;
-  const uint32_t slot = a.sparse ? threadIdx.x / 64 : threadIdx.x;
-  const bool lead = a.sparse ? (threadIdx.x % 64) == 0 : true;
+  const uint32_t per_block = SPARSE ? kLevelBlock / 64 : kLevelBlock;
+  const uint32_t slot = SPARSE ? threadIdx.x / 64 : threadIdx.x;
+  const bool lead = SPARSE ? (threadIdx.x % 64) == 0 : true;
   for (uint64_t base = uint64_t(blockIdx.x) * per_block; base < a.n_paths;
        base += uint64_t(gridDim.x) * per_block) {
     const uint64_t i = base + slot;
-    const bool act = lead && i < a.n_paths;
-    const bool work = a.sparse ? act : true;  // lanes that run the exact inverse
+    const bool act = lead && i < a.n_paths;   // lanes that keep the sums
+    const bool work = SPARSE ? i < a.n_paths : true;  // wave-uniform when SPARSE
     const uint64_t P = a.path_offset + i;
     const uint32_t plo = uint32_t(P), phi = uint32_t(P >> 32);
     double ve = a.v0;
@@ -140,7 +148,7 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
       }
       if (kExact && work) {
         const double lam = ve * a.decay / a.c;
-        ve = a.c * ncx2_icdf(u53, a.nu, lam);
+        ve = a.c * (SPARSE ? ncx2_icdf_wave(u53, a.nu, lam) : ncx2_icdf(u53, a.nu, lam));
         if (FUNC == 1) fe.node(n + 1, N, ve);
       }
       if (kSurr) {
@@ -154,7 +162,11 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
           const float s = lam + a.nuf;
           x = fmaxf(fmaf(2.0f * sqrtf(s), Pt, s), 0.0f);
         } else {
-          x = work ? float(ncx2_icdf(double(u24), a.nu, double(lam))) : 0.0f;
+          if (work)
+            x = float(SPARSE ? ncx2_icdf_wave(double(u24), a.nu, double(lam))
+                             : ncx2_icdf(double(u24), a.nu, double(lam)));
+          else
+            x = 0.0f;
           fb += act ? 1 : 0;
         }
         vs = a.cf * x;
@@ -204,12 +216,18 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
 template <int KIND, int APX>
 void launch_func(int func, const CirArgs& a, unsigned grid, size_t lds, hipStream_t s, const float* p,
                  const uint16_t* w2, const f32x4* wt, double* part, double* po, unsigned long long* fb) {
-  if (func == 0)
-    hipLaunchKernelGGL((cir_level_kernel<KIND, 0, APX>), dim3(grid), dim3(kLevelBlock), lds, s, a, p, w2, wt, part,
-                       po, fb);
-  else
-    hipLaunchKernelGGL((cir_level_kernel<KIND, 1, APX>), dim3(grid), dim3(kLevelBlock), lds, s, a, p, w2, wt, part,
-                       po, fb);
+  const dim3 g(grid), b(kLevelBlock);
+  if (a.sparse) {
+    if (func == 0)
+      hipLaunchKernelGGL((cir_level_kernel<KIND, 0, APX, true>), g, b, lds, s, a, p, w2, wt, part, po, fb);
+    else
+      hipLaunchKernelGGL((cir_level_kernel<KIND, 1, APX, true>), g, b, lds, s, a, p, w2, wt, part, po, fb);
+  } else {
+    if (func == 0)
+      hipLaunchKernelGGL((cir_level_kernel<KIND, 0, APX, false>), g, b, lds, s, a, p, w2, wt, part, po, fb);
+    else
+      hipLaunchKernelGGL((cir_level_kernel<KIND, 1, APX, false>), g, b, lds, s, a, p, w2, wt, part, po, fb);
+  }
 }
 
 template <int APX>
@@ -254,7 +272,11 @@ aicdf_status cir_setup(const aicdf_cir_params* prm, uint32_t level, uint64_t n_p
   a.k0 = uint32_t(seed);
   a.k1 = uint32_t(seed >> 32);
   a.tag = level | (uint32_t(4 + kind) << 8);
-  a.sparse = (kind != AICDF_KIND_APPROX && n_paths <= kSparseMaxPaths) ? 1u : 0u;
+  const double lam_typ = std::fmax(prm->v0, prm->theta) * a.decay / a.c;
+  a.sparse = (kind != AICDF_KIND_APPROX &&
+              (n_paths < kDenseFillPaths || (n_paths <= kSparseLongMaxPaths && lam_typ >= kSparseLambda)))
+                 ? 1u
+                 : 0u;
   const uint64_t per_block = a.sparse ? kLevelBlock / 64 : kLevelBlock;
   const uint64_t need = (n_paths + per_block - 1) / per_block;
   grid = unsigned(need < uint64_t(kMaxLevelBlocks) ? need : kMaxLevelBlocks);

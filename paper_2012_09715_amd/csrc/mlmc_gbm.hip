@@ -12,6 +12,14 @@
 // with g(dW) = 1 + r h + sigma dW (+ sigma^2 (dW^2 - h)/2 for Milstein) and
 // g(dW^) - g(dW~) = sigma d (+ sigma^2 d (dW^ + dW~)/2), d = dW^ - dW~ taken
 // from the FP64 exact normal minus the FP32 approximate one.
+//
+// Calls with few paths of many steps (the high levels of an MLMC allocation,
+// whose time is the serial time of one path) run one path per wavefront
+// instead: every scheme step maps the state linearly,
+//   X' = g X  (EXACT, APPROX),   (X~, e)' = [[g~, 0], [dg, g^]] (X~, e),
+// so each lane forms the product of the step maps of its 2^l/64 consecutive
+// steps (draws and normals included) and an ordered tree of shuffles
+// multiplies the 64 lane products; lane 0 applies the result to (S0, 0).
 #include <cmath>
 
 #include "mlmc_common.hpp"
@@ -29,7 +37,32 @@ struct GbmArgs {
   const float* table;  // dyadic: 64 rows x 4 floats; constant: rows floats
   uint32_t rows;
   int table_in_lds;
+  uint32_t sparse;     // 1: one path per wavefront (2^l >= 128)
 };
+
+// One path per wavefront for calls of at most this many paths with 2^l >= 128
+// steps (two or more steps per lane, so coarse steps stay within a lane):
+// 64 lanes per path then still fill the GPU's 256 x 2048 lanes.
+constexpr uint64_t kGbmSparseMaxPaths = 8192;
+
+// [[a, 0], [c, b]]: X' = a X, e' = c X + b e.
+struct Lt2 {
+  float a, c, b;
+};
+
+// y after x
+__device__ __forceinline__ Lt2 lt2_mul(const Lt2& y, const Lt2& x) {
+  return Lt2{y.a * x.a, fmaf(y.c, x.a, y.b * x.c), y.b * x.b};
+}
+
+// Ordered product over the wave, M_63 ... M_0, delivered to lane 0.
+__device__ __forceinline__ Lt2 lt2_wave_product(Lt2 m, int lane) {
+  for (int d = 1; d < 64; d <<= 1) {
+    const Lt2 o{__shfl_down(m.a, d), __shfl_down(m.c, d), __shfl_down(m.b, d)};
+    if ((lane & (2 * d - 1)) == 0) m = lt2_mul(o, m);
+  }
+  return m;
+}
 
 // Approximate normal from the staged table (Algorithm 1 / Code 1).  Dyadic
 // rows are zero-padded to four coefficients, so one cubic Horner pass gives
@@ -74,7 +107,67 @@ __device__ __forceinline__ float payoff_diff(const GbmArgs& a, float Xt, float e
   return a.disc * (fmaxf(m + e, 0.0f) - fmaxf(m, 0.0f));
 }
 
-template <int KIND, int SCHEME, int PAYOFF, int TAB>
+// The step maps of steps [n0, n1) of one path (n0, n1 even), as products:
+// fine f and coarse c.  The draws are those of the one-path-per-thread loop.
+template <int KIND, int SCHEME, int TAB>
+__device__ __forceinline__ void gbm_chunk(const GbmArgs& a, const float* tab, uint32_t plo, uint32_t phi, uint32_t n0,
+                                          uint32_t n1, Lt2& f, Lt2& c) {
+  f = Lt2{1.0f, 0.0f, 1.0f};
+  c = Lt2{1.0f, 0.0f, 1.0f};
+  if constexpr (KIND == AICDF_KIND_APPROX) {
+    u32x4 w{};
+    float dWprev = 0.0f;
+    for (uint32_t n = n0; n < n1; ++n) {
+      if ((n & 3u) == 0 || n == n0) w = philox4x32_10(n >> 2, plo, phi, a.tag, a.k0, a.k1);
+      const float dW = a.sqrt_dt * approx_normal<TAB>(u24_from_word(w[n & 3u]), tab, a.rows);
+      f.a = fmaf(f.a, increment<SCHEME>(a, dW, a.dt, a.r_dt), f.a);
+      if (n & 1u)
+        c.a = fmaf(c.a, increment<SCHEME>(a, dWprev + dW, 2.0f * a.dt, a.r_2dt), c.a);
+      else
+        dWprev = dW;
+    }
+  } else if constexpr (KIND == AICDF_KIND_EXACT) {
+    for (uint32_t n = n0; n < n1; n += 2) {
+      const u32x4 w = philox4x32_10(n >> 1, plo, phi, a.tag, a.k0, a.k1);
+      const float dW0 = float(exact_phi_inv(u53_from_words(w[0], w[1])) * a.sqrt_dt_d);
+      const float dW1 = float(exact_phi_inv(u53_from_words(w[2], w[3])) * a.sqrt_dt_d);
+      f.a = fmaf(f.a, increment<SCHEME>(a, dW0, a.dt, a.r_dt), f.a);
+      f.a = fmaf(f.a, increment<SCHEME>(a, dW1, a.dt, a.r_dt), f.a);
+      c.a = fmaf(c.a, increment<SCHEME>(a, dW0 + dW1, 2.0f * a.dt, a.r_2dt), c.a);
+    }
+  } else {
+    for (uint32_t n = n0; n < n1; n += 2) {
+      const u32x4 w = philox4x32_10(n >> 1, plo, phi, a.tag, a.k0, a.k1);
+      float sh = 0.0f, st = 0.0f, sd = 0.0f;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const double Z = exact_phi_inv(u53_from_words(w[2 * h], w[2 * h + 1]));
+        const float Zt = approx_normal<TAB>(u24_from_word(w[2 * h]), tab, a.rows);
+        const float dWh = float(Z * a.sqrt_dt_d);
+        const float dWt = a.sqrt_dt * Zt;
+        const float d = float((Z - double(Zt)) * a.sqrt_dt_d);
+        const float gh = increment<SCHEME>(a, dWh, a.dt, a.r_dt);
+        float dg = a.sigma * d;
+        if (SCHEME == 1) dg = fmaf(a.half_sig2 * d, dWh + dWt, dg);
+        f.c = fmaf(dg, f.a, fmaf(f.c, gh, f.c));
+        f.b = fmaf(f.b, gh, f.b);
+        f.a = fmaf(f.a, increment<SCHEME>(a, dWt, a.dt, a.r_dt), f.a);
+        sh += dWh;
+        st += dWt;
+        sd += d;
+      }
+      const float h2 = 2.0f * a.dt;
+      const float gh = increment<SCHEME>(a, sh, h2, a.r_2dt);
+      float dg = a.sigma * sd;
+      if (SCHEME == 1) dg = fmaf(a.half_sig2 * sd, sh + st, dg);
+      c.c = fmaf(dg, c.a, fmaf(c.c, gh, c.c));
+      c.b = fmaf(c.b, gh, c.b);
+      c.a = fmaf(c.a, increment<SCHEME>(a, st, h2, a.r_2dt), c.a);
+    }
+  }
+}
+
+template <int KIND, int SCHEME, int PAYOFF, int TAB, bool SPARSE>
 __global__ __launch_bounds__(kLevelBlock) void gbm_level_kernel(GbmArgs a, double* __restrict__ partials,
                                                                double* __restrict__ path_out) {
   extern __shared__ f32x4 lds4[];
@@ -88,6 +181,46 @@ __global__ __launch_bounds__(kLevelBlock) void gbm_level_kernel(GbmArgs a, doubl
   }
   LevelAcc acc;
   const uint32_t nf = a.nsteps;
+  if constexpr (SPARSE) {
+    // one path per wavefront; lane l takes steps [l m, l m + m), m = 2^l / 64
+    const int lane = int(threadIdx.x % 64);
+    const uint32_t m = nf / 64;
+    const uint64_t per_block = kLevelBlock / 64;
+    for (uint64_t base = uint64_t(blockIdx.x) * per_block; base < a.n_paths;
+         base += uint64_t(gridDim.x) * per_block) {
+      const uint64_t i = base + threadIdx.x / 64;
+      if (i >= a.n_paths) continue;  // wave-uniform
+      const uint64_t P = a.path_offset + i;
+      Lt2 f, c;
+      gbm_chunk<KIND, SCHEME, TAB>(a, tab, uint32_t(P), uint32_t(P >> 32), lane * m, lane * m + m, f, c);
+      f = lt2_wave_product(f, lane);
+      c = lt2_wave_product(c, lane);
+      if (lane == 0) {
+        float Y, Pf, Pc;
+        const float Xf = a.S0 * f.a, Xc = a.S0 * c.a;
+        if constexpr (KIND == AICDF_KIND_CORRECTION) {
+          const float ef = a.S0 * f.c, ec = a.S0 * c.c;
+          const float df = payoff_diff<PAYOFF>(a, Xf, ef);
+          const float dc = payoff_diff<PAYOFF>(a, Xc, ec);
+          Y = df - dc;
+          Pf = payoff<PAYOFF>(a, Xf + ef);
+          Pc = payoff<PAYOFF>(a, Xc + ec);
+        } else {
+          Pf = payoff<PAYOFF>(a, Xf);
+          Pc = payoff<PAYOFF>(a, Xc);
+          Y = Pf - Pc;
+        }
+        acc.add(double(Y), double(Pf), double(Pc));
+        if (path_out) {
+          path_out[3 * i] = double(Y);
+          path_out[3 * i + 1] = double(Pf);
+          path_out[3 * i + 2] = double(Pc);
+        }
+      }
+    }
+    block_reduce_store(acc, partials);
+    return;
+  }
   const uint64_t stride = uint64_t(gridDim.x) * kLevelBlock;
   for (uint64_t i = uint64_t(blockIdx.x) * kLevelBlock + threadIdx.x; i < a.n_paths; i += stride) {
     const uint64_t P = a.path_offset + i;
@@ -179,8 +312,12 @@ __global__ __launch_bounds__(kLevelBlock) void gbm_level_kernel(GbmArgs a, doubl
 
 template <int KIND, int SCHEME, int PAYOFF, int TAB>
 void launch(const GbmArgs& a, unsigned grid, size_t lds, hipStream_t s, double* partials, double* path_out) {
-  hipLaunchKernelGGL((gbm_level_kernel<KIND, SCHEME, PAYOFF, TAB>), dim3(grid), dim3(kLevelBlock), lds, s, a,
-                     partials, path_out);
+  if (a.sparse)
+    hipLaunchKernelGGL((gbm_level_kernel<KIND, SCHEME, PAYOFF, TAB, true>), dim3(grid), dim3(kLevelBlock), lds, s,
+                       a, partials, path_out);
+  else
+    hipLaunchKernelGGL((gbm_level_kernel<KIND, SCHEME, PAYOFF, TAB, false>), dim3(grid), dim3(kLevelBlock), lds, s,
+                       a, partials, path_out);
 }
 
 template <int KIND, int SCHEME, int PAYOFF>
@@ -256,7 +393,9 @@ extern "C" aicdf_status mlmc_level_gbm(const aicdf_gbm_params* prm, uint32_t lev
     a.table_in_lds = bytes <= 64 * 1024;
     lds = a.table_in_lds ? bytes : 0;
   }
-  const uint64_t need = (n_paths + kLevelBlock - 1) / kLevelBlock;
+  a.sparse = (nf >= 128 && n_paths <= kGbmSparseMaxPaths) ? 1u : 0u;
+  const uint64_t per_block = a.sparse ? kLevelBlock / 64 : kLevelBlock;
+  const uint64_t need = (n_paths + per_block - 1) / per_block;
   const unsigned grid = unsigned(need < uint64_t(kMaxLevelBlocks) ? need : kMaxLevelBlocks);
 
   std::lock_guard<std::mutex> lock(level_mutex());

@@ -230,8 +230,10 @@ __host__ __device__ inline __noinline__ double ncx2_guess(double t, bool upper, 
 // bracket spans more than a factor of two).  `iters` receives the number of
 // CDF evaluations.
 __host__ __device__ inline __noinline__ double ncx2_lgamma(double x) { return lgamma(x); }
-__host__ __device__ inline double ncx2_icdf_tail(double t, bool upper, double nu, double lam,
-                                                 int* iters = nullptr) {
+// Ev supplies Ncx2Val cdf(x) and Ncx2Val sf(x) for the given (nu, lambda).
+template <class Ev>
+__host__ __device__ inline double ncx2_solve(double t, bool upper, double nu, double lam, const Ev& ev,
+                                             int* iters) {
   const double a = 0.5 * nu;
   const double lu = upper ? log1p(-t) : log(t);    // log u
   const double lq = upper ? log(t) : log1p(-t);    // log (1 - u)
@@ -245,7 +247,7 @@ __host__ __device__ inline double ncx2_icdf_tail(double t, bool upper, double nu
     double wlo = log(xlo), whi = log(xhi), w = log(x);
     for (; it < 100; ++it) {
       const double xx = exp(w);
-      const Ncx2Val v = ncx2_cdf(xx, nu, lam);
+      const Ncx2Val v = ev.cdf(xx);
       const double g = v.cdf > 0.0 ? log(v.cdf) - lu : -1e300;
       const double dg = v.cdf > 0.0 ? xx * v.pdf / v.cdf : 0.0;
       if (g == 0.0) break;
@@ -263,7 +265,7 @@ __host__ __device__ inline double ncx2_icdf_tail(double t, bool upper, double nu
     x = exp(w);
   } else {
     for (; it < 100; ++it) {
-      const Ncx2Val v = ncx2_sf(x, nu, lam);
+      const Ncx2Val v = ev.sf(x);
       const double g = v.sf > 0.0 ? lq - log(v.sf) : 1e300;
       const double dg = v.sf > 0.0 ? v.pdf / v.sf : 0.0;
       if (g == 0.0) break;
@@ -280,6 +282,18 @@ __host__ __device__ inline double ncx2_icdf_tail(double t, bool upper, double nu
   }
   if (iters) *iters = it + 1;
   return x;
+}
+
+// The sequential evaluator: one lane sums every term.
+struct Ncx2Seq {
+  double nu, lam;
+  __host__ __device__ Ncx2Val cdf(double x) const { return ncx2_cdf(x, nu, lam); }
+  __host__ __device__ Ncx2Val sf(double x) const { return ncx2_sf(x, nu, lam); }
+};
+
+__host__ __device__ inline double ncx2_icdf_tail(double t, bool upper, double nu, double lam,
+                                                 int* iters = nullptr) {
+  return ncx2_solve(t, upper, nu, lam, Ncx2Seq{nu, lam}, iters);
 }
 
 // C_nu^-1(u; lambda) for u in [0, 1]: 0 at u = 0, +inf at u = 1, NaN outside.

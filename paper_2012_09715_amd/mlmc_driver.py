@@ -130,7 +130,10 @@ def run_estimators(model, params, L, eps, approx, seed, accs, alloc):
     out.update(theta_hat=theta_hat, se_hat=math.sqrt(var_hat), theta_tilde=theta_tilde,
                se_tilde=math.sqrt(var_tilde), device_ms_hat=t_hat, device_ms_tilde=t_tilde,
                measured_speedup=t_hat / t_tilde if t_tilde > 0 else None,
-               fallbacks=sum(runs[l][k].fallbacks for l in range(L + 1) for k in KINDS))
+               fallbacks=sum(runs[l][k].fallbacks for l in range(L + 1) for k in KINDS),
+               level_ms={name: [runs[l][k].ms for l in range(L + 1)]
+                         for name, k in (("exact", A.KIND_EXACT), ("approx", A.KIND_APPROX),
+                                         ("correction", A.KIND_CORRECTION))})
     return out
 
 
@@ -210,7 +213,8 @@ def bench_summary(log=print, seed=20201217, large_paths=1e8):
                      chi-squared tables (16 knots, 15 intervals per half)
     At the RMSE for which the regular estimator allocates ~1e8 paths (both
     estimators then fill the GPU and the device-time ratio is meaningful):
-      gbm_milstein_1e8 (levels 0..10), cir_1e8 (levels 0..10)."""
+      gbm_milstein_1e8 (levels 0..10), cir_1e8 (levels 0..10, surrogate),
+      cir_poly1_1e8 (levels 0..10, linear chi-squared table)."""
     res = {}
     lin16 = A.Table.dyadic(16, 1)
     log("mlmc: GBM Euler-Maruyama, levels 0..8")
@@ -240,6 +244,12 @@ def bench_summary(log=print, seed=20201217, large_paths=1e8):
     res["cir_1e8"] = nested_mlmc("cir", CIR_PARAMS, 10, 1e-3, sur, seed + 4, n_pilot=1 << 14,
                                  steps_budget=1 << 24, target_paths=large_paths)
     r = res["cir_1e8"]
+    log(f"  eps {r['eps']:.2e}: formula {r['formula_speedup']:.3f}, measured {r['measured_speedup']:.3f} "
+        f"({r['device_ms_hat']:.1f} ms vs {r['device_ms_tilde']:.1f} ms)")
+    log("mlmc: CIR time average, levels 0..10, chi-squared table degree 1, ~1e8 paths")
+    res["cir_poly1_1e8"] = nested_mlmc("cir", CIR_PARAMS, 10, 1e-3, A.Chi2Table.create(NU_CIR, 1), seed + 5,
+                                       n_pilot=1 << 14, steps_budget=1 << 24, target_paths=large_paths)
+    r = res["cir_poly1_1e8"]
     log(f"  eps {r['eps']:.2e}: formula {r['formula_speedup']:.3f}, measured {r['measured_speedup']:.3f} "
         f"({r['device_ms_hat']:.1f} ms vs {r['device_ms_tilde']:.1f} ms)")
     return res

@@ -196,10 +196,13 @@ def test_cir_table_exact_kind_matches_surrogate_entry():
 def test_cir_table_split_determinism():
     tab, _ = tables(NU_CIR, 3)
     p = dict(CIR, functional=1)
-    _, whole = run_level(p, 4, 3000, 2, tab, 8)
-    _, first = run_level(p, 4, 1000, 2, tab, 8, 0)
-    _, rest = run_level(p, 4, 2000, 2, tab, 8, 1000)
+    _, whole = run_level(p, 4, 6000, 2, tab, 8)
+    _, first = run_level(p, 4, 2500, 2, tab, 8, 0)
+    _, rest = run_level(p, 4, 3500, 2, tab, 8, 2500)
     assert np.array_equal(whole, np.concatenate([first, rest]))
+    # one path per wavefront (<= 2048 paths): the same paths to FP64 rounding
+    _, few = run_level(p, 4, 700, 2, tab, 8, 4000)
+    assert np.allclose(few, whole[4000:4700], rtol=1e-12, atol=1e-15)
 
 
 def test_cir_table_errors():

@@ -98,11 +98,16 @@ def test_surrogate_kinds_parity(damped, kind, level):
 def test_split_determinism_and_fallbacks(damped):
     s, _ = damped
     p = dict(CIR, functional=1)
-    st, whole = run(p, 2, 3000, 2, s, 5)
-    _, a = run(p, 2, 1000, 2, s, 5, 0)
-    _, b = run(p, 2, 2000, 2, s, 5, 1000)
+    # splits within one launch shape (> 2048 paths: one path per thread) are bit-exact
+    st, whole = run(p, 2, 6000, 2, s, 5)
+    _, a = run(p, 2, 2500, 2, s, 5, 0)
+    _, b = run(p, 2, 3500, 2, s, 5, 2500)
     assert np.array_equal(whole, np.concatenate([a, b]))
-    st2 = A.mlmc_level_cir(p, 2, 3000, 2, s, 5)
+    # calls of <= 2048 paths run one path per wavefront, whose cooperative
+    # exact inverse sums in another order: the same paths to FP64 rounding
+    _, c = run(p, 2, 2000, 2, s, 5, 1000)
+    assert np.allclose(c, whole[1000:3000], rtol=1e-12, atol=1e-15)
+    st2 = A.mlmc_level_cir(p, 2, 6000, 2, s, 5)
     assert st["sum"] == st2["sum"] and st["fallbacks"] == st2["fallbacks"]
     # a surrogate whose range excludes every lambda falls back on every step
     narrow = A.Surrogate.create(NU, 50.0, 51.0, seed=2)
@@ -142,3 +147,21 @@ def test_errors(damped):
         A.mlmc_level_cir(CIR, 2, 10, 1, other, 0)
     with pytest.raises(A.AicdfError, match="ERANGE"):
         A.mlmc_level_cir(CIR, 13, 10, 0, None, 0)
+
+
+@pytest.mark.parametrize("kind", [0, 2])
+def test_thread_per_path_launch_parity(damped, kind):
+    # 2^17 + 5 paths run one path per thread; sampled paths against the
+    # oracle, and against the same paths from a one-path-per-wavefront call
+    s, q = damped
+    p = dict(CIR, functional=1)
+    n, seed, level = (1 << 17) + 5, 61, 1
+    st, got = run(p, level, n, kind, s, seed)
+    pick = np.array([0, 1, 63, 64, 255, 256, 4097, 65535, 99999, n - 2, n - 1])
+    ref = cir.level_replay(p, level, kind, seed, pick, surrogate_x=oracle_surrogate_x(q))
+    scale = np.maximum(np.abs(ref[1]), 1e-3)
+    tol = (1e-9 if kind == 0 else 2e-4 * (1 << level)) * scale
+    assert np.all(np.abs(got[pick, 1] - ref[1]) <= tol)
+    assert np.all(np.abs(got[pick, 0] - ref[0]) <= tol)
+    _, few = run(p, level, 300, kind, s, seed, 99900)
+    assert np.allclose(few, got[99900:100200], rtol=1e-12, atol=1e-15)

@@ -179,3 +179,21 @@ def test_nested_identity_on_means(lin16):
         var = lambda s: s["sum"][1] / n - mean(s) ** 2
         se = np.sqrt((var(e) + var(a) + var(c)) / n)
         assert abs(mean(a) + mean(c) - mean(e)) < 5 * se
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_wave_per_path_launch(lin16, kind, scheme):
+    # calls of <= 8192 paths with 2^l >= 128 steps run one path per wavefront
+    # (products of step maps, reduced over the lanes): against the oracle, bit
+    # reproducible within that launch shape, and equal to one path per thread
+    # to FP32 rounding
+    p = dict(GBM, scheme=scheme, payoff=1)
+    level, seed = 9, 404 + kind
+    _, few = run_paths(p, level, 200, kind, lin16[0], seed, 1000)
+    ref = gbm.level_replay(p, level, kind, seed, 1000 + np.arange(200), table=lin16[1])
+    check_paths(few, ref, kind, level)
+    _, a = run_paths(p, level, 120, kind, lin16[0], seed, 1000)
+    assert np.array_equal(a, few[:120])
+    _, many = run_paths(p, level, 9000, kind, lin16[0], seed, 0)
+    check_paths(many[1000:1200], ref, kind, level)
