@@ -146,11 +146,9 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
         u53 = u53_from_words(hi, lo);
         u24 = u24_from_word(hi);
       }
-      if (kExact && work) {
-        const double lam = ve * a.decay / a.c;
-        ve = a.c * (SPARSE ? ncx2_icdf_wave(u53, a.nu, lam) : ncx2_icdf(u53, a.nu, lam));
-        if (FUNC == 1) fe.node(n + 1, N, ve);
-      }
+      // approximate step first: in CORRECTION its value, moved to the exact
+      // path's lambda, starts the exact inverse's Newton iteration
+      double x0 = 0.0;
       if (kSurr) {
         const float lam = vs * a.decayf / a.cf;
         const float ll = lam > 0.0f ? __logf(lam) : -1e30f;
@@ -169,13 +167,20 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
             x = 0.0f;
           fb += act ? 1 : 0;
         }
+        if (kExact) x0 = double(x) + (ve * a.decay / a.c - double(lam));
         vs = a.cf * x;
         if (FUNC == 1) fs.node(n + 1, N, double(vs));
       }
       if (kPoly) {
         const float lam = vs * a.decayf / a.cf;
         vs = a.cf * fmaxf(chi2_approx_x<APX>(u24, lam, ctab, a.geo), 0.0f);
+        if (kExact) x0 = double(chi2_approx_x<APX>(u24, float(ve * a.decay / a.c), ctab, a.geo));
         if (FUNC == 1) fs.node(n + 1, N, double(vs));
+      }
+      if (kExact && work) {
+        const double lam = ve * a.decay / a.c;
+        ve = a.c * (SPARSE ? ncx2_icdf_wave(u53, a.nu, lam, x0) : ncx2_icdf(u53, a.nu, lam, nullptr, x0));
+        if (FUNC == 1) fe.node(n + 1, N, ve);
       }
     }
     double Y = 0.0, Pf = 0.0, Pc = 0.0;

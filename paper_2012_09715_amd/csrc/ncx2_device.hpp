@@ -66,14 +66,20 @@ __host__ __device__ inline void inc_gamma_pq(double A, double y, double t, doubl
   }
 }
 
-// Sweep bounds [jb, je] covering the c_j peak and the Poisson peak.
+// Sweep bounds [jb, je] covering the c_j peak and the Poisson peak.  When
+// mu < 1e-40 or mu y < 1e-40 every term beyond j = 0 is below 1e-40 of it
+// (D_1/D_0 <= mu, c_1/c_0 = mu y/(a+1), and 1 - C differs from the single
+// term by at most C, itself of the size of that term when y is that small),
+// and the range is the single term j = 0 (je = 0); this also keeps every
+// sweep factor j (a+j)/(mu y) far below the 2^424 that the rescaling by
+// 2^-600 can absorb in one step.
 __host__ __device__ inline void ncx2_sweep_range(double y, double a, double mu, double& jb, double& je) {
   double js = 0.0;
   if (mu > 0.0) js = fmax(0.0, floor(0.5 * (sqrt(a * a + 4.0 * mu * y) - (a + 2.0)) + 0.5));
   const double lo = fmin(js, mu), hi = fmax(js, mu);
   jb = fmax(0.0, floor(lo - 9.0 * sqrt(lo + 1.0) - 16.0));
   je = ceil(hi + 9.0 * sqrt(hi + 1.0) + 16.0);
-  if (mu == 0.0) jb = je = 0.0;
+  if (!(mu >= 1e-40) || !(mu * y >= 1e-40)) jb = je = 0.0;
 }
 
 // log w_j and log t_j.
@@ -167,7 +173,7 @@ __host__ __device__ inline __noinline__ Ncx2Val ncx2_sf(double x, double nu, dou
     const double Aj = a + j;
     sf += G;
     pa = fma(c, Aj, pa);
-    if (mu == 0.0) break;
+    if (je == 0.0) break;  // the single term j = 0
     // step to j + 1: G_(j+1) = (mu/(j+1)) (G_j + c_j),  c_(j+1) = c_j (mu/(j+1)) (y/(a+j+1)),
     // with one division: d = 1 / ((j+1)(a+j+1))
     const double d = 1.0 / ((j + 1.0) * (Aj + 1.0));
@@ -231,16 +237,18 @@ __host__ __device__ inline __noinline__ double ncx2_guess(double t, bool upper, 
 // CDF evaluations.
 __host__ __device__ inline __noinline__ double ncx2_lgamma(double x) { return lgamma(x); }
 // Ev supplies Ncx2Val cdf(x) and Ncx2Val sf(x) for the given (nu, lambda).
+// x0 > 0 inside the bracket replaces the built-in initial value (a caller
+// holding an approximation of the root passes it here).
 template <class Ev>
 __host__ __device__ inline double ncx2_solve(double t, bool upper, double nu, double lam, const Ev& ev,
-                                             int* iters) {
+                                             int* iters, double x0 = 0.0) {
   const double a = 0.5 * nu;
   const double lu = upper ? log1p(-t) : log(t);    // log u
   const double lq = upper ? log(t) : log1p(-t);    // log (1 - u)
   double xlo = 2.0 * exp((lu + ncx2_lgamma(a + 1.0)) / a);
   double xhi = 2.0 * nu * 0.69314718055994531 + 2.0 * lam - 4.0 * lq;
   if (!(xhi > xlo * 1.001)) xhi = xlo * 1.001 + 1e-300;
-  double x = ncx2_guess(t, upper, nu, lam);
+  double x = (x0 > xlo && x0 < xhi) ? x0 : ncx2_guess(t, upper, nu, lam);
   if (!(x > xlo && x < xhi)) x = sqrt(xlo) * sqrt(xhi);
   int it = 0;
   if (!upper) {
@@ -292,16 +300,18 @@ struct Ncx2Seq {
 };
 
 __host__ __device__ inline double ncx2_icdf_tail(double t, bool upper, double nu, double lam,
-                                                 int* iters = nullptr) {
-  return ncx2_solve(t, upper, nu, lam, Ncx2Seq{nu, lam}, iters);
+                                                 int* iters = nullptr, double x0 = 0.0) {
+  return ncx2_solve(t, upper, nu, lam, Ncx2Seq{nu, lam}, iters, x0);
 }
 
 // C_nu^-1(u; lambda) for u in [0, 1]: 0 at u = 0, +inf at u = 1, NaN outside.
-__host__ __device__ inline double ncx2_icdf(double u, double nu, double lam, int* iters = nullptr) {
+// x0 > 0: an approximation of the root to start from.
+__host__ __device__ inline double ncx2_icdf(double u, double nu, double lam, int* iters = nullptr,
+                                            double x0 = 0.0) {
   if (!(u > 0.0)) return u == 0.0 ? 0.0 : __builtin_nan("");
   if (!(u < 1.0)) return u == 1.0 ? __builtin_inf() : __builtin_nan("");
   const bool upper = u > 0.5;
-  return ncx2_icdf_tail(upper ? 1.0 - u : u, upper, nu, lam, iters);
+  return ncx2_icdf_tail(upper ? 1.0 - u : u, upper, nu, lam, iters, x0);
 }
 
 }  // namespace aicdf

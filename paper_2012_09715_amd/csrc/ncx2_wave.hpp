@@ -18,7 +18,10 @@
 // reduction sums the partials.  Matrices, states and sums carry a binary
 // exponent of their own (all entries are non-negative), so no product
 // overflows whatever the range.  Start states, ranges and stopping bounds are
-// those of the sequential sweeps; passes continue past the first range while
+// those of the sequential sweeps, except that a sweep starts further out
+// (down to A = 2y for C, up to A = y/2 for 1 - C, at most 4096 terms more),
+// where the series (continued fraction) that gives its first term converges
+// in a few dozen serial steps; passes continue past the first range while
 // the bound on the remaining head (tail) is not met.  The butterfly gives
 // every lane the same bits, so the Newton driver around it takes identical
 // decisions in all lanes.
@@ -113,6 +116,10 @@ __device__ inline __noinline__ Ncx2Val ncx2_cdf_wave(double x, double nu, double
   const double y = 0.5 * x, a = 0.5 * nu, mu = 0.5 * lam, ly = log(y);
   double jbd, jed;
   ncx2_sweep_range(y, a, mu, jbd, jed);
+  // start high enough that the power series for P converges fast (y / A <=
+  // 1/2): its terms are serial, the longer sweep is spread over the lanes
+  // (je = 0: the single term j = 0)
+  if (jed > 0.0) jed = fmax(jed, fmin(ceil(2.0 * y - a), jed + 4096.0));
   const double A = a + jed;
   const double lw = ncx2_logw(jed, mu), lt = ncx2_logt(A, y, ly);
   double P, Q;
@@ -205,6 +212,9 @@ __device__ inline __noinline__ Ncx2Val ncx2_sf_wave(double x, double nu, double 
   const double y = 0.5 * x, a = 0.5 * nu, mu = 0.5 * lam, ly = log(y);
   double jbd, jed;
   ncx2_sweep_range(y, a, mu, jbd, jed);
+  // start low enough that the continued fraction for Q converges fast
+  // (A <= y / 2); the longer sweep is spread over the lanes
+  if (jed > 0.0) jbd = fmin(jbd, fmax(fmax(0.0, floor(0.5 * y - a)), jbd - 4096.0));
   const double A = a + jbd;
   const double lw = ncx2_logw(jbd, mu), lt = ncx2_logt(A, y, ly);
   double P, Q;
@@ -218,7 +228,6 @@ __device__ inline __noinline__ Ncx2Val ncx2_sf_wave(double x, double nu, double 
   double sf = 0.0, pa = 0.0;
   int Et = 0;
   int jlo = int(jbd), jhi = int(jed);
-  if (mu == 0.0) jhi = jlo;  // a single term
   for (int pass = 0; pass < 400; ++pass) {
     const int n = jhi - jlo + 1;
     const int m = (n + 63) / 64;
@@ -255,7 +264,7 @@ __device__ inline __noinline__ Ncx2Val ncx2_sf_wave(double x, double nu, double 
     ncx2_wave_sum2(pc, pp, es + X.e + E, s1, s2, e12);
     ncx2_acc(sf, Et, s1, e12);
     ncx2_acc(pa, Et, s2, e12);
-    if (mu == 0.0) break;
+    if (jed == 0.0) break;  // the single term j = 0
     {
       const double Gn = fma(all.p, G, all.r * c), cn = all.q * c;
       const double mx = fmax(Gn, cn);
@@ -290,12 +299,13 @@ struct Ncx2Wave {
 };
 
 // C_nu^-1(u; lambda) computed by the whole wavefront; every lane must pass
-// the same (u, nu, lambda) and receives the same result.
-__device__ inline double ncx2_icdf_wave(double u, double nu, double lam) {
+// the same (u, nu, lambda, x0) and receives the same result.  x0 > 0: an
+// approximation of the root to start the Newton iteration from.
+__device__ inline double ncx2_icdf_wave(double u, double nu, double lam, double x0 = 0.0) {
   if (!(u > 0.0)) return u == 0.0 ? 0.0 : __builtin_nan("");
   if (!(u < 1.0)) return u == 1.0 ? __builtin_inf() : __builtin_nan("");
   const bool upper = u > 0.5;
-  return ncx2_solve(upper ? 1.0 - u : u, upper, nu, lam, Ncx2Wave{nu, lam}, nullptr);
+  return ncx2_solve(upper ? 1.0 - u : u, upper, nu, lam, Ncx2Wave{nu, lam}, nullptr, x0);
 }
 
 }  // namespace aicdf

@@ -84,3 +84,26 @@ def test_large_batch_monotone_and_mean():
     assert np.all(np.diff(x) >= 0)
     sd = np.sqrt(2 * (NU_CIR + 2 * lam))
     assert abs(x.mean() - (NU_CIR + lam)) < 5 * sd / np.sqrt(n)
+
+
+@pytest.mark.parametrize("nu", [NU_CIR, 0.5, 3.0])
+def test_wave_and_thread_launches_agree(nu):
+    # n <= 8192 runs one inverse per wavefront, larger batches one per thread:
+    # the same inputs through both, including lambda = 0, tiny and large
+    # lambda and the extreme u of the u53 and u24 grids
+    rng = np.random.default_rng(17)
+    m = 500
+    u = np.concatenate([rng.random(m - 12), [2.0 ** -54, 1e-30, 0.5, 0.5 + 2.0 ** -53, 1 - 2.0 ** -53,
+                                             2.0 ** -24, 1 - 2.0 ** -24, 1e-9, 1 - 1e-9, 0.25, 0.75, 1e-16]])
+    lam = np.exp(rng.uniform(-14, 10, m))
+    lam[:40] = 0.0
+    lam[40:60] = 1e-300
+    lam[60:80] = 3e4
+    few = gpu_icdf(nu, u, lam)
+    reps = 20
+    many = gpu_icdf(nu, np.tile(u, reps), np.tile(lam, reps))[:m]
+    assert np.all(np.isfinite(few)) and np.all(few >= 0)
+    assert np.allclose(few, many, rtol=1e-12, atol=0), np.max(np.abs(few - many) / many)
+    pick = np.concatenate([np.arange(0, 80, 7), np.arange(m - 12, m)])
+    xo = ncx2.icdf(u[pick], nu, lam[pick])
+    assert np.all(np.abs(few[pick] - xo) <= 5e-11 * xo)
