@@ -54,9 +54,12 @@ def log(msg):
 
 
 def time_kernel(fn, reps, stream):
-    """Average device time of fn() over reps launches, by HIP events on the
-    stream the library launches on (torch's current stream)."""
+    """Average device time of fn() over reps launches (after one untimed
+    launch), by HIP events on the stream the library launches on (torch's
+    current stream)."""
     import torch
+    fn()
+    torch.cuda.synchronize()
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
     for i in range(reps):

@@ -245,3 +245,14 @@ def test_cir_table_nested_mean_and_variance_drop(degree):
     assert abs(me - 0.04) < 5 * math.sqrt(ve / n)
     ratio = vc / ve
     assert ratio < (2.0 ** -9 if degree == 1 else 2.0 ** -14), ratio
+
+
+def test_transform_largest_table():
+    # 64 knots x 2 halves x 30 intervals: the largest table (60 KiB of LDS)
+    nu = 2.5
+    tab = A.Chi2Table.create(nu, 3, n_knots=64, n_intervals=30)
+    otab = ct.build(nu, 3, n_knots=64, n_int=30)
+    n = 4096 * 3 + 17
+    u = random_u24(n, seed=64)
+    lam = lambdas(n, seed=30)
+    check_parity(otab, nu, u, lam, run_transform(tab, u, lam))
