@@ -247,12 +247,10 @@ typedef struct aicdf_surrogate aicdf_surrogate;
  * Stream kinds are 4 + kind in the counter tag.  level 0..12.  Other
  * arguments as mlmc_level_gbm, with one qualification of split invariance:
  * EXACT and CORRECTION calls of fewer than 2^17 paths (too few to fill the
- * GPU one path per thread), and of at most 2^20 paths when the level's
- * typical lambda = max(v0, theta) e^(-kappa delta) / c is 600 or more, run
- * one path per wavefront with a wave-cooperative exact inverse that sums in
- * another order; their per-path values agree with those of other launch
- * shapes to FP64 rounding (1e-12 relative) and are bit-identical between
- * calls of the same launch shape.  Errors: EINVAL, ERANGE, EHIP, ENOMEM. */
+ * GPU one path per thread) run one path per wavefront with a
+ * wave-cooperative exact inverse that sums in another order; their per-path
+ * values agree with those of larger calls to FP64 rounding (1e-12 relative)
+ * and are bit-identical between calls of the same launch shape.  Errors: EINVAL, ERANGE, EHIP, ENOMEM. */
 aicdf_status mlmc_level_cir(const aicdf_cir_params* params, uint32_t level, uint64_t n_paths,
                             int32_t kind, const aicdf_surrogate* approx, uint64_t seed,
                             uint64_t path_offset, aicdf_level_sums* out, double* path_out,

@@ -49,14 +49,12 @@ struct CirArgs {
 };
 
 // One path per wavefront when one path per thread would not fill the GPU
-// (fewer than 2^17 paths = 256 CUs x 4 SIMDs x 2 waves x 64 lanes), and up
-// to 2^20 paths when the exact sweeps are long (typical non-centrality
-// lambda = max(v0, theta) e^(-kappa delta) / c of 600 or more, about 450
-// terms per evaluation), where spreading a sweep over a wavefront beats
-// running 64 divergent sweeps in one.
+// (fewer than 2^17 paths = 256 CUs x 4 SIMDs x 2 waves x 64 lanes).  Above
+// that, 64 paths per wavefront win even where the exact sweeps are long
+// (level 10: 262144 paths take about 9 s one per wavefront against 4 s one
+// per thread), and the surrogate's wave-wide network call serves 64 paths
+// instead of one.
 constexpr uint64_t kDenseFillPaths = uint64_t(1) << 17;
-constexpr uint64_t kSparseLongMaxPaths = uint64_t(1) << 20;
-constexpr double kSparseLambda = 600.0;
 
 __device__ __forceinline__ float dyadic_w16(float u, const f32x4* __restrict__ tab) {
   const bool p = u < 0.5f;
@@ -277,11 +275,7 @@ aicdf_status cir_setup(const aicdf_cir_params* prm, uint32_t level, uint64_t n_p
   a.k0 = uint32_t(seed);
   a.k1 = uint32_t(seed >> 32);
   a.tag = level | (uint32_t(4 + kind) << 8);
-  const double lam_typ = std::fmax(prm->v0, prm->theta) * a.decay / a.c;
-  a.sparse = (kind != AICDF_KIND_APPROX &&
-              (n_paths < kDenseFillPaths || (n_paths <= kSparseLongMaxPaths && lam_typ >= kSparseLambda)))
-                 ? 1u
-                 : 0u;
+  a.sparse = (kind != AICDF_KIND_APPROX && n_paths < kDenseFillPaths) ? 1u : 0u;
   const uint64_t per_block = a.sparse ? kLevelBlock / 64 : kLevelBlock;
   const uint64_t need = (n_paths + per_block - 1) / per_block;
   grid = unsigned(need < uint64_t(kMaxLevelBlocks) ? need : kMaxLevelBlocks);
