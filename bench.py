@@ -265,7 +265,7 @@ def main():
         if args.detail:
             with open(args.detail, "w") as f:
                 json.dump(full, f, indent=1)
-        result["mlmc"] = {k: (v if k == "surrogate" else mlmc_driver._short(v)) for k, v in full.items()}
+        result["mlmc"] = {k: (v if k in ("surrogate", "fig4b") else mlmc_driver._short(v)) for k, v in full.items()}
 
     # ---------------------------------------------------------- CPU baseline
     log("cpu baseline (oracle) ...")

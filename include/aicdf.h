@@ -180,6 +180,10 @@ aicdf_status aicdf_bw_probe(int32_t mode, size_t n_bytes, const void* src, void*
 #define AICDF_KIND_EXACT 0      /* Y = P^_l - P^_(l-1), exact inverse        */
 #define AICDF_KIND_APPROX 1     /* Y = P~_l - P~_(l-1), approximation        */
 #define AICDF_KIND_CORRECTION 2 /* Y = P^_l - P^_(l-1) - P~_l + P~_(l-1)     */
+#define AICDF_KIND_TWOWAY 3     /* CIR only: Y = P^_l - P~_l on the same draws,
+                                   the two-way difference at one time step
+                                   (Section 5.2, Figure 4b); P_f = P^_l and
+                                   P_c = P~_l in the sums                     */
 
 typedef struct {
   double S0, r, sigma, T, K; /* dX = r X dt + sigma X dW, X_0 = S0, strike K */
@@ -244,6 +248,8 @@ typedef struct aicdf_surrogate aicdf_surrogate;
  *               whose log(lambda) lies outside the surrogate's range use the
  *               exact inverse on the same u24 (counted in out->fallbacks)
  *   CORRECTION  both on two-word draws (surrogate on the u24 of the high word)
+ *   TWOWAY      both on the draws of CORRECTION, fine paths only:
+ *               Y = P^_f - P~_f, sum_pf over P^_f, sum_pc over P~_f
  * Stream kinds are 4 + kind in the counter tag.  level 0..12.  Other
  * arguments as mlmc_level_gbm, with one qualification of split invariance:
  * EXACT and CORRECTION calls of fewer than 2^17 paths (too few to fill the
@@ -270,6 +276,17 @@ aicdf_status mlmc_level_cir_table(const aicdf_cir_params* params, uint32_t level
                                   int32_t kind, const aicdf_chi2_table* approx, uint64_t seed,
                                   uint64_t path_offset, aicdf_level_sums* out, double* path_out,
                                   void* stream);
+
+/* As mlmc_level_cir with the truncated Euler-Maruyama scheme of Section 5.2
+ * as the approximation (the Gaussian scheme of Figure 4b, not a chi-squared
+ * approximation): APPROX steps take
+ *   v' = v + kappa (theta - v) delta + xi sqrt(|v| delta) Phi^-1(u24)
+ * with Phi^-1 in FP64 and v in FP32 (v may become negative; its modulus goes
+ * under the root).  CORRECTION and TWOWAY pair it with the exact transition
+ * on the same draw.  Errors: EINVAL, ERANGE, EHIP, ENOMEM. */
+aicdf_status mlmc_level_cir_em(const aicdf_cir_params* params, uint32_t level, uint64_t n_paths,
+                               int32_t kind, uint64_t seed, uint64_t path_offset,
+                               aicdf_level_sums* out, double* path_out, void* stream);
 
 /* Optimal allocation of the nested estimator at RMSE eps (Section 4.1):
  *   T^ = 2 eps^-2 (sum_l sqrt(v^_l c^_l))^2,

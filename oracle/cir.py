@@ -17,15 +17,22 @@ step chain, so the coupling is exact.  Functionals
   1  P = the trapezoidal time average of the path on the level's grid
      (the arithmetic average of Section 5.2's path-dependent example).
 Kinds: EXACT (stream kind 4, u53 draws, exact inverse), SURROGATE (stream
-kind 5, u24 draws, the surrogate), CORRECTION (stream kind 6, two-word draws:
-exact from u53 and surrogate from the u24 of the same draw); Y = P_f - P_c
-for the first two and D = (P^_f - P^_c) - (P~_f - P~_c) for the third.
+kind 5, u24 draws, the approximation), CORRECTION (stream kind 6, two-word
+draws: exact from u53 and approximation from the u24 of the same draw);
+Y = P_f - P_c for the first two and D = (P^_f - P^_c) - (P~_f - P~_c) for the
+third; TWOWAY (stream kind 7, the draws of CORRECTION, fine paths only):
+Y = P^_f - P~_f, the two-way difference at one time step of Figure 4b.
+
+Truncated Euler-Maruyama (Section 5.2, after Higham and Mao): the Gaussian
+scheme the chi-squared approximations are compared with,
+    v_(n+1) = v_n + kappa (theta - v_n) delta + xi sqrt(|v_n| delta) Z_n,
+with Z_n = Phi^-1(U_n) on the same uniforms.
 """
 import numpy as np
 
-from . import ncx2, rng
+from . import ncx2, normal, rng
 
-EXACT, SURROGATE, CORRECTION = 0, 1, 2
+EXACT, SURROGATE, CORRECTION, TWOWAY = 0, 1, 2, 3
 STREAM_BASE = 4
 
 
@@ -72,6 +79,19 @@ def exact_x(params):
     return lambda u, lam: ncx2.icdf(u, nu, lam)
 
 
+def em_x(params, level):
+    """The truncated Euler-Maruyama step written as x(u, lambda) for run_path:
+    v_n = lambda c / e^(-kappa delta), v_(n+1) as above, x = v_(n+1) / c."""
+    nu, c, decay, dt = transition_constants(params, level)
+    k, th, xi = params["kappa"], params["theta"], params["xi"]
+
+    def f(u, lam):
+        v = np.asarray(lam, float) * c / decay
+        z = normal.Phi_inv(np.asarray(u, float))
+        return (v + k * (th - v) * dt + xi * np.sqrt(np.abs(v) * dt) * z) / c
+    return f
+
+
 def level_replay(params, level, kind, seed, paths, surrogate_x=None):
     """Per-path (Y, P_f, P_c); P_f, P_c of the exact path for EXACT and
     CORRECTION, of the surrogate path for SURROGATE.
@@ -94,6 +114,8 @@ def level_replay(params, level, kind, seed, paths, surrogate_x=None):
         return Pf - Pc, Pf, Pc
     vt = run_path(params, level, surrogate_x, u24.astype(np.float64))
     Ptf, Ptc = functional_pair(params, level, vt)
+    if kind == TWOWAY:
+        return Pf - Ptf, Pf, Ptf
     return (Pf - Pc) - (Ptf - Ptc), Pf, Pc
 
 

@@ -12,7 +12,7 @@ import torch
 from ._lib import (AicdfError, CirParams, GbmParams, LevelSums, check, lib)
 
 F64, F32, F16, BF16 = 0, 1, 2, 3
-KIND_EXACT, KIND_APPROX, KIND_CORRECTION = 0, 1, 2
+KIND_EXACT, KIND_APPROX, KIND_CORRECTION, KIND_TWOWAY = 0, 1, 2, 3
 SURROGATE_NPARAMS = 4417
 
 _TORCH_TO_DT = {torch.float64: F64, torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
@@ -168,6 +168,16 @@ def mlmc_level_cir_table(params, level, n_paths, kind, table=None, seed=0, path_
     po = _dev(path_out, "path_out") if path_out is not None else None
     check(lib.mlmc_level_cir_table(C.byref(p), level, n_paths, kind, table.handle if table is not None else None,
                                    seed, path_offset, C.byref(out), po, _stream(stream)))
+    return _sums_dict(out)
+
+
+def mlmc_level_cir_em(params, level, n_paths, kind, seed=0, path_offset=0, path_out=None, stream=None):
+    """mlmc_level_cir with the truncated Euler-Maruyama scheme as the approximation."""
+    p = _cir_params(params)
+    out = LevelSums()
+    po = _dev(path_out, "path_out") if path_out is not None else None
+    check(lib.mlmc_level_cir_em(C.byref(p), level, n_paths, kind, seed, path_offset, C.byref(out), po,
+                                _stream(stream)))
     return _sums_dict(out)
 
 

@@ -63,6 +63,7 @@ _PROTOS = {
     "approx_ncx2_icdf": (status, [vp, sz, vp, vp, vp, vp]),
     "mlmc_level_cir_table": (status, [C.POINTER(CirParams), u32, u64, i32, vp, u64, u64,
                                       C.POINTER(LevelSums), vp, vp]),
+    "mlmc_level_cir_em": (status, [C.POINTER(CirParams), u32, u64, i32, u64, u64, C.POINTER(LevelSums), vp, vp]),
     "aicdf_surrogate_create": (status, [dbl, dbl, dbl, u64, C.POINTER(vp)]),
     "aicdf_surrogate_destroy": (None, [vp]),
     "aicdf_surrogate_set_params": (status, [vp, fptr, sz]),

@@ -12,6 +12,14 @@
 //   APX_POLY1/3    Section 5.1's piecewise-polynomial approximation (two
 //                  dyadic half tables per knot, linear interpolation in
 //                  sqrt(y)), clamped at 0; the table is staged in LDS.
+//   APX_EM         the truncated Euler-Maruyama step of Section 5.2 (the
+//                  Gaussian scheme the approximations are compared with):
+//                  v' = v + kappa (theta - v) delta + xi sqrt(|v| delta) Z,
+//                  Z = Phi^-1(u24) in FP64, the state in FP32 (may go
+//                  negative; |v| under the root).
+// A fourth kind, TWOWAY, runs the exact and the approximate fine paths on the
+// same draws (as CORRECTION) and returns Y = P^_f - P~_f, P_f = P^_f,
+// P_c = P~_f: the two-way difference at one time step (Figure 4b).
 // Launch shape.  Calls with exact inversions and few paths (the high levels
 // of an MLMC allocation, where a level's time is the serial time of one
 // path) run one path per wavefront: all 64 lanes follow the same path and
@@ -34,7 +42,8 @@ using namespace aicdf;
 
 namespace {
 
-constexpr int APX_SURROGATE = 0, APX_POLY1 = 1, APX_POLY3 = 3;
+constexpr int APX_SURROGATE = 0, APX_POLY1 = 1, APX_POLY3 = 3, APX_EM = 4;
+constexpr int KIND_TWOWAY = 3;
 constexpr uint32_t kMaxLdsRows = 2048;  // 32 KiB of chi-squared table rows
 
 struct CirArgs {
@@ -43,6 +52,7 @@ struct CirArgs {
   uint32_t level, nsteps;
   uint64_t n_paths, path_offset;
   uint32_t k0, k1, tag;
+  float kdt, theta, xi_sqdt;  // APX_EM: kappa delta, theta, xi sqrt(delta)
   Chi2Geom geo;         // APX_POLY*: table geometry
   uint32_t table_rows;  // APX_POLY*: rows staged in LDS
   uint32_t sparse;      // 1: one path per wavefront
@@ -96,7 +106,8 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
   constexpr bool kExact = KIND != AICDF_KIND_APPROX;
   constexpr bool kApx = KIND != AICDF_KIND_EXACT;
   constexpr bool kSurr = kApx && APX == APX_SURROGATE;
-  constexpr bool kPoly = kApx && APX != APX_SURROGATE;
+  constexpr bool kPoly = kApx && (APX == APX_POLY1 || APX == APX_POLY3);
+  constexpr bool kEm = kApx && APX == APX_EM;
   __shared__ MlpLds L;
   __shared__ f32x4 tab[16];
   extern __shared__ f32x4 ctab[];  // APX_POLY*: the chi-squared table (dynamic LDS)
@@ -175,6 +186,11 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
         if (kExact) x0 = double(chi2_approx_x<APX>(u24, float(ve * a.decay / a.c), ctab, a.geo));
         if (FUNC == 1) fs.node(n + 1, N, double(vs));
       }
+      if (kEm) {
+        const float z = float(exact_phi_inv(double(u24)));
+        vs = fmaf(a.xi_sqdt * sqrtf(fabsf(vs)), z, fmaf(a.kdt, a.theta - vs, vs));
+        if (FUNC == 1) fs.node(n + 1, N, double(vs));
+      }
       if (kExact && work) {
         const double lam = ve * a.decay / a.c;
         ve = a.c * (SPARSE ? ncx2_icdf_wave(u53, a.nu, lam, x0) : ncx2_icdf(u53, a.nu, lam, nullptr, x0));
@@ -184,6 +200,11 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
     double Y = 0.0, Pf = 0.0, Pc = 0.0;
     if (KIND == AICDF_KIND_APPROX) {
       fs.template result<FUNC>(a.level, N, double(vs), Pf, Pc);
+      Y = Pf - Pc;
+    } else if (KIND == KIND_TWOWAY) {
+      double q;
+      fe.template result<FUNC>(a.level, N, ve, Pf, q);
+      fs.template result<FUNC>(a.level, N, double(vs), Pc, q);
       Y = Pf - Pc;
     } else {
       fe.template result<FUNC>(a.level, N, ve, Pf, Pc);
@@ -240,8 +261,10 @@ void launch_kind(int kind, int func, const CirArgs& a, unsigned grid, size_t lds
     launch_func<AICDF_KIND_EXACT, APX_SURROGATE>(func, a, grid, 0, s, p, w2, wt, part, po, fb);
   else if (kind == AICDF_KIND_APPROX)
     launch_func<AICDF_KIND_APPROX, APX>(func, a, grid, lds, s, p, w2, wt, part, po, fb);
-  else
+  else if (kind == AICDF_KIND_CORRECTION)
     launch_func<AICDF_KIND_CORRECTION, APX>(func, a, grid, lds, s, p, w2, wt, part, po, fb);
+  else
+    launch_func<KIND_TWOWAY, APX>(func, a, grid, lds, s, p, w2, wt, part, po, fb);
 }
 
 // Checks shared by both approximations; fills the common arguments.
@@ -249,7 +272,7 @@ aicdf_status cir_setup(const aicdf_cir_params* prm, uint32_t level, uint64_t n_p
                        uint64_t path_offset, aicdf_level_sums* out, CirArgs& a, unsigned& grid) {
   if (!prm || !out) return fail(AICDF_EINVAL, "params and out must be non-NULL");
   if (level > 12) return fail(AICDF_ERANGE, "level %u > 12", level);
-  if (kind < 0 || kind > 2) return fail(AICDF_EINVAL, "kind must be 0, 1 or 2");
+  if (kind < 0 || kind > 3) return fail(AICDF_EINVAL, "kind must be 0, 1, 2 or 3");
   if (prm->functional < 0 || prm->functional > 1 || prm->reserved != 0)
     return fail(AICDF_EINVAL, "functional must be 0 or 1 and reserved 0");
   if (!(prm->kappa > 0.0) || !(prm->theta > 0.0) || !(prm->xi > 0.0) || !(prm->T > 0.0) || !(prm->v0 >= 0.0))
@@ -275,6 +298,9 @@ aicdf_status cir_setup(const aicdf_cir_params* prm, uint32_t level, uint64_t n_p
   a.k0 = uint32_t(seed);
   a.k1 = uint32_t(seed >> 32);
   a.tag = level | (uint32_t(4 + kind) << 8);
+  a.kdt = float(prm->kappa * dt);
+  a.theta = float(prm->theta);
+  a.xi_sqdt = float(prm->xi * std::sqrt(dt));
   a.sparse = (kind != AICDF_KIND_APPROX && n_paths < kDenseFillPaths) ? 1u : 0u;
   const uint64_t per_block = a.sparse ? kLevelBlock / 64 : kLevelBlock;
   const uint64_t need = (n_paths + per_block - 1) / per_block;
@@ -370,6 +396,30 @@ extern "C" aicdf_status mlmc_level_cir_table(const aicdf_cir_params* prm, uint32
   else
     launch_kind<APX_POLY3>(kind, prm->functional, a, grid, lds, s, nullptr, nullptr, wt, ws->partials, path_out,
                            ws->counter);
+  AICDF_HIP(hipGetLastError());
+  return finish_level(ws, grid, s, double(n_paths), out);
+}
+
+extern "C" aicdf_status mlmc_level_cir_em(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths, int32_t kind,
+                                          uint64_t seed, uint64_t path_offset, aicdf_level_sums* out,
+                                          double* path_out, void* stream) {
+  CirArgs a;
+  unsigned grid = 0;
+  aicdf_status st = cir_setup(prm, level, n_paths, kind, seed, path_offset, out, a, grid);
+  if (st != AICDF_OK) return st;
+  if (n_paths == 0) {
+    *out = aicdf_level_sums{};
+    return ok();
+  }
+  std::lock_guard<std::mutex> lock(level_mutex());
+  Workspace* ws = nullptr;
+  st = get_workspace(&ws);
+  if (st != AICDF_OK) return st;
+  auto s = static_cast<hipStream_t>(stream);
+  AICDF_HIP(hipMemsetAsync(ws->counter, 0, sizeof(unsigned long long), s));
+  AICDF_HIP(hipEventRecord(ws->ev0, s));
+  launch_kind<APX_EM>(kind, prm->functional, a, grid, 0, s, nullptr, nullptr, nullptr, ws->partials, path_out,
+                      ws->counter);
   AICDF_HIP(hipGetLastError());
   return finish_level(ws, grid, s, double(n_paths), out);
 }

@@ -193,6 +193,35 @@ def train_surrogate(n_train=10_000_000, epochs=8, batch=4096, lr=3e-3, seed=2020
     return s, rep
 
 
+FIG4B_PARAMS = dict(v0=1.0, kappa=0.5, theta=1.0, xi=1.0, T=1.0, functional=0)
+
+
+def variance_study(params=FIG4B_PARAMS, levels=range(0, 9), n=1 << 18, seed=4242):
+    """Figure 4b on the device: log2 Var(X_T - X~_T) / Var(X_T) on the same
+    draws and time step (the TWOWAY kind) for the truncated Euler-Maruyama
+    scheme and the piecewise linear and cubic chi-squared tables, per level
+    (2^l steps); Var(X_T) from one exact transition over T."""
+    nu = 4 * params["kappa"] * params["theta"] / params["xi"] ** 2
+    tabs = {d: A.Chi2Table.create(nu, d) for d in (1, 3)}
+    ex = A.mlmc_level_cir(params, 0, n, A.KIND_EXACT, None, seed)
+    m = ex["sum_pf"] / n
+    var_x = ex["sum"][1] / n - m * m
+
+    def lr(s):
+        mY = s["sum"][0] / n
+        return math.log2(max(s["sum"][1] / n - mY * mY, 1e-300) / var_x)
+
+    out = {"params": params, "nu": nu, "paths": n, "var_XT": var_x, "levels": list(levels),
+           "log2_ratio": {"em": [], "linear": [], "cubic": []}}
+    for l in levels:
+        out["log2_ratio"]["em"].append(lr(A.mlmc_level_cir_em(params, l, n, A.KIND_TWOWAY, seed + 1 + l)))
+        out["log2_ratio"]["linear"].append(lr(A.mlmc_level_cir_table(params, l, n, A.KIND_TWOWAY, tabs[1],
+                                                                     seed + 101 + l)))
+        out["log2_ratio"]["cubic"].append(lr(A.mlmc_level_cir_table(params, l, n, A.KIND_TWOWAY, tabs[3],
+                                                                    seed + 201 + l)))
+    return out
+
+
 def _short(r):
     keys = ("eps", "levels", "formula_speedup", "measured_speedup", "T_hat_s", "T_tilde_s", "device_ms_hat",
             "device_ms_tilde", "paths_hat", "paths_tilde", "theta_hat", "se_hat", "theta_tilde", "se_tilde",
@@ -246,6 +275,10 @@ def bench_summary(log=print, seed=20201217, large_paths=1e8):
     r = res["cir_1e8"]
     log(f"  eps {r['eps']:.2e}: formula {r['formula_speedup']:.3f}, measured {r['measured_speedup']:.3f} "
         f"({r['device_ms_hat']:.1f} ms vs {r['device_ms_tilde']:.1f} ms)")
+    log("variance study (Figure 4b): kappa 1/2, theta = xi = T = v0 = 1, levels 0..8")
+    res["fig4b"] = variance_study()
+    for k, v in res["fig4b"]["log2_ratio"].items():
+        log(f"  {k:7s} log2 Var(X - X~)/Var(X): " + " ".join(f"{x:6.2f}" for x in v))
     log("mlmc: CIR time average, levels 0..10, chi-squared table degree 1, ~1e8 paths")
     res["cir_poly1_1e8"] = nested_mlmc("cir", CIR_PARAMS, 10, 1e-3, A.Chi2Table.create(NU_CIR, 1), seed + 5,
                                        n_pilot=1 << 14, steps_budget=1 << 24, target_paths=large_paths)

@@ -1,0 +1,105 @@
+"""GPU parity of the truncated Euler-Maruyama CIR level and of the two-way
+difference kind (Section 5.2, Figure 4b) against the oracle's replay, and
+Figure 4b's variance structure on the device.
+
+Tolerances as for the surrogate paths: the approximate path is FP32 on the
+device against FP64 in the oracle (2e-4 N relative), the exact path FP64 on
+both sides.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2012_09715_amd as A
+from oracle import chi2table as ct
+from oracle import cir
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+CIR = dict(v0=0.04, kappa=0.5, theta=0.04, xi=0.3, T=1.0, functional=0)
+# Figure 4b: kappa = 1/2, theta = sigma = T = X0 = 1 (nu = 2, the Feller boundary)
+FIG4B = dict(v0=1.0, kappa=0.5, theta=1.0, xi=1.0, T=1.0, functional=0)
+
+
+def run_em(params, level, n, kind, seed, offset=0):
+    out = torch.zeros(n * 3, dtype=torch.float64, device=DEV)
+    s = A.mlmc_level_cir_em(params, level, n, kind, seed, offset, path_out=out)
+    return s, out.cpu().numpy().reshape(n, 3)
+
+
+def check(got, ref, level):
+    N = 1 << level
+    scale = np.maximum(np.abs(ref[1]), 1e-3)
+    for j in range(3):
+        assert np.all(np.abs(got[:, j] - ref[j]) <= 2e-4 * N * scale), (j, np.max(np.abs(got[:, j] - ref[j]) / scale))
+
+
+@pytest.mark.parametrize("params", [CIR, FIG4B], ids=["cir", "fig4b"])
+@pytest.mark.parametrize("kind", [1, 2, 3])
+@pytest.mark.parametrize("level,functional", [(0, 0), (3, 1), (5, 0)])
+def test_em_level_parity(params, kind, level, functional):
+    p = dict(params, functional=functional)
+    n, seed = 200, 500 + 10 * level + kind
+    st, got = run_em(p, level, n, kind, seed)
+    ref = cir.level_replay(p, level, kind, seed, np.arange(n), surrogate_x=cir.em_x(p, level))
+    check(got, ref, level)
+    assert st["n"] == n
+    assert abs(st["sum"][0] - got[:, 0].sum()) <= 1e-12 * max(1.0, np.abs(got[:, 0]).sum())
+
+
+def test_twoway_with_tables_and_exact_kind():
+    nu = 4 * 0.5 * 0.04 / 0.09
+    tab = A.Chi2Table.create(nu, 1)
+    otab = ct.build(nu, 1)
+    p = dict(CIR, functional=1)
+    level, n, seed = 3, 150, 44
+    out = torch.zeros(n * 3, dtype=torch.float64, device=DEV)
+    A.mlmc_level_cir_table(p, level, n, 3, tab, seed, 0, path_out=out)
+    got = out.cpu().numpy().reshape(n, 3)
+    f = lambda u, lam: np.maximum(ct.approx_x(otab, u, lam, nu), 0.0)
+    ref = cir.level_replay(p, level, 3, seed, np.arange(n), surrogate_x=f)
+    check(got, ref, level)
+    # the exact kind through the EM entry is the exact level itself
+    _, e1 = run_em(p, level, n, 0, seed)
+    out2 = torch.zeros(n * 3, dtype=torch.float64, device=DEV)
+    A.mlmc_level_cir(p, level, n, 0, None, seed, 0, path_out=out2)
+    assert np.array_equal(e1, out2.cpu().numpy().reshape(n, 3))
+
+
+def test_em_errors():
+    with pytest.raises(A.AicdfError, match="EINVAL"):
+        A.mlmc_level_cir_em(CIR, 2, 10, 4, 0)
+    with pytest.raises(A.AicdfError, match="ERANGE"):
+        A.mlmc_level_cir_em(CIR, 13, 10, 1, 0)
+    assert A.mlmc_level_cir_em(CIR, 2, 0, 1, 0)["n"] == 0
+
+
+def test_figure4b_variance_structure():
+    # Var(X_T - X~_T) / Var(X_T) on the same draws and time step: the
+    # truncated EM scheme has strong order 1/2 (the ratio halves per level),
+    # the chi-squared tables give a drop that does not depend on the level
+    # (Figure 4b: about 2^-15 for linear and 2^-25 for cubic).
+    nu = 2.0
+    n = 1 << 16
+    tabs = {d: A.Chi2Table.create(nu, d) for d in (1, 3)}
+    ex = A.mlmc_level_cir(FIG4B, 0, n, 0, None, 700)  # X_T exactly in law: one transition
+    m = ex["sum_pf"] / n
+    var_x = ex["sum"][1] / n - m * m
+
+    def ratio(s):
+        mY = s["sum"][0] / n
+        return (s["sum"][1] / n - mY * mY) / var_x
+
+    em, lin, cub = [], [], []
+    for level in range(0, 7):
+        em.append(ratio(A.mlmc_level_cir_em(FIG4B, level, n, 3, 900 + level)))
+        lin.append(ratio(A.mlmc_level_cir_table(FIG4B, level, n, 3, tabs[1], 810 + level)))
+        cub.append(ratio(A.mlmc_level_cir_table(FIG4B, level, n, 3, tabs[3], 830 + level)))
+    slope = np.diff(np.log2(np.array(em[2:])))
+    assert np.all(np.abs(slope + 1.0) < 0.35), (np.log2(em), slope)
+    for name, r, (lo, hi) in (("linear", lin, (-19.0, -11.0)), ("cubic", cub, (-31.0, -19.0))):
+        r = np.log2(np.array(r))
+        assert np.all((r > lo) & (r < hi)), (name, r)
+        assert r.max() - r.min() < 2.5, (name, r)

@@ -141,3 +141,33 @@ def test_mlp_hand_case():
     P = mlp.forward(p, np.array([1.5, -2.0]), np.array([0.0, 0.3]))
     s = 2.0 / (1.0 + np.exp(-2.0))  # silu(2)
     assert np.allclose(P, np.array([1.5, -2.0]) + 0.25 + 0.5 * s, rtol=1e-15)
+
+
+def test_truncated_em_step_closed_form():
+    # v' = v + kappa (theta - v) delta + xi sqrt(|v| delta) Phi^-1(u): at u = 1/2
+    # the drift alone; antisymmetric in Phi^-1(u) about it; |v| under the root
+    from oracle import normal
+    p = dict(v0=1.0, kappa=0.5, theta=1.0, xi=1.0, T=1.0, functional=0)
+    level = 3
+    nu, c, decay, dt = cir.transition_constants(p, level)
+    f = cir.em_x(p, level)
+    for v in (2.0, 0.3, -0.05):
+        lam = np.array([v * decay / c])
+        drift = v + 0.5 * (1.0 - v) * dt
+        assert np.isclose(f(np.array([0.5]), lam)[0] * c, drift, rtol=0, atol=1e-15)
+        for u in (0.01, 0.3):
+            up = f(np.array([1 - u]), lam)[0] * c
+            lo = f(np.array([u]), lam)[0] * c
+            assert np.isclose(0.5 * (up + lo), drift, rtol=0, atol=1e-14)
+            z = normal.Phi_inv(np.array([1 - u]))[0]
+            assert np.isclose(up - drift, np.sqrt(abs(v) * dt) * z, rtol=1e-13)
+
+
+def test_twoway_replay_is_fine_difference():
+    # TWOWAY returns P^_f - P~_f on the CORRECTION draws, with (P^_f, P~_f)
+    p = dict(CIR, functional=1)
+    em = cir.em_x(p, 2)
+    Y, Pf, Pt = cir.level_replay(p, 2, cir.TWOWAY, 5, np.arange(6), surrogate_x=em)
+    assert np.allclose(Y, Pf - Pt, rtol=0, atol=0)
+    Yc, Pfc, _ = cir.level_replay(p, 2, cir.CORRECTION, 5, np.arange(6), surrogate_x=em)
+    assert not np.allclose(Pf, Pfc)  # another stream (kind 7 vs 6)
