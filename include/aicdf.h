@@ -77,6 +77,15 @@ typedef struct aicdf_table aicdf_table;
 aicdf_status aicdf_table_const_create(uint32_t n_intervals, int32_t construction,
                                       aicdf_dtype coef_t, aicdf_table** out);
 
+/* A piecewise-constant table with caller-given values on N equal intervals
+ * (Section 2.2 includes moment-matching schemes as special cases; N = 2 with
+ * values {-1, +1} gives the Rademacher variables of Section 1 and Table 3).
+ * values: host array of N finite doubles, copied and rounded to coef_t.
+ * n_intervals: power of two in [2, 65536].  Errors: EINVAL, EDTYPE, ENOMEM,
+ * EHIP. */
+aicdf_status aicdf_table_const_values(uint32_t n_intervals, const double* values, aicdf_dtype coef_t,
+                                      aicdf_table** out);
+
 /* Piecewise-polynomial approximation on dyadic intervals (Section 2.3,
  * Theorem 2.5 with decay rate r = 1/2; Section 3.3, Table 1).  A table of
  * T = n_entries rows serves u in (0, 1/2]:

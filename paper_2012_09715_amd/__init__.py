@@ -57,6 +57,20 @@ class Table:
         return cls(h, "const")
 
     @classmethod
+    def const_values(cls, values, coef_dtype=torch.float32):
+        """A piecewise-constant table with the given values (len a power of two)."""
+        vals = [float(v) for v in values]
+        h = C.c_void_p()
+        check(lib.aicdf_table_const_values(len(vals), (C.c_double * len(vals))(*vals), _TORCH_TO_DT[coef_dtype],
+                                           C.byref(h)))
+        return cls(h, "const")
+
+    @classmethod
+    def rademacher(cls):
+        """Rademacher variables (+-1 with probability 1/2): the 2-interval table {-1, +1}."""
+        return cls.const_values([-1.0, 1.0])
+
+    @classmethod
     def dyadic(cls, n_entries=16, degree=1, coef_dtype=torch.float32):
         h = C.c_void_p()
         check(lib.aicdf_table_dyadic_create(n_entries, degree, _TORCH_TO_DT[coef_dtype], C.byref(h)))

@@ -278,6 +278,35 @@ extern "C" aicdf_status aicdf_table_const_create(uint32_t n, int32_t constructio
   return ok();
 }
 
+extern "C" aicdf_status aicdf_table_const_values(uint32_t n, const double* values, aicdf_dtype coef_t,
+                                                 aicdf_table** out) {
+  if (!out) return fail(AICDF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 2 || n > 65536 || (n & (n - 1)))
+    return fail(AICDF_EINVAL, "n_intervals must be a power of two in [2, 65536], got %u", n);
+  if (!values) return fail(AICDF_EINVAL, "values is NULL");
+  if (!dtype_valid(coef_t)) return fail(AICDF_EDTYPE, "invalid coefficient dtype %d", int(coef_t));
+  for (uint32_t k = 0; k < n; ++k)
+    if (!std::isfinite(values[k])) return fail(AICDF_EINVAL, "values[%u] is not finite", k);
+  auto* t = new (std::nothrow) aicdf_table();
+  if (!t) return fail(AICDF_ENOMEM, "host allocation failed");
+  t->kind = 0;
+  t->rows = n;
+  t->cols = 1;
+  t->construction = -1;
+  t->coef_t = coef_t;
+  t->dev = nullptr;
+  t->host.assign(values, values + n);
+  for (auto& v : t->host) v = round_to_dtype(v, coef_t);
+  aicdf_status st = upload_table(t);
+  if (st != AICDF_OK) {
+    delete t;
+    return st;
+  }
+  *out = t;
+  return ok();
+}
+
 extern "C" aicdf_status aicdf_table_dyadic_create(uint32_t n_entries, uint32_t degree,
                                                   aicdf_dtype coef_t, aicdf_table** out) {
   if (!out) return fail(AICDF_EINVAL, "out is NULL");

@@ -236,6 +236,8 @@ def bench_summary(log=print, seed=20201217, large_paths=1e8):
     GPU-filling calls; the estimators themselves are sub-millisecond):
       gbm_em         GBM, Euler-Maruyama, discounted call, levels 0..8,
                      16-row linear dyadic table (FP32)
+      gbm_em_rademacher  the same with Rademacher variables (Table 3's
+                     "too crude" comparator)
       gbm_milstein   the same with the Milstein scheme, levels 0..10
       cir            CIR time average, levels 0..6, trained BF16 surrogate
       cir_poly1/3    the same with Section 5.1's piecewise linear / cubic
@@ -249,6 +251,9 @@ def bench_summary(log=print, seed=20201217, large_paths=1e8):
     log("mlmc: GBM Euler-Maruyama, levels 0..8")
     res["gbm_em"] = nested_mlmc("gbm", GBM_CALL, 8, 1e-3, lin16, seed)
     log(f"  formula speedup {res['gbm_em']['formula_speedup']:.3f}")
+    log("mlmc: GBM Euler-Maruyama, levels 0..8, Rademacher variables")
+    res["gbm_em_rademacher"] = nested_mlmc("gbm", GBM_CALL, 8, 1e-3, A.Table.rademacher(), seed + 6)
+    log(f"  formula speedup {res['gbm_em_rademacher']['formula_speedup']:.3f}")
     log("mlmc: GBM Milstein, levels 0..10")
     res["gbm_milstein"] = nested_mlmc("gbm", dict(GBM_CALL, scheme=1), 10, 1e-3, lin16, seed + 1)
     log(f"  formula speedup {res['gbm_milstein']['formula_speedup']:.3f}")

@@ -132,3 +132,13 @@ def test_host_chi2_table_shapes_and_errors():
         assert lib.aicdf_chi2_host_coeffs(*args, buf, 4) == -1, args
     assert lib.aicdf_chi2_host_coeffs(1.0, 1, 2, 2, buf, 4) == -1  # needs 16 doubles
     assert lib.aicdf_chi2_host_coeffs(1.0, 1, 2, 2, None, 16) == -1
+
+
+def test_const_values_argument_errors():
+    h = C.c_void_p()
+    vals = (C.c_double * 4)(-1.0, 0.0, 1.0, 2.0)
+    assert lib.aicdf_table_const_values(3, vals, 1, C.byref(h)) == -1  # not a power of two
+    assert lib.aicdf_table_const_values(4, None, 1, C.byref(h)) == -1
+    assert lib.aicdf_table_const_values(4, vals, 9, C.byref(h)) == -2
+    bad = (C.c_double * 2)(1.0, float("nan"))
+    assert lib.aicdf_table_const_values(2, bad, 1, C.byref(h)) == -1

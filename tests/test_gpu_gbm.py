@@ -197,3 +197,31 @@ def test_wave_per_path_launch(lin16, kind, scheme):
     assert np.array_equal(a, few[:120])
     _, many = run_paths(p, level, 9000, kind, lin16[0], seed, 0)
     check_paths(many[1000:1200], ref, kind, level)
+
+
+def test_rademacher_table_and_variance():
+    # Rademacher variables as the 2-interval table {-1, +1} (Section 1, Table
+    # 3's first row): the transform gives sign(u - 1/2); the fused levels
+    # match the oracle, and the four-way variance drops only by about 2^-1
+    # against the two-way one (Table 3: log2 ratio -1), the reason the paper
+    # calls them too crude for nested MLMC
+    rad = A.Table.rademacher()
+    u = torch.tensor([0.1, 0.4999, 0.5, 0.9, 1e-9, 1 - 2 ** -24], dtype=torch.float32, device=DEV)
+    z = A.approx_icdf_const(rad, u).cpu().numpy()
+    assert np.array_equal(z, [-1, -1, 1, 1, -1, 1])
+    tab = ("const", np.array([-1.0, 1.0]))
+    for kind in (1, 2):
+        _, got = run_paths(GBM, 4, 500, kind, rad, 61 + kind)
+        ref = gbm.level_replay(GBM, 4, kind, 61 + kind, np.arange(500), table=tab)
+        # |X^ - X~| reaches ~0.3 S0 with +-1 normals: the FP32 rounding bound
+        # of the difference state is that of a full path
+        tol = 3e-7 * 16 * np.maximum(np.abs(ref[1]), 1.0) + 2.4e-7
+        for j in range(3):
+            assert np.all(np.abs(got[:, j] - ref[j]) <= tol), (kind, j)
+    n = 1 << 20
+    for level in (2, 4, 6):
+        s2 = A.mlmc_level_gbm(GBM, level, n, 0, None, 70 + level)
+        s4 = A.mlmc_level_gbm(GBM, level, n, 2, rad, 80 + level)
+        v = lambda s: s["sum"][1] / n - (s["sum"][0] / n) ** 2
+        r = np.log2(v(s4) / v(s2))
+        assert -2.0 < r < -0.3, (level, r)
