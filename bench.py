@@ -113,7 +113,8 @@ def chi2_sweep(A, torch, u, stream):
     [-8, 10], the range the CIR levels visit), 12 algorithmic bytes per
     sample; the exact FP64 inverse on 2^20 of the same pairs for the cost
     ratio; the L2 error against the exact inverse over the midpoints of 2^20
-    cells of (0, 1) at lambda in {1, 10, 100} (Table 6 measure)."""
+    cells of (0, 1) at lambda in {1, 10, 100} (Table 6 measure); the same for
+    the Sankaran approximation (Section 5.1's comparator)."""
     out = []
     n = 1 << 28
     g = torch.Generator(device="cuda")
@@ -141,6 +142,17 @@ def chi2_sweep(A, torch, u, stream):
                     "exact_fp64_samples_per_s": ne / (ms_ex * 1e-3),
                     "exact_over_approx_cost": rate / (ne / (ms_ex * 1e-3))})
         log(f"sweep {out[-1]}")
+    ms = time_kernel(lambda: A.approx_ncx2_sankaran(NU_CIR, uu, lam, x=x), 5, stream)
+    rm = {}
+    for lv in (1.0, 10.0, 100.0):
+        lg = torch.full((m,), lv, dtype=torch.float32, device="cuda")
+        d = A.approx_ncx2_sankaran(NU_CIR, ug, lg).double() - A.ncx2_icdf_exact(NU_CIR, ug.double(), lg.double())
+        rm[str(lv)] = float(torch.sqrt(torch.mean(d * d)).item())
+    rate = n / (ms * 1e-3)
+    out.append({"table": "sankaran", "nu": NU_CIR, "samples_per_s": rate, "GBs": 12 * rate / 1e9,
+                "hbm_frac": 12 * rate / 1e9 / HBM_PEAK_GBS, "ms": ms, "rmse_vs_exact_by_lambda": rm,
+                "exact_over_approx_cost": rate / (ne / (ms_ex * 1e-3))})
+    log(f"sweep {out[-1]}")
     del lam, x
     return out
 
@@ -265,7 +277,8 @@ def main():
         if args.detail:
             with open(args.detail, "w") as f:
                 json.dump(full, f, indent=1)
-        result["mlmc"] = {k: (v if k in ("surrogate", "fig4b") else mlmc_driver._short(v)) for k, v in full.items()}
+        result["mlmc"] = {k: (v if k in ("surrogate", "fig4b", "fig4b_time_average") else mlmc_driver._short(v))
+                          for k, v in full.items()}
 
     # ---------------------------------------------------------- CPU baseline
     log("cpu baseline (oracle) ...")

@@ -297,6 +297,14 @@ aicdf_status mlmc_level_cir_em(const aicdf_cir_params* params, uint32_t level, u
                                int32_t kind, uint64_t seed, uint64_t path_offset,
                                aicdf_level_sums* out, double* path_out, void* stream);
 
+/* As mlmc_level_cir with the Sankaran approximation (approx_ncx2_sankaran,
+ * Section 5.1's comparator) as the approximate transition; CORRECTION and
+ * TWOWAY pair it with the exact transition on the same draw.
+ * Errors: EINVAL, ERANGE, EHIP, ENOMEM. */
+aicdf_status mlmc_level_cir_sankaran(const aicdf_cir_params* params, uint32_t level, uint64_t n_paths,
+                                     int32_t kind, uint64_t seed, uint64_t path_offset,
+                                     aicdf_level_sums* out, double* path_out, void* stream);
+
 /* Optimal allocation of the nested estimator at RMSE eps (Section 4.1):
  *   T^ = 2 eps^-2 (sum_l sqrt(v^_l c^_l))^2,
  *   T~ = 2 eps^-2 (sum_l sqrt(v~_l c~_l) + sqrt(V~_l C~_l))^2,
@@ -362,6 +370,19 @@ aicdf_status aicdf_chi2_host_coeffs(double nu, uint32_t degree, uint32_t n_knots
  * Errors: EINVAL, EALIAS, EHIP. */
 aicdf_status approx_ncx2_icdf(const aicdf_chi2_table* t, size_t n, const float* u,
                               const float* lambda, float* x, void* stream);
+
+/* The Sankaran approximation, Section 5.1's comparator (Table 6d): with
+ * k = nu, c1 = 1 - (2/3)(k+lambda)(k+3 lambda)/(k+2 lambda)^2,
+ * c2 = (k+2 lambda)/(k+lambda)^2, c3 = (c1-1)(1-3 c1),
+ *   x[i] = (k+lambda) max(B, 0)^(1/c1),
+ *   B = 1 + c1 c2 (c1 - 1 + (2-c1) c2 c3/2) + c1 sqrt(2 c2)(1 + c2 c3/2) Phi^-1(u),
+ * with Phi^-1 the exact FP64 inverse and the rest in FP32.  The Gaussian
+ * term's root is sqrt(2 c2) and B is clamped at 0 (both as Table 6d fixes
+ * them).  u, lambda, x: device arrays of n floats; nu in (0, 1e4].
+ * lambda < 0 or NaN gives NaN.  Enqueues on `stream`.
+ * Errors: EINVAL, EALIAS, EHIP. */
+aicdf_status approx_ncx2_sankaran(double nu, size_t n, const float* u, const float* lambda, float* x,
+                                  void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Learned surrogate for the CIR transition (MLP on BF16 MFMA)               */

@@ -195,6 +195,30 @@ def mlmc_level_cir_em(params, level, n_paths, kind, seed=0, path_offset=0, path_
     return _sums_dict(out)
 
 
+def mlmc_level_cir_sankaran(params, level, n_paths, kind, seed=0, path_offset=0, path_out=None, stream=None):
+    """mlmc_level_cir with the Sankaran approximation as the approximate transition."""
+    p = _cir_params(params)
+    out = LevelSums()
+    po = _dev(path_out, "path_out") if path_out is not None else None
+    check(lib.mlmc_level_cir_sankaran(C.byref(p), level, n_paths, kind, seed, path_offset, C.byref(out), po,
+                                      _stream(stream)))
+    return _sums_dict(out)
+
+
+def approx_ncx2_sankaran(nu, u, lam, x=None, stream=None):
+    """The Sankaran approximation x~(u; lambda) in FP32 (u, lambda: float32 device tensors)."""
+    if u.dtype != torch.float32 or lam.dtype != torch.float32:
+        raise AicdfError(-2, "u and lambda must be float32")
+    if u.numel() != lam.numel():
+        raise AicdfError(-1, "u and lambda must have the same number of elements")
+    if x is None:
+        x = torch.empty_like(u)
+    elif x.dtype != torch.float32 or x.numel() != u.numel():
+        raise AicdfError(-2, "x must be float32 with as many elements as u")
+    check(lib.approx_ncx2_sankaran(nu, u.numel(), _dev(u, "u"), _dev(lam, "lambda"), _dev(x, "x"), _stream(stream)))
+    return x
+
+
 def mlmc_allocate(eps, v_hat, c_hat, v2, c2, v4, c4):
     n = len(v_hat)
     arr = lambda xs: (C.c_double * n)(*[float(x) for x in xs])

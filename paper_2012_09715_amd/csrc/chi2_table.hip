@@ -165,6 +165,23 @@ __global__ __launch_bounds__(kBlock) void chi2_transform_kernel(const float* __r
   }
 }
 
+// Sankaran transform: compute-bound (an FP64 exact normal and a power per
+// sample), 256-lane work-groups, four samples per thread.
+__global__ __launch_bounds__(256) void sankaran_kernel(const float* __restrict__ u, const float* __restrict__ lam,
+                                                       float* __restrict__ x, size_t n, float nu, int vec_ok) {
+  const size_t i0 = (size_t(blockIdx.x) * 256 + threadIdx.x) * 4;
+  if (vec_ok && i0 + 4 <= n) {
+    const f32x4 uu = *reinterpret_cast<const f32x4*>(u + i0);
+    const f32x4 ll = *reinterpret_cast<const f32x4*>(lam + i0);
+    f32x4 y;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) y[k] = sankaran_x(uu[k], ll[k], nu);
+    *reinterpret_cast<f32x4*>(x + i0) = y;
+  } else {
+    for (size_t i = i0; i < n && i < i0 + 4; ++i) x[i] = sankaran_x(u[i], lam[i], nu);
+  }
+}
+
 }  // namespace
 
 namespace aicdf {
@@ -250,6 +267,26 @@ extern "C" aicdf_status approx_ncx2_icdf(const aicdf_chi2_table* t, size_t n, co
     else
       hipLaunchKernelGGL(chi2_transform_kernel<3>, dim3(unsigned(blocks)), dim3(kBlock), lds, s, u, lambda, x, n,
                          first, t->dev, rows, g, vec_ok);
+  }
+  AICDF_HIP(hipGetLastError());
+  return ok();
+}
+
+extern "C" aicdf_status approx_ncx2_sankaran(double nu, size_t n, const float* u, const float* lambda, float* x,
+                                             void* stream) {
+  if (!(nu > 0.0) || !(nu <= 1e4)) return fail(AICDF_EINVAL, "nu must be in (0, 1e4]");
+  if (n == 0) return ok();
+  if (!u || !lambda || !x) return fail(AICDF_EINVAL, "NULL buffer with n = %zu", n);
+  if (overlaps(u, n * 4, x, n * 4) || overlaps(lambda, n * 4, x, n * 4))
+    return fail(AICDF_EALIAS, "x overlaps an input");
+  const int vec_ok = aligned(u, 16) && aligned(lambda, 16) && aligned(x, 16);
+  const size_t per_block = 256 * 4;
+  const size_t max_blocks = size_t(1) << 24;
+  auto s = static_cast<hipStream_t>(stream);
+  for (size_t first = 0; first < n; first += max_blocks * per_block) {
+    const size_t m = std::min(n - first, max_blocks * per_block);
+    hipLaunchKernelGGL(sankaran_kernel, dim3(unsigned((m + per_block - 1) / per_block)), dim3(256), 0, s, u + first,
+                       lambda + first, x + first, m, float(nu), vec_ok);
   }
   AICDF_HIP(hipGetLastError());
   return ok();

@@ -12,6 +12,7 @@
 //   APX_POLY1/3    Section 5.1's piecewise-polynomial approximation (two
 //                  dyadic half tables per knot, linear interpolation in
 //                  sqrt(y)), clamped at 0; the table is staged in LDS.
+//   APX_SANKARAN   Section 5.1's comparator (sankaran_x), clamped at 0.
 //   APX_EM         the truncated Euler-Maruyama step of Section 5.2 (the
 //                  Gaussian scheme the approximations are compared with):
 //                  v' = v + kappa (theta - v) delta + xi sqrt(|v| delta) Z,
@@ -42,7 +43,7 @@ using namespace aicdf;
 
 namespace {
 
-constexpr int APX_SURROGATE = 0, APX_POLY1 = 1, APX_POLY3 = 3, APX_EM = 4;
+constexpr int APX_SURROGATE = 0, APX_POLY1 = 1, APX_POLY3 = 3, APX_EM = 4, APX_SANKARAN = 5;
 constexpr int KIND_TWOWAY = 3;
 constexpr uint32_t kMaxLdsRows = 2048;  // 32 KiB of chi-squared table rows
 
@@ -108,6 +109,7 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
   constexpr bool kSurr = kApx && APX == APX_SURROGATE;
   constexpr bool kPoly = kApx && (APX == APX_POLY1 || APX == APX_POLY3);
   constexpr bool kEm = kApx && APX == APX_EM;
+  constexpr bool kSank = kApx && APX == APX_SANKARAN;
   __shared__ MlpLds L;
   __shared__ f32x4 tab[16];
   extern __shared__ f32x4 ctab[];  // APX_POLY*: the chi-squared table (dynamic LDS)
@@ -184,6 +186,12 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
         const float lam = vs * a.decayf / a.cf;
         vs = a.cf * fmaxf(chi2_approx_x<APX>(u24, lam, ctab, a.geo), 0.0f);
         if (kExact) x0 = double(chi2_approx_x<APX>(u24, float(ve * a.decay / a.c), ctab, a.geo));
+        if (FUNC == 1) fs.node(n + 1, N, double(vs));
+      }
+      if (kSank) {
+        const float lam = vs * a.decayf / a.cf;
+        vs = a.cf * sankaran_x(u24, lam, a.nuf);
+        if (kExact) x0 = double(sankaran_x(u24, float(ve * a.decay / a.c), a.nuf));
         if (FUNC == 1) fs.node(n + 1, N, double(vs));
       }
       if (kEm) {
@@ -420,6 +428,30 @@ extern "C" aicdf_status mlmc_level_cir_em(const aicdf_cir_params* prm, uint32_t 
   AICDF_HIP(hipEventRecord(ws->ev0, s));
   launch_kind<APX_EM>(kind, prm->functional, a, grid, 0, s, nullptr, nullptr, nullptr, ws->partials, path_out,
                       ws->counter);
+  AICDF_HIP(hipGetLastError());
+  return finish_level(ws, grid, s, double(n_paths), out);
+}
+
+extern "C" aicdf_status mlmc_level_cir_sankaran(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths,
+                                                int32_t kind, uint64_t seed, uint64_t path_offset,
+                                                aicdf_level_sums* out, double* path_out, void* stream) {
+  CirArgs a;
+  unsigned grid = 0;
+  aicdf_status st = cir_setup(prm, level, n_paths, kind, seed, path_offset, out, a, grid);
+  if (st != AICDF_OK) return st;
+  if (n_paths == 0) {
+    *out = aicdf_level_sums{};
+    return ok();
+  }
+  std::lock_guard<std::mutex> lock(level_mutex());
+  Workspace* ws = nullptr;
+  st = get_workspace(&ws);
+  if (st != AICDF_OK) return st;
+  auto s = static_cast<hipStream_t>(stream);
+  AICDF_HIP(hipMemsetAsync(ws->counter, 0, sizeof(unsigned long long), s));
+  AICDF_HIP(hipEventRecord(ws->ev0, s));
+  launch_kind<APX_SANKARAN>(kind, prm->functional, a, grid, 0, s, nullptr, nullptr, nullptr, ws->partials, path_out,
+                            ws->counter);
   AICDF_HIP(hipGetLastError());
   return finish_level(ws, grid, s, double(n_paths), out);
 }

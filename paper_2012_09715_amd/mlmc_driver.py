@@ -31,6 +31,10 @@ def level_call(model, params, level, n, kind, approx, seed, offset=0):
         return A.mlmc_level_gbm(params, level, n, kind, approx, seed, offset)
     if isinstance(approx, A.Chi2Table):
         return A.mlmc_level_cir_table(params, level, n, kind, approx, seed, offset)
+    if approx == "sankaran":
+        return A.mlmc_level_cir_sankaran(params, level, n, kind, seed, offset)
+    if approx == "em":
+        return A.mlmc_level_cir_em(params, level, n, kind, seed, offset)
     return A.mlmc_level_cir(params, level, n, kind, approx, seed, offset)
 
 
@@ -196,29 +200,31 @@ def train_surrogate(n_train=10_000_000, epochs=8, batch=4096, lr=3e-3, seed=2020
 FIG4B_PARAMS = dict(v0=1.0, kappa=0.5, theta=1.0, xi=1.0, T=1.0, functional=0)
 
 
-def variance_study(params=FIG4B_PARAMS, levels=range(0, 9), n=1 << 18, seed=4242):
-    """Figure 4b on the device: log2 Var(X_T - X~_T) / Var(X_T) on the same
-    draws and time step (the TWOWAY kind) for the truncated Euler-Maruyama
-    scheme and the piecewise linear and cubic chi-squared tables, per level
-    (2^l steps); Var(X_T) from one exact transition over T."""
+def variance_study(params=FIG4B_PARAMS, levels=range(0, 9), n=1 << 16, seed=4242):
+    """Figure 4b on the device: log2 Var(P^ - P~) / Var(P^) for the fine
+    functional on the same draws and time step (the TWOWAY kind: per-path
+    (P^ - P~, P^, P~) in path_out) for the truncated Euler-Maruyama scheme,
+    the piecewise linear and cubic chi-squared tables and the Sankaran
+    approximation, per level (2^l steps).  params["functional"] 0 is X_T,
+    1 the trapezoidal time average (the path-dependent, Asian, case of
+    Section 5.2)."""
+    import torch
     nu = 4 * params["kappa"] * params["theta"] / params["xi"] ** 2
     tabs = {d: A.Chi2Table.create(nu, d) for d in (1, 3)}
-    ex = A.mlmc_level_cir(params, 0, n, A.KIND_EXACT, None, seed)
-    m = ex["sum_pf"] / n
-    var_x = ex["sum"][1] / n - m * m
-
-    def lr(s):
-        mY = s["sum"][0] / n
-        return math.log2(max(s["sum"][1] / n - mY * mY, 1e-300) / var_x)
-
-    out = {"params": params, "nu": nu, "paths": n, "var_XT": var_x, "levels": list(levels),
-           "log2_ratio": {"em": [], "linear": [], "cubic": []}}
+    po = torch.empty(n * 3, dtype=torch.float64, device="cuda")
+    calls = {"em": lambda l, sd: A.mlmc_level_cir_em(params, l, n, A.KIND_TWOWAY, sd, 0, path_out=po),
+             "linear": lambda l, sd: A.mlmc_level_cir_table(params, l, n, A.KIND_TWOWAY, tabs[1], sd, 0,
+                                                            path_out=po),
+             "cubic": lambda l, sd: A.mlmc_level_cir_table(params, l, n, A.KIND_TWOWAY, tabs[3], sd, 0,
+                                                           path_out=po),
+             "sankaran": lambda l, sd: A.mlmc_level_cir_sankaran(params, l, n, A.KIND_TWOWAY, sd, 0, path_out=po)}
+    out = {"params": params, "nu": nu, "paths": n, "levels": list(levels),
+           "log2_ratio": {k: [] for k in calls}}
     for l in levels:
-        out["log2_ratio"]["em"].append(lr(A.mlmc_level_cir_em(params, l, n, A.KIND_TWOWAY, seed + 1 + l)))
-        out["log2_ratio"]["linear"].append(lr(A.mlmc_level_cir_table(params, l, n, A.KIND_TWOWAY, tabs[1],
-                                                                     seed + 101 + l)))
-        out["log2_ratio"]["cubic"].append(lr(A.mlmc_level_cir_table(params, l, n, A.KIND_TWOWAY, tabs[3],
-                                                                    seed + 201 + l)))
+        for j, (k, fn) in enumerate(calls.items()):
+            fn(l, seed + 1000 * j + l)
+            v = po.view(n, 3)
+            out["log2_ratio"][k].append(math.log2(max(float(v[:, 0].var()), 1e-300) / float(v[:, 1].var())))
     return out
 
 
@@ -242,6 +248,7 @@ def bench_summary(log=print, seed=20201217, large_paths=1e8):
       cir            CIR time average, levels 0..6, trained BF16 surrogate
       cir_poly1/3    the same with Section 5.1's piecewise linear / cubic
                      chi-squared tables (16 knots, 15 intervals per half)
+      cir_sankaran   the same with the Sankaran approximation
     At the RMSE for which the regular estimator allocates ~1e8 paths (both
     estimators then fill the GPU and the device-time ratio is meaningful):
       gbm_milstein_1e8 (levels 0..10), cir_1e8 (levels 0..10, surrogate),
@@ -274,16 +281,20 @@ def bench_summary(log=print, seed=20201217, large_paths=1e8):
         log(f"mlmc: CIR time average, levels 0..6, chi-squared table degree {deg}")
         res[key] = nested_mlmc("cir", CIR_PARAMS, 6, 1e-3, tab, seed + 2, steps_budget=1 << 24)
         log(f"  formula speedup {res[key]['formula_speedup']:.3f}")
+    log("mlmc: CIR time average, levels 0..6, Sankaran approximation")
+    res["cir_sankaran"] = nested_mlmc("cir", CIR_PARAMS, 6, 1e-3, "sankaran", seed + 2, steps_budget=1 << 24)
+    log(f"  formula speedup {res['cir_sankaran']['formula_speedup']:.3f}")
     log("mlmc: CIR time average, levels 0..10, surrogate, ~1e8 paths")
     res["cir_1e8"] = nested_mlmc("cir", CIR_PARAMS, 10, 1e-3, sur, seed + 4, n_pilot=1 << 14,
                                  steps_budget=1 << 24, target_paths=large_paths)
     r = res["cir_1e8"]
     log(f"  eps {r['eps']:.2e}: formula {r['formula_speedup']:.3f}, measured {r['measured_speedup']:.3f} "
         f"({r['device_ms_hat']:.1f} ms vs {r['device_ms_tilde']:.1f} ms)")
-    log("variance study (Figure 4b): kappa 1/2, theta = xi = T = v0 = 1, levels 0..8")
-    res["fig4b"] = variance_study()
-    for k, v in res["fig4b"]["log2_ratio"].items():
-        log(f"  {k:7s} log2 Var(X - X~)/Var(X): " + " ".join(f"{x:6.2f}" for x in v))
+    for func, key in ((0, "fig4b"), (1, "fig4b_time_average")):
+        log(f"variance study (Figure 4b, functional {func}): kappa 1/2, theta = xi = T = v0 = 1, levels 0..8")
+        res[key] = variance_study(dict(FIG4B_PARAMS, functional=func))
+        for k, v in res[key]["log2_ratio"].items():
+            log(f"  {k:8s} log2 Var(P - P~)/Var(P): " + " ".join(f"{x:6.2f}" for x in v))
     log("mlmc: CIR time average, levels 0..10, chi-squared table degree 1, ~1e8 paths")
     res["cir_poly1_1e8"] = nested_mlmc("cir", CIR_PARAMS, 10, 1e-3, A.Chi2Table.create(NU_CIR, 1), seed + 5,
                                        n_pilot=1 << 14, steps_budget=1 << 24, target_paths=large_paths)
