@@ -21,6 +21,13 @@ Theorem 2.5, generalised to degree d as the paper describes for piecewise
 polynomials).  The polynomial is written in the local variable
 s = u * 2^(e+1) (s in [1, 2), or (0, 2) on the singular interval); this only
 changes the basis, not the approximant (see `to_u_monomials`).
+
+Geometric intervals (Theorem 2.5 with a general decay rate r in (0, 1)): the
+same layout with entry e on [B_e, B_(e-1)) and the singular (0, B_(T-2)), where
+B_k is r^k / 2 computed by repeated FP64 multiplication and rounded to FP32
+(the thresholds that decide the row, so that a FP32 input's row is fixed by
+exact comparisons); the local variable is s = u / B_e.  r = 1/2 gives the
+dyadic table exactly.
 """
 import numpy as np
 from scipy import integrate
@@ -189,3 +196,93 @@ def dyadic_l2_error_quad(tab):
             val, _ = integrate.quad(f, lo, hi, epsabs=0.0, epsrel=1e-11, limit=400)
             tot += val
     return float(np.sqrt(2.0 * tot))
+
+
+# --------------------------------------------------------------------------
+# geometric intervals with a general decay rate r (Theorem 2.5)
+# --------------------------------------------------------------------------
+def geometric_thresholds(r, n_entries):
+    """Interval bounds B_0..B_(T-1): b_0 = 1/2, b_k = b_(k-1) r by FP64
+    multiplication, B_k = b_k rounded to FP32 (the thresholds that decide the
+    row; exact powers of two when r = 1/2)."""
+    T = int(n_entries)
+    b = np.empty(T)
+    b[0] = 0.5
+    for k in range(1, T):
+        b[k] = b[k - 1] * float(r)
+    return b.astype(np.float32).astype(np.float64)
+
+
+def geometric_interval(e, r, n_entries):
+    """(a, b, h) of row e (1 <= e <= T-1): Theorem 2.5's I_e = [B_e, B_(e-1))
+    for e < T-1 and the singular I_(T-1) = (0, B_(T-2)); s = t / h, h = B_e."""
+    T = int(n_entries)
+    if not 1 <= e <= T - 1:
+        raise ValueError("row 0 is the u = 1/2 row and has no interval")
+    B = geometric_thresholds(r, T)
+    a = 0.0 if e == T - 1 else B[e]
+    return a, B[e - 1], B[e]
+
+
+def geometric_table(r, n_entries, degree):
+    """T x (d+1) table of L2-best polynomials in s = t / B_e on the geometric
+    intervals (row 0 all zeros, as for the dyadic tables, which it equals when
+    r = 1/2)."""
+    T, d = int(n_entries), int(degree)
+    tab = np.zeros((T, d + 1))
+    for e in range(1, T):
+        a, b, h = geometric_interval(e, r, T)
+        s0, s1 = a / h, b / h
+        G = np.empty((d + 1, d + 1))
+        for i in range(d + 1):
+            for j in range(d + 1):
+                p = i + j + 1
+                G[i, j] = h * (s1 ** p - s0 ** p) / p
+        m = np.array([_moment(i, a, b, h) for i in range(d + 1)])
+        tab[e] = np.linalg.solve(G, m)
+    return tab
+
+
+def geometric_row(t, r, n_entries):
+    """Row of the reflected t <= 1/2: 0 at t = 1/2, else the e with
+    B_e <= t < B_(e-1) (e <= T-2) or the singular row T-1, decided by
+    comparisons with the FP32 thresholds (no logarithm)."""
+    t = np.asarray(t, float)
+    B = geometric_thresholds(r, n_entries)
+    T = int(n_entries)
+    e = 1 + np.sum(t[..., None] < B[1:T - 1], axis=-1)
+    return np.where(t >= 0.5, 0, e)
+
+
+def geometric_transform(tab, r, u):
+    """FP64 evaluation: reflect, row, s = t / B_e, Horner, sign."""
+    u = np.asarray(u, float)
+    T = tab.shape[0]
+    B = geometric_thresholds(r, T)
+    p = u < 0.5
+    t = np.where(p, u, 1.0 - u)
+    e = geometric_row(t, r, T)
+    s = t / B[e]
+    c = tab[e]
+    z = np.zeros(u.shape)
+    for j in range(c.shape[-1] - 1, -1, -1):
+        z = z * s + c[..., j]
+    return np.where(p, z, -z)
+
+
+def geometric_l2_error(tab, r):
+    """RMSE ||D - Phi^-1||_2 by the projection identity: on every interval the
+    L2 fit D satisfies int D^2 = int D Phi^-1, so ||D - Phi^-1||^2 =
+    1 - 2 sum_e int_(I_e) D^2 (both halves)."""
+    T, d1 = tab.shape
+    total = 0.0
+    for e in range(1, T):
+        a, b, h = geometric_interval(e, r, T)
+        s0, s1 = a / h, b / h
+        # int (sum c_j s^j)^2 du = h sum_ij c_i c_j (s1^(i+j+1) - s0^(i+j+1)) / (i+j+1)
+        c = tab[e]
+        for i in range(d1):
+            for j in range(d1):
+                p = i + j + 1
+                total += c[i] * c[j] * h * (s1 ** p - s0 ** p) / p
+    return float(np.sqrt(max(1.0 - 2.0 * total, 0.0)))

@@ -188,3 +188,155 @@ def test_dyadic_zero_entry_and_local_basis_range():
             tab = tables.dyadic_table(T, d)
             assert np.all(tab[0] == 0.0)
             assert np.abs(tab).max() < 8.0  # fits FP16 (unlike u-monomials)
+
+
+# ---------------------------------------------------------------- geometric (Theorem 2.5, general r)
+@pytest.mark.parametrize("T,d", [(8, 1), (16, 1), (16, 3), (32, 2)])
+def test_geometric_half_rate_is_the_dyadic_table(T, d):
+    # r = 1/2: the thresholds are the exact powers 2^-(e+1) and s = t 2^(e+1)
+    tab = tables.geometric_table(0.5, T, d)
+    assert np.array_equal(tab, tables.dyadic_table(T, d))
+    assert np.array_equal(tables.geometric_thresholds(0.5, T), 2.0 ** -(np.arange(T) + 1.0))
+
+
+@pytest.mark.parametrize("r", [0.3, 0.6, 0.75, 0.9])
+def test_geometric_row_is_the_logarithm(r):
+    # t in [B_e, B_(e-1)) <=> e = ceil(log(2t) / log r), away from the FP32
+    # rounding of the thresholds; the last row also takes everything below
+    T = 24
+    rng = np.random.default_rng(5)
+    t = 0.5 * r ** rng.uniform(0.0, T + 6.0, 20000)
+    e_log = np.ceil(np.log(2 * t) / math.log(r))
+    frac = e_log - np.log(2 * t) / math.log(r)
+    keep = (frac > 1e-5) & (frac < 1 - 1e-5)
+    want = np.minimum(e_log, T - 1)
+    got = tables.geometric_row(t, r, T)
+    assert keep.sum() > 19000
+    assert np.array_equal(got[keep], want[keep])
+    # boundaries: B_e is in row e, the float below it in row e + 1
+    B = tables.geometric_thresholds(r, T)
+    for e in range(1, T - 1):
+        assert tables.geometric_row(B[e], r, T) == e
+        assert tables.geometric_row(np.nextafter(B[e], 0.0), r, T) == e + 1
+    assert tables.geometric_row(0.5, r, T) == 0 and tables.geometric_row(0.0, r, T) == T - 1
+
+
+@pytest.mark.parametrize("r,T", [(0.6, 12), (0.8, 24), (0.9, 40)])
+def test_geometric_singular_interval_closed_form(r, T):
+    # proof of Theorem 2.5: on (0, b) the linear fit is alpha + beta u with
+    # alpha, beta in closed form from z_b = Phi^-1(b); here s = u / B_(T-1)
+    tab = tables.geometric_table(r, T, 1)
+    a, b, h = tables.geometric_interval(T - 1, r, T)
+    assert a == 0.0
+    alpha, beta = tables.singular_closed_form(b)
+    assert tab[T - 1, 0] == pytest.approx(alpha, rel=1e-10)
+    assert tab[T - 1, 1] / h == pytest.approx(beta, rel=1e-10)
+
+
+@pytest.mark.parametrize("r", [0.6, 0.8, 0.9])
+def test_geometric_brute_force_mpmath(r):
+    # L2 fit by mpmath quadrature directly in u on a non-singular and the singular row
+    mp.mp.dps = 30
+    inv = lambda u: mp.sqrt(2) * mp.erfinv(2 * u - 1)
+    T, d = 10, 2
+    tab = tables.geometric_table(r, T, d)
+    for e in (1, 5, T - 1):
+        a, b, h = tables.geometric_interval(e, r, T)
+        G = mp.matrix(d + 1, d + 1)
+        m = mp.matrix(d + 1, 1)
+        for i in range(d + 1):
+            for j in range(d + 1):
+                G[i, j] = mp.quad(lambda u: (u / h) ** (i + j), [a, b])
+            m[i] = mp.quad(lambda u: (u / h) ** i * inv(u), [a, b])
+        c = mp.lu_solve(G, m)
+        # values, not monomial coefficients: for r near 1 the basis 1, s, s^2
+        # on [1, 1/r) is nearly collinear and the coefficients ill-conditioned
+        s = np.linspace(a / h, b / h, 41)
+        want = np.array([float(sum(c[j] * mp.mpf(x) ** j for j in range(d + 1))) for x in s])
+        assert np.allclose(np.polyval(tab[e][::-1], s), want, rtol=0, atol=1e-11)
+
+
+@pytest.mark.parametrize("r", [0.6, 0.75, 0.9])
+def test_geometric_peano_pointwise_bound(r):
+    # |eps(u)| <= -6 (b-a)^2 (Phi^-1)''(a) <= 2.59 ((1-r)/r)^2 (proof of Theorem 2.5)
+    T = 30
+    tab = tables.geometric_table(r, T, 1)
+    for e in (1, 2, 5, 12, T - 2):
+        a, b, h = tables.geometric_interval(e, r, T)
+        za = float(Phi_inv(a))
+        bound = -6.0 * (b - a) ** 2 * za / float(phi(za)) ** 2
+        assert bound <= 2.59 * ((1 - r) / r) ** 2 * (1 + 1e-6)
+        u = np.linspace(a, b, 2001)[:-1]
+        err = np.abs(Phi_inv(u) - np.polyval(tab[e][::-1], u / h))
+        assert err.max() <= bound
+
+
+@pytest.mark.parametrize("r,T,d", [(0.7, 12, 1), (0.85, 20, 3)])
+def test_geometric_projection_identity_vs_quadrature(r, T, d):
+    # the RMSE from the projection identity against direct quadrature of
+    # (D - Phi^-1)^2 over both halves
+    from scipy import integrate
+    tab = tables.geometric_table(r, T, d)
+    tot = 0.0
+    for e in range(1, T):
+        a, b, h = tables.geometric_interval(e, r, T)
+        f = lambda u: (np.polyval(tab[e][::-1], u / h) - float(Phi_inv(u))) ** 2
+        pts = [b * 1e-8, b * 1e-4, b * 1e-2] if a == 0.0 else None
+        tot += integrate.quad(f, a, b, epsabs=0.0, epsrel=1e-11, limit=400, points=pts)[0]
+    assert tables.geometric_l2_error(tab, r) == pytest.approx(math.sqrt(2 * tot), rel=1e-5)
+
+
+def test_geometric_theorem_2_5_central_rate():
+    # with the singular row negligible (r^(T-1) ~ 1e-30) the error is the
+    # central O((1-r)^2) in L2: local log-log slope in (1 - r) near 2 for
+    # linear rows, and the cubic rows fall faster
+    def rmse(r, d):
+        T = int(math.ceil(math.log(1e-30) / math.log(r))) + 1
+        return tables.geometric_l2_error(tables.geometric_table(r, T, d), r)
+
+    for d, lo, hi in ((1, 1.8, 2.4), (3, 3.5, 5.5)):
+        e8, e9 = rmse(0.8, d), rmse(0.9, d)
+        slope = math.log(e8 / e9) / math.log(2.0)
+        assert lo < slope < hi, (d, slope)
+    assert rmse(0.6, 1) < rmse(0.5, 1) and rmse(0.9, 1) < rmse(0.8, 1)
+
+
+def test_geometric_theorem_2_5_decoupling():
+    # adding intervals at fixed r only shrinks the singular term: the error
+    # plateaus at the central one; the singular row's own contribution is of
+    # order b / |z_b|^2 with b = r^(T-1)/2
+    from scipy import integrate
+    for r, Ts in ((0.5, (40, 60, 90)), (0.8, (100, 150, 200))):
+        e = [tables.geometric_l2_error(tables.geometric_table(r, T, 1), r) for T in Ts]
+        assert abs(e[1] / e[0] - 1) < 0.02 and abs(e[2] / e[1] - 1) < 1e-3
+    for r in (0.5, 0.8):
+        for T in (8, 16, 24, 32):
+            tab = tables.geometric_table(r, T, 1)
+            a, b, h = tables.geometric_interval(T - 1, r, T)
+            f = lambda u: (np.polyval(tab[T - 1][::-1], u / h) - float(Phi_inv(u))) ** 2
+            part = 2 * integrate.quad(f, 0.0, b, epsabs=0.0, epsrel=1e-10, limit=400,
+                                      points=[b * 1e-8, b * 1e-4])[0]
+            zb = float(Phi_inv(b))
+            assert 0.05 < part / (b / zb ** 2) < 1.0, (r, T, part / (b / zb ** 2))
+
+
+def test_geometric_transform_matches_rows():
+    # evaluation: reflection, row choice and local variable against a direct
+    # per-sample polynomial evaluation
+    r, T, d = 0.7, 20, 3
+    tab = tables.geometric_table(r, T, d)
+    rng = np.random.default_rng(9)
+    u = np.concatenate([rng.random(5000), [0.5, 1e-30, 1 - 1e-12]])
+    z = tables.geometric_transform(tab, r, u)
+    for k in rng.integers(0, u.size, 300).tolist() + [u.size - 3, u.size - 2, u.size - 1]:
+        t = min(u[k], 1 - u[k])
+        e = int(tables.geometric_row(np.float64(t), r, T))
+        if e == 0:
+            want = 0.0
+        else:
+            h = tables.geometric_interval(e, r, T)[2]
+            want = np.polyval(tab[e][::-1], t / h)
+        assert z[k] == pytest.approx(want if u[k] < 0.5 else -want, rel=1e-14, abs=1e-14)
+    # Phi^-1 increases: the fit may step back only at a row boundary, and by little
+    zs = z[np.argsort(u)]
+    assert np.all(np.diff(zs) > -0.05)
