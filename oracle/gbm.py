@@ -29,6 +29,7 @@ import numpy as np
 
 from . import rng
 from .normal import Phi_inv
+from .tables import geometric_transform
 from .transform import const_transform, dyadic_transform, dyadic_transform_f32
 
 EXACT, APPROX, CORRECTION = 0, 1, 2
@@ -36,10 +37,14 @@ EXACT, APPROX, CORRECTION = 0, 1, 2
 
 def approx_normals(table, u):
     """Z~ from a table: ('dyadic', T x (d+1) array) evaluated in FP64,
-    ('dyadic_f32', table) evaluated in FP32 as Code 2 does, or ('const', Q)."""
+    ('dyadic_f32', table) evaluated in FP32 as Code 2 does, ('geometric',
+    (table, r)) evaluated in FP64 (Theorem 2.5 with decay rate r), or
+    ('const', Q)."""
     kind, tab = table
     if kind == "dyadic":
         return dyadic_transform(tab, u)[0]
+    if kind == "geometric":
+        return geometric_transform(tab[0], tab[1], u)
     if kind == "dyadic_f32":
         return dyadic_transform_f32(tab, u)[0].astype(np.float64)
     return const_transform(tab, u)

@@ -27,7 +27,7 @@ same layout with entry e on [B_e, B_(e-1)) and the singular (0, B_(T-2)), where
 B_k is r^k / 2 computed by repeated FP64 multiplication and rounded to FP32
 (the thresholds that decide the row, so that a FP32 input's row is fixed by
 exact comparisons); the local variable is s = u / B_e.  r = 1/2 gives the
-dyadic table exactly.
+dyadic table (up to the rounding of the fit).
 """
 import numpy as np
 from scipy import integrate
@@ -224,22 +224,44 @@ def geometric_interval(e, r, n_entries):
     return a, B[e - 1], B[e]
 
 
+def _legendre_moment(i, a, b):
+    """int_a^b P_i(x) Phi^-1(u) du with x = (2u - a - b) / (b - a) mapping the
+    interval onto [-1, 1], by quadrature in z = Phi^-1(u) as in `_moment`."""
+    za = Z_FLOOR if a == 0.0 else float(Phi_inv(a))
+    zb = float(Phi_inv(b))
+    Pi = np.polynomial.legendre.Legendre.basis(i)
+    f = lambda z: float(Pi((2.0 * float(Phi(z)) - a - b) / (b - a))) * z * float(phi(z))
+    pts = [zb - w for w in (8.0, 4.0, 2.0, 1.0, 0.5) if zb - w > za]
+    edges = [za] + sorted(pts) + [zb]
+    total = 0.0
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        # for i >= 1 the moment is a small difference of large parts: an
+        # absolute target keeps the coefficient error near 1e-15
+        val, _ = integrate.quad(f, lo, hi, epsabs=1e-15 * (b - a), epsrel=1e-13, limit=400)
+        total += val
+    return total
+
+
 def geometric_table(r, n_entries, degree):
     """T x (d+1) table of L2-best polynomials in s = t / B_e on the geometric
-    intervals (row 0 all zeros, as for the dyadic tables, which it equals when
-    r = 1/2)."""
+    intervals (row 0 all zeros, as for the dyadic tables, which it reproduces
+    when r = 1/2).  The projection is taken in the Legendre basis of the
+    interval, whose Gram matrix is diagonal (int_a^b P_i P_j du =
+    (b - a) / (2i + 1) when i = j), and then written in powers of s: for r
+    near 1 the normal equations in 1, s, .., s^d on the short range
+    [1, 1/r) would be too ill-conditioned for FP64."""
     T, d = int(n_entries), int(degree)
+    P = np.polynomial.polynomial
     tab = np.zeros((T, d + 1))
     for e in range(1, T):
         a, b, h = geometric_interval(e, r, T)
-        s0, s1 = a / h, b / h
-        G = np.empty((d + 1, d + 1))
-        for i in range(d + 1):
-            for j in range(d + 1):
-                p = i + j + 1
-                G[i, j] = h * (s1 ** p - s0 ** p) / p
-        m = np.array([_moment(i, a, b, h) for i in range(d + 1)])
-        tab[e] = np.linalg.solve(G, m)
+        leg = np.array([(2 * i + 1) / (b - a) * _legendre_moment(i, a, b) for i in range(d + 1)])
+        px = np.polynomial.legendre.leg2poly(leg)           # powers of x
+        x_of_s = np.array([-(a + b) / (b - a), 2.0 * h / (b - a)])  # x = (2 h s - a - b)/(b - a)
+        cs = np.zeros(1)
+        for k in range(len(px) - 1, -1, -1):                # Horner in the polynomial x(s)
+            cs = P.polyadd(P.polymul(cs, x_of_s), [px[k]])
+        tab[e, :len(cs)] = cs[: d + 1]
     return tab
 
 

@@ -195,7 +195,9 @@ def test_dyadic_zero_entry_and_local_basis_range():
 def test_geometric_half_rate_is_the_dyadic_table(T, d):
     # r = 1/2: the thresholds are the exact powers 2^-(e+1) and s = t 2^(e+1)
     tab = tables.geometric_table(0.5, T, d)
-    assert np.array_equal(tab, tables.dyadic_table(T, d))
+    # the dyadic fit solves the monomial normal equations, which lose ~1e-10
+    # for cubics; the geometric fit projects in the Legendre basis
+    assert np.allclose(tab, tables.dyadic_table(T, d), rtol=1e-9, atol=1e-9)
     assert np.array_equal(tables.geometric_thresholds(0.5, T), 2.0 ** -(np.arange(T) + 1.0))
 
 
