@@ -10,9 +10,10 @@ steps.  The JSON line also carries
                 average duration against the 8 TB/s HBM peak
   cpu_baseline  the FP64 oracle on a bounded sample of the same workload
   sweep         the precision sweep (rows 8/16/32 x degree 1/3 x FP32/FP16/BF16
-                coefficients and outputs, plus the 1024-interval constant
-                table): samples/s, GB/s and the exact RMSE/max error against
-                FP64 Phi^-1 over the whole u24 input grid
+                coefficients and outputs, 64-row geometric tables with decay
+                rate r in 0.5..0.9, the 1024-interval constant table):
+                samples/s, GB/s and the exact RMSE/max error against FP64
+                Phi^-1 over the whole u24 input grid
   bandwidth     the plain copy kernel on the same byte count
   mlmc          nested-MLMC speed-ups over the exact inverse at fixed RMSE:
                 GBM (Euler-Maruyama, Milstein) with the linear-16 table and
@@ -252,6 +253,17 @@ def main():
                               "rmse_vs_fp64": rmse, "max_err_vs_fp64": mx})
                 log(f"sweep {sweep[-1]}")
                 del zo
+    # geometric intervals with decay rate r (Theorem 2.5): 64 rows, FP32
+    for rr in (0.5, 0.6, 0.7, 0.8, 0.9):
+        for d in (1, 3):
+            t = A.Table.geometric(rr, 64, d)
+            ms = time_kernel(lambda: A.approx_icdf_linear(t, u, z=z), reps, stream)
+            rmse, mx = exact_error_on_grid(A, torch, t, torch.float32, "geometric")
+            sweep.append({"table": f"geometric64_r{rr}", "degree": d, "coef": "f32", "out": "f32",
+                          "samples_per_s": N_MAIN / (ms * 1e-3), "GBs": 8 * N_MAIN / (ms * 1e-3) / 1e9,
+                          "hbm_frac": 8 * N_MAIN / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "ms": ms,
+                          "rmse_vs_fp64": rmse, "max_err_vs_fp64": mx})
+            log(f"sweep {sweep[-1]}")
     tc = A.Table.const(1024, 0, torch.float32)
     ms = time_kernel(lambda: A.approx_icdf_const(tc, u, z=z), reps, stream)
     rmse, mx = exact_error_on_grid(A, torch, tc, torch.float32, "const")

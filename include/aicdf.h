@@ -101,8 +101,35 @@ aicdf_status aicdf_table_const_values(uint32_t n_intervals, const double* values
 aicdf_status aicdf_table_dyadic_create(uint32_t n_entries, uint32_t degree,
                                        aicdf_dtype coef_t, aicdf_table** out);
 
+/* Piecewise-polynomial approximation on geometric intervals with a general
+ * decay rate r (Theorem 2.5).  With thresholds B_k = r^k / 2 (computed by
+ * repeated FP64 multiplication from B_0 = 1/2 and rounded to FP32, so that a
+ * FP32 input's row is decided by exact comparisons), T = n_entries rows serve
+ * u in (0, 1/2]:
+ *   row 0        u = 1/2 exactly; all coefficients zero
+ *   row e        [B_e, B_(e-1)) for 1 <= e <= T-2
+ *   row T-1      the singular interval (0, B_(T-2))
+ * u > 1/2 is served by antisymmetry.  Each row holds the L2-best polynomial
+ * of the given degree in s = u / B_e.  r = 1/2 reproduces the dyadic table
+ * exactly.  The transform takes F32 input only: the row comes from a log2
+ * estimate corrected against the thresholds, which costs more than the
+ * dyadic exponent read (the trade-off of Section 3.3).
+ * r in [0.05, 0.95]; n_entries in [3, 64] with r^(n_entries-1)/2 a normal
+ * FP32 number; degree in [0, 3]; coef_t: F32, F16 or BF16.
+ * Errors: EINVAL, EDTYPE, ENOMEM, EHIP. */
+aicdf_status aicdf_table_geometric_create(double r, uint32_t n_entries, uint32_t degree, aicdf_dtype coef_t,
+                                          aicdf_table** out);
+
+/* The coef_t-rounded coefficients aicdf_table_geometric_create would store,
+ * computed on the host, row-major T x (degree+1) into host_out
+ * (cap >= T*(degree+1)); coef_t = F64 gives the unrounded FP64 fit.
+ * Errors: EINVAL, EDTYPE, ERANGE. */
+aicdf_status aicdf_table_geometric_host(double r, uint32_t n_entries, uint32_t degree, aicdf_dtype coef_t,
+                                        double* host_out, size_t cap);
+
 /* Copies the stored (coef_t-rounded) coefficients to host memory as doubles,
- * row-major rows x cols (constant tables: N x 1; dyadic: T x (degree+1)).
+ * row-major rows x cols (constant tables: N x 1; dyadic and geometric:
+ * T x (degree+1)).
  * host_out may be NULL to query rows/cols; otherwise cap >= rows*cols.
  * Errors: EINVAL, ERANGE. */
 aicdf_status aicdf_table_coeffs(const aicdf_table* table, double* host_out, size_t cap,
@@ -138,14 +165,17 @@ aicdf_status approx_icdf_const(const aicdf_table* table, size_t n, const void* u
  * F64 input), s = u' 2^(e+1), Horner's rule with fused multiply-adds, sign
  * restored.  F32 input evaluates in FP32; F64 input evaluates in FP64 on the
  * stored coefficients.  Same dtype pairs, layout and errors as
- * approx_icdf_const. */
+ * approx_icdf_const.  On a geometric table (F32 input only, else EDTYPE) the
+ * row is the e with B_e <= u' < B_(e-1) and s = u' (1/B_e) with the FP32
+ * reciprocal of B_e. */
 aicdf_status approx_icdf_linear(const aicdf_table* table, size_t n, const void* u, aicdf_dtype u_t,
                                 void* z, aicdf_dtype z_t, void* stream);
 
-/* The row (dyadic table) or interval (constant table) index that the two
- * transforms above select for each u, computed by the same device code; for
- * verifying the index step of Code 1 / Algorithm 1.  idx: device, n uint32.
- * u_t: F32 or F64.  Errors: EINVAL, EDTYPE, EALIAS, EHIP. */
+/* The row (dyadic or geometric table) or interval (constant table) index
+ * that the two transforms above select for each u, computed by the same
+ * device code; for verifying the index step of Code 1 / Algorithm 1.
+ * idx: device, n uint32.  u_t: F32 or F64 (F32 only for geometric tables).
+ * Errors: EINVAL, EDTYPE, EALIAS, EHIP. */
 aicdf_status approx_icdf_index(const aicdf_table* table, size_t n, const void* u, aicdf_dtype u_t,
                                uint32_t* idx, void* stream);
 
@@ -223,8 +253,10 @@ typedef struct {
  * Milstein; the coarse Wiener increments are pairwise sums of the fine ones;
  * exact and approximate normals of one step come from one uniform).
  * level: 0..20 (2^level fine steps; no coarse path at level 0).
- * kind: AICDF_KIND_*.  approx: dyadic or constant table, required unless
- * kind == EXACT (ignored then).  Paths path_offset .. path_offset+n_paths-1
+ * kind: AICDF_KIND_*.  approx: dyadic, geometric or constant table, required
+ * unless kind == EXACT (ignored then); its normals are those of
+ * approx_icdf_linear / approx_icdf_const on the same u24 values.
+ * Paths path_offset .. path_offset+n_paths-1
  * of the stream (seed, level, kind) are simulated; any split of a path range
  * over calls gives the same per-path values, except that calls of at most
  * 8192 paths with 2^level >= 128 run one path per wavefront (each lane

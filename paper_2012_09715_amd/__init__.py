@@ -76,6 +76,15 @@ class Table:
         check(lib.aicdf_table_dyadic_create(n_entries, degree, _TORCH_TO_DT[coef_dtype], C.byref(h)))
         return cls(h, "dyadic")
 
+    @classmethod
+    def geometric(cls, r=0.5, n_entries=16, degree=1, coef_dtype=torch.float32):
+        """Piecewise polynomial on geometric intervals [r^e/2, r^(e-1)/2) (Theorem 2.5)."""
+        h = C.c_void_p()
+        check(lib.aicdf_table_geometric_create(float(r), n_entries, degree, _TORCH_TO_DT[coef_dtype], C.byref(h)))
+        t = cls(h, "geometric")
+        t.r = float(r)
+        return t
+
     def coeffs(self):
         rows, cols = C.c_uint32(), C.c_uint32()
         check(lib.aicdf_table_coeffs(self._h, None, 0, C.byref(rows), C.byref(cols)))
@@ -97,6 +106,13 @@ def table_host_coeffs(kind, n, param, coef_dtype=torch.float32):
     buf = (C.c_double * (n * cols))()
     check(lib.aicdf_table_host_coeffs(k, n, param, _TORCH_TO_DT[coef_dtype], buf, len(buf)))
     return torch.tensor(list(buf), dtype=torch.float64).reshape(n, cols)
+
+
+def geometric_host_coeffs(r, n_entries, degree, coef_dtype=torch.float32):
+    """Host-built coefficients of a geometric table (no device needed)."""
+    buf = (C.c_double * (n_entries * (degree + 1)))()
+    check(lib.aicdf_table_geometric_host(float(r), n_entries, degree, _TORCH_TO_DT[coef_dtype], buf, len(buf)))
+    return torch.tensor(list(buf), dtype=torch.float64).reshape(n_entries, degree + 1)
 
 
 def _out(u, z, out_dtype):

@@ -40,6 +40,8 @@ _PROTOS = {
     "aicdf_last_error": (C.c_char_p, []),
     "aicdf_table_const_create": (status, [u32, i32, i32, C.POINTER(vp)]),
     "aicdf_table_dyadic_create": (status, [u32, u32, i32, C.POINTER(vp)]),
+    "aicdf_table_geometric_create": (status, [dbl, u32, u32, i32, C.POINTER(vp)]),
+    "aicdf_table_geometric_host": (status, [dbl, u32, u32, i32, dptr, sz]),
     "aicdf_table_const_values": (status, [u32, dptr, i32, C.POINTER(vp)]),
     "aicdf_table_coeffs": (status, [vp, dptr, sz, C.POINTER(u32), C.POINTER(u32)]),
     "aicdf_table_destroy": (None, [vp]),

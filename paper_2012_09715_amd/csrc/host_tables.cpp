@@ -190,6 +190,68 @@ std::vector<double> build_dyadic_table(uint32_t T, uint32_t degree) {
   return tab;
 }
 
+// Theorem 2.5's bounds for decay rate r: b_0 = 1/2, b_k = b_(k-1) r by FP64
+// multiplication, each rounded to FP32 (the thresholds that decide the row).
+std::vector<double> geometric_thresholds(double r, uint32_t T) {
+  std::vector<double> B(T);
+  double b = 0.5;
+  for (uint32_t k = 0; k < T; ++k) {
+    B[k] = double(float(b));
+    b *= r;
+  }
+  return B;
+}
+
+// L2 fits on I_e = [B_e, B_(e-1)) (e < T-1) and the singular (0, B_(T-2)).
+// The projection is taken in the Legendre basis of the interval (x = (2u - a
+// - b)/(b - a) on [-1, 1]; diagonal Gram matrix (b - a)/(2i + 1)), moments by
+// quadrature in z = Phi^-1(u) as for the dyadic rows, and the result is then
+// written in powers of s = u / B_e.  The monomial normal equations would lose
+// most digits for r near 1, where [1, 1/r) is short.
+std::vector<double> build_geometric_table(double r, uint32_t T, uint32_t degree) {
+  const int d1 = int(degree) + 1;
+  const std::vector<double> B = geometric_thresholds(r, T);
+  std::vector<double> tab(size_t(T) * d1, 0.0);
+  for (uint32_t e = 1; e < T; ++e) {
+    const bool singular = (e == T - 1);
+    const double b = B[e - 1], a = singular ? 0.0 : B[e], h = B[e];
+    const double w = b - a;
+    const double zb = host_Phi_inv(b);
+    const double za = singular ? zb - 14.0 : host_Phi_inv(a);
+    const int panels = singular ? 112 : 16;
+    double leg[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < d1; ++i) {
+      auto f = [&](double z) {
+        const double x = (2.0 * host_Phi(z) - a - b) / w;
+        double p0 = 1.0, p1 = x;  // Bonnet's recurrence for P_i(x)
+        for (int k = 1; k < i; ++k) {
+          const double p2 = ((2 * k + 1) * x * p1 - k * p0) / (k + 1);
+          p0 = p1;
+          p1 = p2;
+        }
+        return (i == 0 ? p0 : p1) * z * host_phi(z);
+      };
+      leg[i] = (2 * i + 1) / w * integrate_z(f, za, zb, panels);
+    }
+    // Legendre series -> powers of x (P_2 = (3x^2 - 1)/2, P_3 = (5x^3 - 3x)/2)
+    const double px[4] = {leg[0] - 0.5 * leg[2], leg[1] - 1.5 * leg[3], 1.5 * leg[2], 2.5 * leg[3]};
+    // powers of x -> powers of s by Horner's rule in the linear map x = alpha s + beta
+    const double alpha = 2.0 * h / w, beta = -(a + b) / w;
+    double cs[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = d1 - 1; k >= 0; --k) {
+      double nx[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int j = 0; j < d1; ++j) {
+        nx[j] += beta * cs[j];
+        if (j + 1 < d1) nx[j + 1] += alpha * cs[j];
+      }
+      nx[0] += px[k];
+      for (int j = 0; j < d1; ++j) cs[j] = nx[j];
+    }
+    for (int j = 0; j < d1; ++j) tab[size_t(e) * d1 + j] = cs[j];
+  }
+  return tab;
+}
+
 // Round to nearest even into the given dtype (single rounding from FP64).
 static double round_bits(double x, int keep_bits, int min_exp) {
   // keep_bits significant bits; values below 2^min_exp keep the fixed spacing
@@ -235,10 +297,18 @@ static aicdf_status upload_table(aicdf_table* t) {
     src = f32.data();
     t->dev_bytes = f32.size() * 4;
   } else {
-    // 64 rows of four floats (zero padded): one row per lane of a wave
-    f32.assign(size_t(64) * 4, 0.0f);
+    // 64 rows of four floats (zero padded): one row per lane of a wave;
+    // geometric tables append 64 thresholds and 64 scales
+    f32.assign(size_t(64) * (t->kind == 2 ? 6 : 4), 0.0f);
     for (uint32_t r = 0; r < t->rows; ++r)
       for (uint32_t c = 0; c < t->cols; ++c) f32[r * 4 + c] = float(t->host[size_t(r) * t->cols + c]);
+    if (t->kind == 2) {
+      const std::vector<double> B = geometric_thresholds(t->r, t->rows);
+      for (uint32_t e = 0; e < t->rows; ++e) {
+        f32[256 + e] = float(B[e]);
+        f32[320 + e] = float(1.0 / B[e]);
+      }
+    }
     src = f32.data();
     t->dev_bytes = f32.size() * 4;
   }
@@ -332,6 +402,58 @@ extern "C" aicdf_status aicdf_table_dyadic_create(uint32_t n_entries, uint32_t d
     return st;
   }
   *out = t;
+  return ok();
+}
+
+static aicdf_status check_geometric(double r, uint32_t n_entries, uint32_t degree, aicdf_dtype coef_t,
+                                    bool allow_f64) {
+  if (!(r >= 0.05) || !(r <= 0.95)) return fail(AICDF_EINVAL, "decay rate r must be in [0.05, 0.95]");
+  if (n_entries < 3 || n_entries > 64)
+    return fail(AICDF_EINVAL, "n_entries must be in [3, 64], got %u", n_entries);
+  if (degree > 3) return fail(AICDF_EINVAL, "degree must be in [0, 3], got %u", degree);
+  if (coef_t != AICDF_F32 && coef_t != AICDF_F16 && coef_t != AICDF_BF16 && !(allow_f64 && coef_t == AICDF_F64))
+    return fail(AICDF_EDTYPE, "geometric coefficients must be F32, F16 or BF16");
+  // every threshold a normal FP32 number: the rows stay strictly ordered and
+  // their scales 1 / B_e finite
+  if (!(geometric_thresholds(r, n_entries).back() >= 0x1p-126))
+    return fail(AICDF_EINVAL, "r^(n_entries-1) / 2 underflows FP32 (r = %g, n_entries = %u)", r, n_entries);
+  return AICDF_OK;
+}
+
+extern "C" aicdf_status aicdf_table_geometric_create(double r, uint32_t n_entries, uint32_t degree,
+                                                     aicdf_dtype coef_t, aicdf_table** out) {
+  if (!out) return fail(AICDF_EINVAL, "out is NULL");
+  *out = nullptr;
+  aicdf_status st = check_geometric(r, n_entries, degree, coef_t, false);
+  if (st != AICDF_OK) return st;
+  auto* t = new (std::nothrow) aicdf_table();
+  if (!t) return fail(AICDF_ENOMEM, "host allocation failed");
+  t->kind = 2;
+  t->rows = n_entries;
+  t->cols = degree + 1;
+  t->construction = 0;
+  t->coef_t = coef_t;
+  t->dev = nullptr;
+  t->r = r;
+  t->host = build_geometric_table(r, n_entries, degree);
+  for (auto& v : t->host) v = round_to_dtype(v, coef_t);
+  st = upload_table(t);
+  if (st != AICDF_OK) {
+    delete t;
+    return st;
+  }
+  *out = t;
+  return ok();
+}
+
+extern "C" aicdf_status aicdf_table_geometric_host(double r, uint32_t n_entries, uint32_t degree, aicdf_dtype coef_t,
+                                                   double* host_out, size_t cap) {
+  aicdf_status st = check_geometric(r, n_entries, degree, coef_t, true);
+  if (st != AICDF_OK) return st;
+  if (!host_out) return fail(AICDF_EINVAL, "host_out is NULL");
+  const std::vector<double> v = build_geometric_table(r, n_entries, degree);
+  if (cap < v.size()) return fail(AICDF_ERANGE, "cap %zu < %zu coefficients", cap, v.size());
+  for (size_t i = 0; i < v.size(); ++i) host_out[i] = round_to_dtype(v[i], coef_t);
   return ok();
 }
 

@@ -52,6 +52,8 @@ double host_phi(double z);
 double host_Phi_inv(double u);
 std::vector<double> build_const_table(uint32_t n, int construction);
 std::vector<double> build_dyadic_table(uint32_t n_entries, uint32_t degree);
+std::vector<double> geometric_thresholds(double r, uint32_t n_entries);
+std::vector<double> build_geometric_table(double r, uint32_t n_entries, uint32_t degree);
 double round_to_dtype(double x, aicdf_dtype t);
 // n-point Gauss-Legendre rule on [-1, 1]; small dense solve (n <= 4, A and b overwritten, b := A^-1 b).
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
@@ -76,11 +78,13 @@ Chi2Info chi2_info(const aicdf_chi2_table* t);
 
 // A coefficient table: host FP64 copy of the stored (dtype-rounded) values
 // and a device copy.  Dyadic tables are stored on the device as 64 FP32 rows
-// of four (c0..c3; rows and columns beyond the table are zero); constant
+// of four (c0..c3; rows and columns beyond the table are zero); geometric
+// tables likewise, followed by 64 FP32 row thresholds B_e and 64 FP32 scales
+// 1/B_e (zero beyond the table); constant
 // tables as FP32, or FP64 when coef_t is F64.  FP16/BF16 coefficients are exactly representable in FP32, so the
 // device copy holds the rounded values without further error.
 struct aicdf_table {
-  int kind;  // 0 constant, 1 dyadic
+  int kind;  // 0 constant, 1 dyadic, 2 geometric (decay rate r)
   uint32_t rows, cols;
   int construction;
   aicdf_dtype coef_t;
@@ -88,4 +92,5 @@ struct aicdf_table {
   std::vector<double> host;  // rows x cols, rounded to coef_t
   void* dev;                 // device copy (see above)
   size_t dev_bytes;
+  double r;                  // geometric tables: decay rate
 };

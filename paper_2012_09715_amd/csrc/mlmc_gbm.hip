@@ -34,8 +34,10 @@ struct GbmArgs {
   uint32_t level, nsteps;
   uint64_t n_paths, path_offset;
   uint32_t k0, k1, tag;
-  const float* table;  // dyadic: 64 rows x 4 floats; constant: rows floats
+  const float* table;  // dyadic: 64 rows x 4 floats; geometric: the same, then
+                       // 64 thresholds and 64 scales; constant: rows floats
   uint32_t rows;
+  float inv_log2r;     // geometric: 1 / log2(r)
   int table_in_lds;
   uint32_t sparse;     // 1: one path per wavefront (2^l >= 128)
 };
@@ -68,8 +70,24 @@ __device__ __forceinline__ Lt2 lt2_wave_product(Lt2 m, int lane) {
 // rows are zero-padded to four coefficients, so one cubic Horner pass gives
 // the exact result of every degree.
 template <int TAB>
-__device__ __forceinline__ float approx_normal(float u, const float* tab, uint32_t rows) {
-  if constexpr (TAB == 0) {
+__device__ __forceinline__ float approx_normal(float u, const float* tab, uint32_t rows, float inv_log2r) {
+  if constexpr (TAB == 2) {
+    // geometric rows (Theorem 2.5): ceil(log2(2t) / log2(r) - 1/64) is the
+    // row or the one before it, one comparison with the FP32 threshold B_e
+    // decides, then s = t / B_e; the same arithmetic as the streaming
+    // transform
+    const bool p = u < 0.5f;
+    const float t = p ? u : 1.0f - u;
+    const float t2 = 2.0f * t;
+    const float x = __log2f(t2 < 0x1p-126f ? 0x1p-126f : t2) * inv_log2r;
+    int e = int(fminf(fmaxf(ceilf(x - 0x1p-6f), 1.0f), float(rows - 1)));
+    if (e < int(rows) - 1 && t < tab[256 + e]) ++e;
+    if (t >= 0.5f) e = 0;
+    const float s = t * tab[320 + e];
+    const f32x4 c = reinterpret_cast<const f32x4*>(tab)[e];
+    float z = fmaf(fmaf(fmaf(c[3], s, c[2]), s, c[1]), s, c[0]);
+    return p ? z : -z;
+  } else if constexpr (TAB == 0) {
     const bool p = u < 0.5f;
     const float ur = p ? u : 1.0f - u;
     const uint32_t e = min(126u - (__float_as_uint(ur) >> 23), rows - 1u);
@@ -119,7 +137,7 @@ __device__ __forceinline__ void gbm_chunk(const GbmArgs& a, const float* tab, ui
     float dWprev = 0.0f;
     for (uint32_t n = n0; n < n1; ++n) {
       if ((n & 3u) == 0 || n == n0) w = philox4x32_10(n >> 2, plo, phi, a.tag, a.k0, a.k1);
-      const float dW = a.sqrt_dt * approx_normal<TAB>(u24_from_word(w[n & 3u]), tab, a.rows);
+      const float dW = a.sqrt_dt * approx_normal<TAB>(u24_from_word(w[n & 3u]), tab, a.rows, a.inv_log2r);
       f.a = fmaf(f.a, increment<SCHEME>(a, dW, a.dt, a.r_dt), f.a);
       if (n & 1u)
         c.a = fmaf(c.a, increment<SCHEME>(a, dWprev + dW, 2.0f * a.dt, a.r_2dt), c.a);
@@ -142,7 +160,7 @@ __device__ __forceinline__ void gbm_chunk(const GbmArgs& a, const float* tab, ui
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const double Z = exact_phi_inv(u53_from_words(w[2 * h], w[2 * h + 1]));
-        const float Zt = approx_normal<TAB>(u24_from_word(w[2 * h]), tab, a.rows);
+        const float Zt = approx_normal<TAB>(u24_from_word(w[2 * h]), tab, a.rows, a.inv_log2r);
         const float dWh = float(Z * a.sqrt_dt_d);
         const float dWt = a.sqrt_dt * Zt;
         const float d = float((Z - double(Zt)) * a.sqrt_dt_d);
@@ -174,7 +192,7 @@ __global__ __launch_bounds__(kLevelBlock) void gbm_level_kernel(GbmArgs a, doubl
   const float* tab = a.table;
   if (KIND != AICDF_KIND_EXACT && a.table_in_lds) {
     float* l = reinterpret_cast<float*>(lds4);
-    const uint32_t nf = TAB == 0 ? 64u * 4u : a.rows;
+    const uint32_t nf = TAB == 0 ? 64u * 4u : TAB == 2 ? 64u * 6u : a.rows;
     for (uint32_t i = threadIdx.x; i < nf; i += kLevelBlock) l[i] = a.table[i];
     __syncthreads();
     tab = l;
@@ -233,7 +251,7 @@ __global__ __launch_bounds__(kLevelBlock) void gbm_level_kernel(GbmArgs a, doubl
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           if (b * 4 + q < nf) {
-            const float dW = a.sqrt_dt * approx_normal<TAB>(u24_from_word(w[q]), tab, a.rows);
+            const float dW = a.sqrt_dt * approx_normal<TAB>(u24_from_word(w[q]), tab, a.rows, a.inv_log2r);
             Xf = fmaf(Xf, increment<SCHEME>(a, dW, a.dt, a.r_dt), Xf);
             if (q & 1) {
               Xc = fmaf(Xc, increment<SCHEME>(a, dWprev + dW, 2.0f * a.dt, a.r_2dt), Xc);
@@ -271,7 +289,7 @@ __global__ __launch_bounds__(kLevelBlock) void gbm_level_kernel(GbmArgs a, doubl
         for (int h = 0; h < 2; ++h) {
           if (b * 2 + h < nf) {
             const double Z = exact_phi_inv(u53_from_words(w[2 * h], w[2 * h + 1]));
-            const float Zt = approx_normal<TAB>(u24_from_word(w[2 * h]), tab, a.rows);
+            const float Zt = approx_normal<TAB>(u24_from_word(w[2 * h]), tab, a.rows, a.inv_log2r);
             const float dWh = float(Z * a.sqrt_dt_d);
             const float dWt = a.sqrt_dt * Zt;
             const float d = float((Z - double(Zt)) * a.sqrt_dt_d);
@@ -324,6 +342,8 @@ template <int KIND, int SCHEME, int PAYOFF>
 void launch_tab(int tab, const GbmArgs& a, unsigned grid, size_t lds, hipStream_t s, double* p, double* po) {
   if (tab == 0)
     launch<KIND, SCHEME, PAYOFF, 0>(a, grid, lds, s, p, po);
+  else if (tab == 2)
+    launch<KIND, SCHEME, PAYOFF, 2>(a, grid, lds, s, p, po);
   else
     launch<KIND, SCHEME, PAYOFF, 1>(a, grid, lds, s, p, po);
 }
@@ -384,12 +404,13 @@ extern "C" aicdf_status mlmc_level_gbm(const aicdf_gbm_params* prm, uint32_t lev
   int tab = 0;
   size_t lds = 0;
   if (kind != AICDF_KIND_EXACT) {
-    tab = approx->kind == 1 ? 0 : 1;
+    tab = approx->kind == 1 ? 0 : approx->kind == 2 ? 2 : 1;
+    if (tab == 2) a.inv_log2r = float(1.0 / std::log2(approx->r));
     if (tab == 1 && approx->coef_t == AICDF_F64)
       return fail(AICDF_EDTYPE, "the fused levels use FP32 arithmetic: the constant table must not be F64");
     a.table = static_cast<const float*>(approx->dev);
     a.rows = approx->rows;
-    const size_t bytes = tab == 0 ? 64 * 16 : size_t(approx->rows) * 4;
+    const size_t bytes = tab == 0 ? 64 * 16 : tab == 2 ? 64 * 24 : size_t(approx->rows) * 4;
     a.table_in_lds = bytes <= 64 * 1024;
     lds = a.table_in_lds ? bytes : 0;
   }

@@ -163,6 +163,60 @@ struct DyadicF64 {
   }
 };
 
+// Geometric intervals with decay rate r (Theorem 2.5): lane l also holds the
+// row threshold B_l (row e covers [B_e, B_(e-1)), the singular last row
+// (0, B_(T-2))) and the scale 1/B_l of the local variable s = t / B_e.  The
+// row coordinate x = log2(2t) / log2(r) puts row e at x in (e-1, e]; its
+// FP32 estimate is within 1e-3 of the value the FP32 thresholds imply (log2
+// error a few ulps of |log2 t| <= 127, |1/log2 r| <= 14), so ceil(x - 1/64)
+// is the row or the one before it, and a single comparison with that row's
+// lower threshold decides: the row is exact, the logarithm only narrows it.
+template <int DEG>
+struct GeometricLane {
+  float c[DEG + 1];
+  float thr, inv;
+};
+
+template <int DEG>
+struct GeometricF32 {
+  const f32x4* tab;  // 64 rows of four coefficients, then 64 thresholds, then 64 scales
+  uint32_t rows;
+  float inv_log2r;   // 1 / log2(r)
+  using In = float;
+  using Acc = float;
+  using Lane = GeometricLane<DEG>;
+  __device__ Lane prep() const {
+    const DyadicLane<DEG> d = dyadic_prep<DEG>(tab, rows);
+    Lane L;
+#pragma unroll
+    for (int j = 0; j <= DEG; ++j) L.c[j] = d.c[j];
+    const float* extra = reinterpret_cast<const float*>(tab + 64);
+    L.thr = extra[__lane_id()];
+    L.inv = extra[64 + __lane_id()];
+    return L;
+  }
+  __device__ __forceinline__ uint32_t row(float t, const Lane& L) const {
+    // subnormal t: estimate from the least normal number (a NaN passes)
+    const float t2 = 2.0f * t;
+    const float x = __log2f(t2 < 0x1p-126f ? 0x1p-126f : t2) * inv_log2r;
+    int e = int(fminf(fmaxf(ceilf(x - 0x1p-6f), 1.0f), float(rows - 1)));  // NaN -> 1
+    const float lo = row_coef(uint32_t(e), L.thr);  // lower bound of row e
+    if (e < int(rows) - 1 && t < lo) ++e;
+    return t >= 0.5f ? 0u : uint32_t(e);
+  }
+  __device__ __forceinline__ float eval(float u, const Lane& L) const {
+    const bool p = u < 0.5f;
+    const float t = p ? u : 1.0f - u;
+    const uint32_t e = row(t, L);
+    const float s = t * row_coef(e, L.inv);
+    float z = row_coef(e, L.c[DEG]);
+    if (DEG == 0) z = fmaf(0.0f, s, z);
+#pragma unroll
+    for (int j = DEG - 1; j >= 0; --j) z = fmaf(z, s, row_coef(e, L.c[j]));
+    return p ? z : -z;
+  }
+};
+
 struct NoLane {};
 
 // Constant table with FP32 entries: gathered through the vector L1/L2 (the
@@ -314,13 +368,24 @@ aicdf_status check_table_device(const aicdf_table* t) {
 extern "C" aicdf_status approx_icdf_linear(const aicdf_table* t, size_t n, const void* u,
                                            aicdf_dtype u_t, void* z, aicdf_dtype z_t, void* stream) {
   if (!t) return fail(AICDF_EINVAL, "table is NULL");
-  if (t->kind != 1) return fail(AICDF_EINVAL, "approx_icdf_linear needs a dyadic table");
+  if (t->kind != 1 && t->kind != 2)
+    return fail(AICDF_EINVAL, "approx_icdf_linear needs a dyadic or geometric table");
   aicdf_status st = check_io(n, u, u_t, z, z_t);
   if (st != AICDF_OK || n == 0) return st == AICDF_OK ? ok() : st;
   if ((st = check_table_device(t)) != AICDF_OK) return st;
   auto s = static_cast<hipStream_t>(stream);
   const auto* tab = static_cast<const f32x4*>(t->dev);
   const int deg = int(t->cols) - 1;
+  if (t->kind == 2) {
+    if (u_t != AICDF_F32) return fail(AICDF_EDTYPE, "geometric tables take F32 input");
+    const float il = float(1.0 / std::log2(t->r));
+    switch (deg) {
+      case 0: return dispatch_out(u, z, z_t, n, GeometricF32<0>{tab, t->rows, il}, s);
+      case 1: return dispatch_out(u, z, z_t, n, GeometricF32<1>{tab, t->rows, il}, s);
+      case 2: return dispatch_out(u, z, z_t, n, GeometricF32<2>{tab, t->rows, il}, s);
+      default: return dispatch_out(u, z, z_t, n, GeometricF32<3>{tab, t->rows, il}, s);
+    }
+  }
   if (u_t == AICDF_F32) {
     switch (deg) {
       case 0: return dispatch_out(u, z, z_t, n, DyadicF32<0>{tab, t->rows}, s);
@@ -381,6 +446,21 @@ __global__ __launch_bounds__(kBlock) void index_kernel(const InT* __restrict__ u
 }
 }  // namespace
 
+namespace {
+// Rows of a geometric table, one wave per 64 consecutive inputs (all lanes
+// take part in the cross-lane threshold reads; lanes past n use t = 1/4).
+__global__ __launch_bounds__(kStreamBlock) void geometric_index_kernel(const float* __restrict__ u,
+                                                                       uint32_t* __restrict__ idx, size_t n,
+                                                                       GeometricF32<0> op) {
+  const GeometricLane<0> L = op.prep();
+  const size_t i = size_t(blockIdx.x) * kStreamBlock + threadIdx.x;
+  const float x = i < n ? u[i] : 0.25f;
+  const float t = x < 0.5f ? x : 1.0f - x;
+  const uint32_t r = op.row(t, L);
+  if (i < n) idx[i] = r;
+}
+}  // namespace
+
 extern "C" aicdf_status approx_icdf_index(const aicdf_table* t, size_t n, const void* u, aicdf_dtype u_t,
                                           uint32_t* idx, void* stream) {
   if (!t) return fail(AICDF_EINVAL, "table is NULL");
@@ -388,6 +468,20 @@ extern "C" aicdf_status approx_icdf_index(const aicdf_table* t, size_t n, const 
   if (st != AICDF_OK || n == 0) return st == AICDF_OK ? ok() : st;
   if (u_t != AICDF_F32 && u_t != AICDF_F64) return fail(AICDF_EDTYPE, "input dtype must be F32 or F64");
   if ((st = check_table_device(t)) != AICDF_OK) return st;
+  if (t->kind == 2) {
+    if (u_t != AICDF_F32) return fail(AICDF_EDTYPE, "geometric tables take F32 input");
+    const GeometricF32<0> op{static_cast<const f32x4*>(t->dev), t->rows, float(1.0 / std::log2(t->r))};
+    const size_t blocks = (n + kStreamBlock - 1) / kStreamBlock;
+    for (size_t b0 = 0; b0 < blocks; b0 += size_t(1) << 30) {
+      const size_t nb = std::min(blocks - b0, size_t(1) << 30);
+      const size_t first = b0 * kStreamBlock;
+      hipLaunchKernelGGL(geometric_index_kernel, dim3(unsigned(nb)), dim3(kStreamBlock), 0,
+                         static_cast<hipStream_t>(stream), static_cast<const float*>(u) + first, idx + first,
+                         n - first, op);
+    }
+    AICDF_HIP(hipGetLastError());
+    return ok();
+  }
   const size_t need = (n + kBlock - 1) / kBlock;
   const size_t maxg = size_t(num_cus()) * 16;
   const unsigned grid = unsigned(need < maxg ? need : maxg);

@@ -244,6 +244,8 @@ def bench_summary(log=print, seed=20201217, large_paths=1e8):
                      16-row linear dyadic table (FP32)
       gbm_em_rademacher  the same with Rademacher variables (Table 3's
                      "too crude" comparator)
+      gbm_em_geometric  the same with a cubic table on geometric intervals,
+                     r = 0.7, 64 rows (Theorem 2.5 with r != 1/2)
       gbm_milstein   the same with the Milstein scheme, levels 0..10
       cir            CIR time average, levels 0..6, trained BF16 surrogate
       cir_poly1/3    the same with Section 5.1's piecewise linear / cubic
@@ -261,6 +263,9 @@ def bench_summary(log=print, seed=20201217, large_paths=1e8):
     log("mlmc: GBM Euler-Maruyama, levels 0..8, Rademacher variables")
     res["gbm_em_rademacher"] = nested_mlmc("gbm", GBM_CALL, 8, 1e-3, A.Table.rademacher(), seed + 6)
     log(f"  formula speedup {res['gbm_em_rademacher']['formula_speedup']:.3f}")
+    log("mlmc: GBM Euler-Maruyama, levels 0..8, geometric cubic table r = 0.7")
+    res["gbm_em_geometric"] = nested_mlmc("gbm", GBM_CALL, 8, 1e-3, A.Table.geometric(0.7, 64, 3), seed + 7)
+    log(f"  formula speedup {res['gbm_em_geometric']['formula_speedup']:.3f}")
     log("mlmc: GBM Milstein, levels 0..10")
     res["gbm_milstein"] = nested_mlmc("gbm", dict(GBM_CALL, scheme=1), 10, 1e-3, lin16, seed + 1)
     log(f"  formula speedup {res['gbm_milstein']['formula_speedup']:.3f}")

@@ -142,3 +142,43 @@ def test_const_values_argument_errors():
     assert lib.aicdf_table_const_values(4, vals, 9, C.byref(h)) == -2
     bad = (C.c_double * 2)(1.0, float("nan"))
     assert lib.aicdf_table_const_values(2, bad, 1, C.byref(h)) == -1
+
+
+@pytest.mark.parametrize("r,T", [(0.5, 16), (0.3, 40), (0.7, 64), (0.95, 64)])
+@pytest.mark.parametrize("d", [0, 1, 3])
+def test_host_geometric_fit_matches_oracle(r, T, d):
+    # compared as functions on each row: for r near 1 the monomial basis in
+    # s on [1, 1/r) is ill-conditioned, so two accurate fits can differ in
+    # their coefficients while agreeing as polynomials
+    lib64 = A.geometric_host_coeffs(r, T, d, torch.float64).numpy()
+    ref = tables.geometric_table(r, T, d)
+    for e in range(1, T):
+        a, b, h = tables.geometric_interval(e, r, T)
+        s = np.linspace(a / h, b / h, 17)
+        assert np.allclose(np.polyval(lib64[e][::-1], s), np.polyval(ref[e][::-1], s), rtol=0, atol=1e-10), e
+    if r == 0.5:
+        # the dyadic builder solves the monomial normal equations (~1e-10 for cubics)
+        assert np.allclose(lib64, A.table_host_coeffs("dyadic", T, d, torch.float64).numpy(), rtol=1e-9, atol=1e-9)
+    for dt, name in ((torch.float32, "f32"), (torch.bfloat16, "bf16")):
+        assert np.array_equal(A.geometric_host_coeffs(r, T, d, dt).numpy(), ROUND[name](lib64))
+
+
+def test_host_geometric_argument_errors():
+    buf = (C.c_double * 256)()
+    f = lib.aicdf_table_geometric_host
+    assert f(0.04, 16, 1, 1, buf, 256) == -1      # r below 0.05
+    assert f(0.96, 16, 1, 1, buf, 256) == -1      # r above 0.95
+    assert f(float("nan"), 16, 1, 1, buf, 256) == -1
+    assert f(0.7, 2, 1, 1, buf, 256) == -1        # n_entries below 3
+    assert f(0.7, 65, 1, 1, buf, 256) == -1       # above 64
+    assert f(0.7, 16, 4, 1, buf, 256) == -1       # degree 4
+    assert f(0.05, 30, 1, 1, buf, 256) == -1      # r^29 / 2 below the FP32 normal range
+    assert "underflows" in lib.aicdf_last_error().decode()
+    assert f(0.05, 29, 1, 1, buf, 256) == 0
+    assert f(0.7, 16, 1, 9, buf, 256) == -2       # bad dtype
+    assert f(0.7, 16, 1, 1, buf, 31) == -6        # cap too small
+    assert f(0.7, 16, 1, 1, None, 32) == -1
+    h = C.c_void_p()
+    assert lib.aicdf_table_geometric_create(0.7, 16, 1, 0, C.byref(h)) == -2  # F64 tables not stored
+    assert lib.aicdf_table_geometric_create(0.99, 16, 1, 1, C.byref(h)) == -1
+    assert not h.value
