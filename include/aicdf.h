@@ -271,7 +271,11 @@ typedef struct {
  * the high word drives the approximate path).
  * out: host, receives the sums.  path_out: optional device buffer of
  * n_paths x 3 doubles (Y, P_f, P_c per path) or NULL.
- * Synchronises `stream`.  Errors: EINVAL, ERANGE, EHIP, ENOMEM. */
+ * Synchronises `stream`.  The library keeps one small workspace (~200 KB of
+ * device memory) per (device, stream) that a level call has used, until the
+ * process ends: level calls (GBM and CIR) on different streams, from
+ * different host threads, run concurrently; calls on one stream are
+ * serialised.  Errors: EINVAL, ERANGE, EHIP, ENOMEM. */
 aicdf_status mlmc_level_gbm(const aicdf_gbm_params* params, uint32_t level, uint64_t n_paths,
                             int32_t kind, const aicdf_table* approx, uint64_t seed,
                             uint64_t path_offset, aicdf_level_sums* out, double* path_out,

@@ -345,11 +345,11 @@ extern "C" aicdf_status mlmc_level_cir(const aicdf_cir_params* prm, uint32_t lev
   a.hi = float(hi);
   a.inv_span2 = sur ? float(2.0 / (hi - lo)) : 0.0f;
 
-  std::lock_guard<std::mutex> lock(level_mutex());
-  Workspace* ws = nullptr;
-  st = get_workspace(&ws);
-  if (st != AICDF_OK) return st;
   auto s = static_cast<hipStream_t>(stream);
+  Workspace* ws = nullptr;
+  st = get_workspace(s, &ws);
+  if (st != AICDF_OK) return st;
+  std::lock_guard<std::mutex> lock(ws->mu);
   const float* p = sur ? surrogate_params(sur) : nullptr;
   const uint16_t* w2 = sur ? surrogate_w2b(sur) : nullptr;
   const f32x4* wt = sur ? reinterpret_cast<const f32x4*>(surrogate_wtab(sur)) : nullptr;
@@ -390,11 +390,11 @@ extern "C" aicdf_status mlmc_level_cir_table(const aicdf_cir_params* prm, uint32
     lds = size_t(a.table_rows) * sizeof(f32x4);
   }
 
-  std::lock_guard<std::mutex> lock(level_mutex());
-  Workspace* ws = nullptr;
-  st = get_workspace(&ws);
-  if (st != AICDF_OK) return st;
   auto s = static_cast<hipStream_t>(stream);
+  Workspace* ws = nullptr;
+  st = get_workspace(s, &ws);
+  if (st != AICDF_OK) return st;
+  std::lock_guard<std::mutex> lock(ws->mu);
   const auto* wt = static_cast<const f32x4*>(ti.dev_rows);
   AICDF_HIP(hipMemsetAsync(ws->counter, 0, sizeof(unsigned long long), s));
   AICDF_HIP(hipEventRecord(ws->ev0, s));
@@ -419,11 +419,11 @@ extern "C" aicdf_status mlmc_level_cir_em(const aicdf_cir_params* prm, uint32_t 
     *out = aicdf_level_sums{};
     return ok();
   }
-  std::lock_guard<std::mutex> lock(level_mutex());
-  Workspace* ws = nullptr;
-  st = get_workspace(&ws);
-  if (st != AICDF_OK) return st;
   auto s = static_cast<hipStream_t>(stream);
+  Workspace* ws = nullptr;
+  st = get_workspace(s, &ws);
+  if (st != AICDF_OK) return st;
+  std::lock_guard<std::mutex> lock(ws->mu);
   AICDF_HIP(hipMemsetAsync(ws->counter, 0, sizeof(unsigned long long), s));
   AICDF_HIP(hipEventRecord(ws->ev0, s));
   launch_kind<APX_EM>(kind, prm->functional, a, grid, 0, s, nullptr, nullptr, nullptr, ws->partials, path_out,
@@ -443,11 +443,11 @@ extern "C" aicdf_status mlmc_level_cir_sankaran(const aicdf_cir_params* prm, uin
     *out = aicdf_level_sums{};
     return ok();
   }
-  std::lock_guard<std::mutex> lock(level_mutex());
-  Workspace* ws = nullptr;
-  st = get_workspace(&ws);
-  if (st != AICDF_OK) return st;
   auto s = static_cast<hipStream_t>(stream);
+  Workspace* ws = nullptr;
+  st = get_workspace(s, &ws);
+  if (st != AICDF_OK) return st;
+  std::lock_guard<std::mutex> lock(ws->mu);
   AICDF_HIP(hipMemsetAsync(ws->counter, 0, sizeof(unsigned long long), s));
   AICDF_HIP(hipEventRecord(ws->ev0, s));
   launch_kind<APX_SANKARAN>(kind, prm->functional, a, grid, 0, s, nullptr, nullptr, nullptr, ws->partials, path_out,

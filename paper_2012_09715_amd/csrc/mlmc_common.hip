@@ -1,4 +1,4 @@
-// Per-device workspace, the deterministic final pass over the per-block level
+// Per-stream workspaces, the deterministic final pass over the per-block level
 // partials, and the optimal allocation of the nested estimator.
 #include <cmath>
 #include <map>
@@ -32,20 +32,16 @@ __global__ __launch_bounds__(kLevelBlock) void reduce_partials_kernel(const doub
 }
 
 std::mutex g_ws_mutex;
-std::map<int, Workspace*> g_ws;
+std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
 
 }  // namespace
 
-std::mutex& level_mutex() {
-  static std::mutex m;
-  return m;
-}
-
-aicdf_status get_workspace(Workspace** out) {
+aicdf_status get_workspace(hipStream_t s, Workspace** out) {
   int dev = 0;
   AICDF_HIP(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lock(g_ws_mutex);
-  auto it = g_ws.find(dev);
+  const auto key = std::make_pair(dev, s);
+  auto it = g_ws.find(key);
   if (it != g_ws.end()) {
     *out = it->second;
     return AICDF_OK;
@@ -60,7 +56,7 @@ aicdf_status get_workspace(Workspace** out) {
   }
   AICDF_HIP(hipEventCreate(&ws->ev0));
   AICDF_HIP(hipEventCreate(&ws->ev1));
-  g_ws[dev] = ws;
+  g_ws[key] = ws;
   *out = ws;
   return AICDF_OK;
 }

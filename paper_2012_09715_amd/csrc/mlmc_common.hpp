@@ -55,17 +55,20 @@ __device__ __forceinline__ void block_reduce_store(const LevelAcc& acc, double* 
   if (threadIdx.x < kSums) partials[size_t(blockIdx.x) * kSums + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// Host side: one workspace per device (grown on demand, freed at exit), and
-// the final pass over the partials.
+// Host side: one workspace per (device, stream) a level call has used
+// (created on first use, kept until the process ends), so that calls on
+// different streams can run concurrently; a call holds its workspace's mutex
+// from the first launch to the copy-out, which serialises calls that share a
+// stream.  Also the final pass over the partials.
 struct Workspace {
   double* partials = nullptr;  // kMaxLevelBlocks * kSums doubles
   double* result = nullptr;    // kSums doubles
   unsigned long long* counter = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::mutex mu;
 };
 
-aicdf_status get_workspace(Workspace** ws);
-std::mutex& level_mutex();
+aicdf_status get_workspace(hipStream_t s, Workspace** ws);
 
 aicdf_status finish_level(Workspace* ws, unsigned nblocks, hipStream_t s, double n_paths,
                           aicdf_level_sums* out);

@@ -419,11 +419,11 @@ extern "C" aicdf_status mlmc_level_gbm(const aicdf_gbm_params* prm, uint32_t lev
   const uint64_t need = (n_paths + per_block - 1) / per_block;
   const unsigned grid = unsigned(need < uint64_t(kMaxLevelBlocks) ? need : kMaxLevelBlocks);
 
-  std::lock_guard<std::mutex> lock(level_mutex());
-  Workspace* ws = nullptr;
-  aicdf_status st = get_workspace(&ws);
-  if (st != AICDF_OK) return st;
   auto s = static_cast<hipStream_t>(stream);
+  Workspace* ws = nullptr;
+  aicdf_status st = get_workspace(s, &ws);
+  if (st != AICDF_OK) return st;
+  std::lock_guard<std::mutex> lock(ws->mu);
   AICDF_HIP(hipMemsetAsync(ws->counter, 0, sizeof(unsigned long long), s));
   AICDF_HIP(hipEventRecord(ws->ev0, s));
   if (kind == AICDF_KIND_EXACT)

@@ -12,11 +12,20 @@ level the driver
      (mlmc_allocate: T^, T~, m^_l, m~_l, M~_l),
   3. runs the allocated path counts (continuing each stream after the pilot
      paths) and forms the estimators and their measured device times.
-The speed-up is reported two ways: T^/T~ from the cost formula with the
-measured (v, c), and the ratio of the measured device times of the two
-estimators at the same target RMSE.
+The speed-up is reported three ways: T^/T~ from the cost formula with the
+measured (v, c); the ratio of the summed device times of the two estimators'
+level calls at the same target RMSE, run one after another; and the ratio of
+their wall-clock times when each estimator's level calls run concurrently on
+a few streams (the latency-bound high levels, a few hundred paths of 2^l
+serial steps each, then overlap instead of adding up).  The concurrent pass
+repeats the same calls on the same paths, so its sums are bit-identical to
+the sequential pass.
 """
 import math
+import threading
+import time
+
+import torch
 
 import paper_2012_09715_amd as A
 
@@ -109,21 +118,88 @@ def allocate(eps, accs, costs):
     return r
 
 
-def run_estimators(model, params, L, eps, approx, seed, accs, alloc):
+_STREAMS = []
+
+
+def _streams(k):
+    """A fixed pool of k streams at the default priority (the library keeps a
+    workspace per stream it has seen, so the pool is reused)."""
+    while len(_STREAMS) < k:
+        _STREAMS.append(torch.cuda.Stream())
+    return _STREAMS[:k]
+
+
+def run_concurrent(jobs, n_streams=4):
+    """Runs zero-argument level calls on n_streams streams, one host thread
+    per stream taking the next job in list order (put the dearest first); the
+    library's calls release the GIL while they wait for the device.  Returns
+    the results in job order and the wall-clock milliseconds from the first
+    launch to the last result."""
+    streams = _streams(n_streams)
+    results = [None] * len(jobs)
+    errors = []
+    nxt = [0]
+    lock = threading.Lock()
+
+    def worker(st):
+        with torch.cuda.stream(st):
+            while True:
+                with lock:
+                    i = nxt[0]
+                    nxt[0] += 1
+                if i >= len(jobs) or errors:
+                    return
+                try:
+                    results[i] = jobs[i]()
+                except BaseException as e:  # re-raised on the calling thread
+                    errors.append(e)
+                    return
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    threads = [threading.Thread(target=worker, args=(st,)) for st in streams]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    wall = (time.perf_counter() - t0) * 1e3
+    if errors:
+        raise errors[0]
+    return results, wall
+
+
+def run_estimators(model, params, L, eps, approx, seed, accs, alloc, n_streams=4):
     """Runs the allocated path counts on fresh paths of every stream (the
     pilot paths are not reused, so the estimate is independent of the
     allocation) and returns the two estimators, their standard errors and
     their measured device times."""
     out = {}
     plan = {A.KIND_EXACT: alloc["m_hat"], A.KIND_APPROX: alloc["m_tilde"], A.KIND_CORRECTION: alloc["M_tilde"]}
+    cost = {A.KIND_EXACT: alloc["c_hat"], A.KIND_APPROX: alloc["c2"], A.KIND_CORRECTION: alloc["c4"]}
     runs = [[Acc() for _ in KINDS] for _ in range(L + 1)]
     time_ms = {k: 0.0 for k in KINDS}
+    calls = {}
     for l in range(L + 1):
         for k in KINDS:
             want = max(int(math.ceil(plan[k][l])), 2)
+            off = int(accs[l][k].n)
+            calls[(l, k)] = (want, off)
             r = runs[l][k]
-            r.add(level_call(model, params, l, want, k, approx, seed, int(accs[l][k].n)))
+            s = level_call(model, params, l, want, k, approx, seed, off)
+            r.add(s)
             time_ms[k] += r.ms
+            calls[(l, k)] += (s,)
+    # the same calls again, each estimator's levels concurrently, dearest first
+    wall = {}
+    same = True
+    for name, kinds in (("hat", (A.KIND_EXACT,)), ("tilde", (A.KIND_APPROX, A.KIND_CORRECTION))):
+        keys = sorted(((l, k) for l in range(L + 1) for k in kinds),
+                      key=lambda lk: -calls[lk][0] * cost[lk[1]][lk[0]])
+        jobs = [(lambda lk=lk: level_call(model, params, lk[0], calls[lk][0], lk[1], approx, seed, calls[lk][1]))
+                for lk in keys]
+        res, wall[name] = run_concurrent(jobs, n_streams)
+        for lk, r in zip(keys, res):
+            same = same and r["sum"] == calls[lk][2]["sum"] and r["sum_pf"] == calls[lk][2]["sum_pf"]
     theta_hat = sum(runs[l][A.KIND_EXACT].mean for l in range(L + 1))
     var_hat = sum(runs[l][A.KIND_EXACT].var / runs[l][A.KIND_EXACT].n for l in range(L + 1))
     theta_tilde = sum(runs[l][A.KIND_APPROX].mean + runs[l][A.KIND_CORRECTION].mean for l in range(L + 1))
@@ -134,6 +210,9 @@ def run_estimators(model, params, L, eps, approx, seed, accs, alloc):
     out.update(theta_hat=theta_hat, se_hat=math.sqrt(var_hat), theta_tilde=theta_tilde,
                se_tilde=math.sqrt(var_tilde), device_ms_hat=t_hat, device_ms_tilde=t_tilde,
                measured_speedup=t_hat / t_tilde if t_tilde > 0 else None,
+               wall_ms_hat_concurrent=wall["hat"], wall_ms_tilde_concurrent=wall["tilde"],
+               measured_speedup_concurrent=wall["hat"] / wall["tilde"], concurrent_streams=n_streams,
+               concurrent_sums_identical=bool(same),
                fallbacks=sum(runs[l][k].fallbacks for l in range(L + 1) for k in KINDS),
                level_ms={name: [runs[l][k].ms for l in range(L + 1)]
                          for name, k in (("exact", A.KIND_EXACT), ("approx", A.KIND_APPROX),
@@ -174,8 +253,6 @@ SURROGATE_RANGE = (-8.0, 10.0)
 def train_surrogate(n_train=10_000_000, epochs=8, batch=4096, lr=3e-3, seed=20201217, n_eval=1 << 18, log=print):
     """Builds and trains the CIR surrogate on n_train exact FP64 targets;
     returns (surrogate, report) with the held-out RMSE against exact targets."""
-    import time
-    import torch
     s = A.Surrogate.create(NU_CIR, *SURROGATE_RANGE, seed=seed)
     t0 = time.perf_counter()
     u, ll, t = s.make_data(n_train, seed)
@@ -208,7 +285,6 @@ def variance_study(params=FIG4B_PARAMS, levels=range(0, 9), n=1 << 16, seed=4242
     approximation, per level (2^l steps).  params["functional"] 0 is X_T,
     1 the trapezoidal time average (the path-dependent, Asian, case of
     Section 5.2)."""
-    import torch
     nu = 4 * params["kappa"] * params["theta"] / params["xi"] ** 2
     tabs = {d: A.Chi2Table.create(nu, d) for d in (1, 3)}
     po = torch.empty(n * 3, dtype=torch.float64, device="cuda")
@@ -229,9 +305,10 @@ def variance_study(params=FIG4B_PARAMS, levels=range(0, 9), n=1 << 16, seed=4242
 
 
 def _short(r):
-    keys = ("eps", "levels", "formula_speedup", "measured_speedup", "T_hat_s", "T_tilde_s", "device_ms_hat",
-            "device_ms_tilde", "paths_hat", "paths_tilde", "theta_hat", "se_hat", "theta_tilde", "se_tilde",
-            "fallbacks")
+    keys = ("eps", "levels", "formula_speedup", "measured_speedup", "measured_speedup_concurrent", "T_hat_s",
+            "T_tilde_s", "device_ms_hat", "device_ms_tilde", "wall_ms_hat_concurrent", "wall_ms_tilde_concurrent",
+            "concurrent_sums_identical", "paths_hat", "paths_tilde", "theta_hat", "se_hat", "theta_tilde",
+            "se_tilde", "fallbacks")
     return {k: r[k] for k in keys if k in r}
 
 
@@ -274,7 +351,9 @@ def bench_summary(log=print, seed=20201217, large_paths=1e8):
                                           target_paths=large_paths)
     r = res["gbm_milstein_1e8"]
     log(f"  eps {r['eps']:.2e}: formula {r['formula_speedup']:.3f}, measured {r['measured_speedup']:.3f} "
-        f"({r['device_ms_hat']:.1f} ms vs {r['device_ms_tilde']:.1f} ms)")
+        f"({r['device_ms_hat']:.1f} ms vs {r['device_ms_tilde']:.1f} ms), concurrent "
+        f"{r['measured_speedup_concurrent']:.3f} ({r['wall_ms_hat_concurrent']:.1f} ms vs "
+        f"{r['wall_ms_tilde_concurrent']:.1f} ms)")
     sur, rep = train_surrogate(seed=seed, log=log)
     res["surrogate"] = rep
     log("mlmc: CIR time average, levels 0..6, surrogate")
@@ -294,7 +373,9 @@ def bench_summary(log=print, seed=20201217, large_paths=1e8):
                                  steps_budget=1 << 24, target_paths=large_paths)
     r = res["cir_1e8"]
     log(f"  eps {r['eps']:.2e}: formula {r['formula_speedup']:.3f}, measured {r['measured_speedup']:.3f} "
-        f"({r['device_ms_hat']:.1f} ms vs {r['device_ms_tilde']:.1f} ms)")
+        f"({r['device_ms_hat']:.1f} ms vs {r['device_ms_tilde']:.1f} ms), concurrent "
+        f"{r['measured_speedup_concurrent']:.3f} ({r['wall_ms_hat_concurrent']:.1f} ms vs "
+        f"{r['wall_ms_tilde_concurrent']:.1f} ms)")
     for func, key in ((0, "fig4b"), (1, "fig4b_time_average")):
         log(f"variance study (Figure 4b, functional {func}): kappa 1/2, theta = xi = T = v0 = 1, levels 0..8")
         res[key] = variance_study(dict(FIG4B_PARAMS, functional=func))
@@ -305,5 +386,7 @@ def bench_summary(log=print, seed=20201217, large_paths=1e8):
                                        n_pilot=1 << 14, steps_budget=1 << 24, target_paths=large_paths)
     r = res["cir_poly1_1e8"]
     log(f"  eps {r['eps']:.2e}: formula {r['formula_speedup']:.3f}, measured {r['measured_speedup']:.3f} "
-        f"({r['device_ms_hat']:.1f} ms vs {r['device_ms_tilde']:.1f} ms)")
+        f"({r['device_ms_hat']:.1f} ms vs {r['device_ms_tilde']:.1f} ms), concurrent "
+        f"{r['measured_speedup_concurrent']:.3f} ({r['wall_ms_hat_concurrent']:.1f} ms vs "
+        f"{r['wall_ms_tilde_concurrent']:.1f} ms)")
     return res
