@@ -300,8 +300,9 @@ typedef struct aicdf_surrogate aicdf_surrogate;
  * EXACT and CORRECTION calls of fewer than 2^17 paths (too few to fill the
  * GPU one path per thread) run one path per wavefront with a
  * wave-cooperative exact inverse that sums in another order; their per-path
- * values agree with those of larger calls to FP64 rounding (1e-12 relative)
- * and are bit-identical between calls of the same launch shape.  Errors: EINVAL, ERANGE, EHIP, ENOMEM. */
+ * values agree with those of larger calls to 1e-11 relative (rounding of
+ * the sums, which can steer the root iteration to another last step) and
+ * are bit-identical between calls of the same launch shape.  Errors: EINVAL, ERANGE, EHIP, ENOMEM. */
 aicdf_status mlmc_level_cir(const aicdf_cir_params* params, uint32_t level, uint64_t n_paths,
                             int32_t kind, const aicdf_surrogate* approx, uint64_t seed,
                             uint64_t path_offset, aicdf_level_sums* out, double* path_out,
@@ -360,12 +361,14 @@ aicdf_status mlmc_allocate(uint32_t n_levels, double eps, const double* v_hat, c
 /* x[i] = C_nu^-1(u[i]; lambda[i]) in FP64: the CDF is the Poisson mixture of
  * central chi-squared CDFs (Abramowitz & Stegun 26.4.25, which Section 5
  * cites), summed outward from the Poisson mode with incomplete-gamma
- * recurrences; the root is found by safeguarded Newton steps in log x on
- * log C (u <= 1/2) or log(1 - C) (u > 1/2), inside a maintained bracket.
+ * recurrences; the root is found by safeguarded Halley steps (with the
+ * density and its derivative from the same sweep) in log x on log C
+ * (u <= 1/2) or in x on log(1 - C) (u > 1/2), inside a maintained bracket.
  * u, lambda, x: device arrays of n doubles; nu > 0; lambda >= 0.
  * u = 0 gives 0, u = 1 gives +inf.  Batches of n <= 8192 run one inverse per
  * wavefront (the sweeps split over the 64 lanes, for latency); larger ones
- * one per thread.  The two agree to FP64 rounding (1e-12 relative).
+ * one per thread.  The two agree to 1e-11 relative (they round their sums
+ * differently, which can change the last step of the root iteration).
  * Errors: EINVAL, EALIAS, EHIP. */
 aicdf_status ncx2_icdf_exact(double nu, size_t n, const double* u, const double* lambda,
                              double* x, void* stream);

@@ -29,8 +29,13 @@
 
 namespace aicdf {
 
+// C, 1 - C, the density f and its derivative f' = df/dx.  With the central
+// densities f_k(x) = (1/2) y^(a+j-1) e^-y / Gamma(a+j), k = 2(a+j), and
+// d f_k/dx = f_k ((a+j-1)/y - 1)/2:
+//   f  = sum_j c_j (a+j) / (2y),
+//   f' = sum_j c_j (a+j)(a+j-1) / (4y^2) - f/2.
 struct Ncx2Val {
-  double cdf, sf, pdf;
+  double cdf, sf, pdf, dpdf;
 };
 
 // P(A, y) and Q(A, y) with t = y^A e^-y / Gamma(A+1) given (A > 0, y > 0).
@@ -82,6 +87,15 @@ __host__ __device__ inline void ncx2_sweep_range(double y, double a, double mu, 
   if (!(mu >= 1e-40) || !(mu * y >= 1e-40)) jb = je = 0.0;
 }
 
+// m e^ls without underflow or overflow of e^ls alone (the carried sums can
+// be far outside the FP64 range of e^ls in the far tails while the product
+// is not).
+__host__ __device__ inline double ncx2_scale(double m, double ls) {
+  if (ls > -700.0 && ls < 700.0) return m * exp(ls);
+  if (m == 0.0) return 0.0;
+  return copysign(exp(log(fabs(m)) + ls), m);
+}
+
 // log w_j and log t_j.
 __host__ __device__ inline double ncx2_logw(double j, double mu) {
   return mu > 0.0 ? -mu + j * log(mu) - lgamma(j + 1.0) : (j == 0.0 ? 0.0 : -1e308);
@@ -97,8 +111,8 @@ constexpr double kNcx2Small = 0x1p-600;
 
 // C(x) and pdf(x) by the downward sweep.
 __host__ __device__ inline __noinline__ Ncx2Val ncx2_cdf(double x, double nu, double lam) {
-  if (!(x > 0.0)) return Ncx2Val{0.0, 1.0, 0.0};
-  if (x > 1.7976931348623157e308) return Ncx2Val{1.0, 0.0, 0.0};
+  if (!(x > 0.0)) return Ncx2Val{0.0, 1.0, 0.0, 0.0};
+  if (x > 1.7976931348623157e308) return Ncx2Val{1.0, 0.0, 0.0, 0.0};
   const double y = 0.5 * x, a = 0.5 * nu, mu = 0.5 * lam, ly = log(y);
   double jb, je;
   ncx2_sweep_range(y, a, mu, jb, je);
@@ -112,12 +126,13 @@ __host__ __device__ inline __noinline__ Ncx2Val ncx2_cdf(double x, double nu, do
   double D = exp(lD - L), c = exp(lc - L), w = 1.0;
   // mu = 0 ends the sweep at j = 0 before inv_mu is used
   const double inv_mu = 1.0 / mu, inv_y = 1.0 / y;
-  double cdf = 0.0, pa = 0.0;  // pa = sum c_j (a + j), pdf = pa / (2y)
+  double cdf = 0.0, pa = 0.0, pb = 0.0;  // pa = sum c_j (a+j), pb = sum c_j (a+j)(a+j-1)
   int k = 0;
   for (int j = int(je);; --j) {
     const double Aj = a + j;
     cdf += D;
     pa = fma(c, Aj, pa);
+    pb = fma(c, Aj * (Aj - 1.0), pb);
     if (j == 0) break;
     // step to j - 1: D_(j-1) = (j/mu) D_j + c_(j-1),  c_(j-1) = c_j (j/mu) ((a+j)/y)
     const double rw = j * inv_mu;
@@ -129,6 +144,7 @@ __host__ __device__ inline __noinline__ Ncx2Val ncx2_cdf(double x, double nu, do
       c *= kNcx2Small;
       cdf *= kNcx2Small;
       pa *= kNcx2Small;
+      pb *= kNcx2Small;
       ++k;
     }
     if (j - 1 < mu && j - 1 < jb + 1.0) {
@@ -141,20 +157,22 @@ __host__ __device__ inline __noinline__ Ncx2Val ncx2_cdf(double x, double nu, do
         if (log_head <= log(1e-17 * cdf) && D <= 1e-17 * cdf && c * rc / (1.0 - rc) <= 0.5e-17 * pa) {
           cdf += D;
           pa = fma(c, a + j - 1, pa);
+          pb = fma(c, (a + j - 1) * (a + j - 2), pb);
           break;
         }
       }
     }
   }
-  const double e = exp(L + k * 415.88830833596718);  // e^L 2^(600 k)
-  const double C = cdf * e, f = pa * (0.5 * inv_y) * e;
-  return Ncx2Val{fmin(C, 1.0), fmax(1.0 - C, 0.0), f};
+  const double ls = L + k * 415.88830833596718;  // e^L 2^(600 k)
+  const double C = ncx2_scale(cdf, ls), f = ncx2_scale(pa * (0.5 * inv_y), ls);
+  const double fp = ncx2_scale(pb * (0.25 * inv_y * inv_y), ls) - 0.5 * f;
+  return Ncx2Val{fmin(C, 1.0), fmax(1.0 - C, 0.0), f, fp};
 }
 
 // 1 - C(x) and pdf(x) by the upward sweep.
 __host__ __device__ inline __noinline__ Ncx2Val ncx2_sf(double x, double nu, double lam) {
-  if (!(x > 0.0)) return Ncx2Val{0.0, 1.0, 0.0};
-  if (x > 1.7976931348623157e308) return Ncx2Val{1.0, 0.0, 0.0};
+  if (!(x > 0.0)) return Ncx2Val{0.0, 1.0, 0.0, 0.0};
+  if (x > 1.7976931348623157e308) return Ncx2Val{1.0, 0.0, 0.0, 0.0};
   const double y = 0.5 * x, a = 0.5 * nu, mu = 0.5 * lam, ly = log(y);
   double jb, je;
   ncx2_sweep_range(y, a, mu, jb, je);
@@ -167,12 +185,13 @@ __host__ __device__ inline __noinline__ Ncx2Val ncx2_sf(double x, double nu, dou
   const double L = fmax(lG, lc);
   double G = exp(lG - L), c = exp(lc - L), w = 1.0;
   const double muy = mu * y;
-  double sf = 0.0, pa = 0.0;  // pa = sum c_j (a + j), pdf = pa / (2y)
+  double sf = 0.0, pa = 0.0, pb = 0.0;  // pa = sum c_j (a+j), pb = sum c_j (a+j)(a+j-1)
   int k = 0;
   for (int j = int(jb); j < int(jb) + 400000; ++j) {
     const double Aj = a + j;
     sf += G;
     pa = fma(c, Aj, pa);
+    pb = fma(c, Aj * (Aj - 1.0), pb);
     if (je == 0.0) break;  // the single term j = 0
     // step to j + 1: G_(j+1) = (mu/(j+1)) (G_j + c_j),  c_(j+1) = c_j (mu/(j+1)) (y/(a+j+1)),
     // with one division: d = 1 / ((j+1)(a+j+1))
@@ -186,6 +205,7 @@ __host__ __device__ inline __noinline__ Ncx2Val ncx2_sf(double x, double nu, dou
       c *= kNcx2Small;
       sf *= kNcx2Small;
       pa *= kNcx2Small;
+      pb *= kNcx2Small;
       ++k;
     }
     if (j + 1 > mu && j + 1 > je - 1.0) {
@@ -198,9 +218,10 @@ __host__ __device__ inline __noinline__ Ncx2Val ncx2_sf(double x, double nu, dou
       }
     }
   }
-  const double e = exp(L + k * 415.88830833596718);  // e^L 2^(600 k)
-  const double S = sf * e, f = pa * (0.5 / y) * e;
-  return Ncx2Val{fmax(1.0 - S, 0.0), fmin(S, 1.0), f};
+  const double ls = L + k * 415.88830833596718;  // e^L 2^(600 k)
+  const double S = ncx2_scale(sf, ls), f = ncx2_scale(pa * (0.5 / y), ls);
+  const double fp = ncx2_scale(pb * (0.25 / (y * y)), ls) - 0.5 * f;
+  return Ncx2Val{fmax(1.0 - S, 0.0), fmin(S, 1.0), f, fp};
 }
 
 // Quick initial value: Patnaik's scaled central chi-squared with the
@@ -218,7 +239,7 @@ __host__ __device__ inline __noinline__ double ncx2_guess(double t, bool upper, 
   return rho * k * b * b * b;
 }
 
-// Inverse CDF by safeguarded Newton steps, inside a bracket that is valid
+// Inverse CDF by safeguarded Halley steps, inside a bracket that is valid
 // before any evaluation:
 //   lower: C(x) <= P(a, x/2) <= (x/2)^a / Gamma(a+1), so
 //          x_lo = 2 (u Gamma(a+1))^(1/a) has C(x_lo) <= u;
@@ -229,13 +250,36 @@ __host__ __device__ inline __noinline__ double ncx2_guess(double t, bool upper, 
 // tail, upper = false) or 1 - u = t (upper tail, upper = true), so that
 // upper-tail targets below the FP64 spacing near 1 keep full precision.
 // lower: g(w) = log C(e^w) - log t in w = log x (the lower tail of C is
-//        close to a power of x, so g is close to linear in w);
+//        close to a power of x, so g is close to linear in w),
+//        g' = x f / C,  g'' = g' + x^2 f' / C - g'^2;
 // upper: g(x) = log t - log(1 - C(x)) in x (close to linear in x in the
-//        upper tail).
-// Steps that leave the bracket are replaced by bisection (geometric while the
-// bracket spans more than a factor of two).  `iters` receives the number of
-// CDF evaluations.
+//        upper tail),  g' = f / S,  g'' = f' / S + g'^2,  S = 1 - C.
+// The Halley step 2 g g' / (2 g'^2 - g g'') is taken when it points the way
+// of the Newton step g / g' and is at most twice as long; otherwise the
+// Newton step.  Steps that leave the bracket are replaced by bisection
+// (geometric while the bracket spans more than a factor of two).  The
+// iteration stops when a step is below 2e-15 relative, or when a Halley
+// (Newton) step inside the bracket is below 1e-6 (1e-9) relative: the error
+// after it is of the order of the cube (square) of the step, far below the
+// FP64 resolution, so the confirming evaluation is skipped.  `iters`
+// receives the number of CDF evaluations.
 __host__ __device__ inline __noinline__ double ncx2_lgamma(double x) { return lgamma(x); }
+
+// The Halley step if usable, else the Newton step; `halley` tells which.
+__host__ __device__ inline double ncx2_step(double g, double dg, double d2g, bool& halley) {
+  const double newton = g / dg;
+  const double den = 2.0 * dg * dg - g * d2g;
+  halley = false;
+  if (den > 0.0) {
+    const double h = 2.0 * g * dg / den;
+    if (h * newton > 0.0 && fabs(h) <= 2.0 * fabs(newton)) {
+      halley = true;
+      return h;
+    }
+  }
+  return newton;
+}
+
 // Ev supplies Ncx2Val cdf(x) and Ncx2Val sf(x) for the given (nu, lambda).
 // x0 > 0 inside the bracket replaces the built-in initial value (a caller
 // holding an approximation of the root passes it here).
@@ -257,16 +301,27 @@ __host__ __device__ inline double ncx2_solve(double t, bool upper, double nu, do
       const double xx = exp(w);
       const Ncx2Val v = ev.cdf(xx);
       const double g = v.cdf > 0.0 ? log(v.cdf) - lu : -1e300;
-      const double dg = v.cdf > 0.0 ? xx * v.pdf / v.cdf : 0.0;
       if (g == 0.0) break;
       if (g < 0.0) wlo = w; else whi = w;
       const double tol = 2e-15 * fmax(1.0, fabs(w));
-      double wn = (dg > 0.0 && g > -1e300) ? w - g / dg : 0.5 * (wlo + whi);
-      if (fabs(wn - w) <= tol) {  // converged (may sit on the bracket end)
+      double wn = 0.5 * (wlo + whi);
+      bool halley = false, good = false;
+      if (v.cdf > 0.0 && v.pdf > 0.0) {
+        const double dg = xx * v.pdf / v.cdf;
+        const double d2g = dg + xx * xx * v.dpdf / v.cdf - dg * dg;
+        wn = w - ncx2_step(g, dg, d2g, halley);
+        good = true;
+      }
+      if (good && fabs(wn - w) <= tol) {  // converged (may sit on the bracket end)
         w = wn;
         break;
       }
-      if (!(wn > wlo && wn < whi)) wn = 0.5 * (wlo + whi);
+      if (!(wn > wlo && wn < whi)) {
+        wn = 0.5 * (wlo + whi);
+      } else if (good && fabs(wn - w) <= (halley ? 1e-6 : 1e-9) * fmax(1.0, fabs(w))) {
+        w = wn;
+        break;
+      }
       w = wn;
       if (whi - wlo <= tol) break;
     }
@@ -275,15 +330,26 @@ __host__ __device__ inline double ncx2_solve(double t, bool upper, double nu, do
     for (; it < 100; ++it) {
       const Ncx2Val v = ev.sf(x);
       const double g = v.sf > 0.0 ? lq - log(v.sf) : 1e300;
-      const double dg = v.sf > 0.0 ? v.pdf / v.sf : 0.0;
       if (g == 0.0) break;
       if (g < 0.0) xlo = x; else xhi = x;
-      double xn = (dg > 0.0 && g < 1e300) ? x - g / dg : -1.0;
-      if (xn > 0.0 && fabs(xn - x) <= 2e-15 * x) {  // converged (may sit on the bracket end)
+      double xn = -1.0;
+      bool halley = false, good = false;
+      if (v.sf > 0.0 && v.pdf > 0.0) {
+        const double dg = v.pdf / v.sf;
+        const double d2g = v.dpdf / v.sf + dg * dg;
+        xn = x - ncx2_step(g, dg, d2g, halley);
+        good = true;
+      }
+      if (good && xn > 0.0 && fabs(xn - x) <= 2e-15 * x) {  // converged (may sit on the bracket end)
         x = xn;
         break;
       }
-      if (!(xn > xlo && xn < xhi)) xn = (xhi > 2.0 * xlo) ? sqrt(xlo) * sqrt(xhi) : 0.5 * (xlo + xhi);
+      if (!(xn > xlo && xn < xhi)) {
+        xn = (xhi > 2.0 * xlo) ? sqrt(xlo) * sqrt(xhi) : 0.5 * (xlo + xhi);
+      } else if (good && fabs(xn - x) <= (halley ? 1e-6 : 1e-9) * x) {
+        x = xn;
+        break;
+      }
       x = xn;
       if (xhi - xlo <= 2e-15 * x) break;
     }

@@ -76,42 +76,93 @@ __device__ __forceinline__ Ncx2Tri ncx2_scan(Ncx2Tri t, int lane, Ncx2Tri& all) 
   return x;
 }
 
-// Sum over the wave of m_l 2^(e_l), returned as (mantissa, exponent) in every lane.
-__device__ __forceinline__ void ncx2_wave_sum2(double m1, double m2, int e, double& s1, double& s2, int& es) {
-  int emax = (m1 > 0.0 || m2 > 0.0) ? e : -100000;
+// Sums over the wave of three values m_i 2^(e_l) with a common per-lane
+// exponent, returned as mantissas on one exponent in every lane (the
+// butterfly gives every lane the same bits).  m1, m2 >= 0; m3 may be negative.
+__device__ __forceinline__ void ncx2_wave_sum3(double m1, double m2, double m3, int e, double& s1, double& s2,
+                                               double& s3, int& es) {
+  int emax = (m1 > 0.0 || m2 > 0.0 || m3 != 0.0) ? e : -100000;
   for (int k = 32; k > 0; k >>= 1) emax = max(emax, __shfl_xor(emax, k));
-  double a1 = ldexp(m1, max(e - emax, -2000)), a2 = ldexp(m2, max(e - emax, -2000));
+  const int sh = max(e - emax, -2000);
+  double a1 = ldexp(m1, sh), a2 = ldexp(m2, sh), a3 = ldexp(m3, sh);
   for (int k = 32; k > 0; k >>= 1) {
     a1 += __shfl_xor(a1, k);
     a2 += __shfl_xor(a2, k);
+    a3 += __shfl_xor(a3, k);
   }
   s1 = a1;
   s2 = a2;
+  s3 = a3;
   es = emax == -100000 ? 0 : emax;
 }
 
-// (m, e) += (a, ea)
-__device__ __forceinline__ void ncx2_acc(double& m, int& e, double a, int ea) {
-  if (!(a > 0.0)) return;
-  if (!(m > 0.0)) {
-    m = a;
+// (m1, m2, m3) 2^e += (a1, a2, a3) 2^ea: the three totals share one exponent.
+__device__ __forceinline__ void ncx2_acc3(double& m1, double& m2, double& m3, int& e, double a1, double a2,
+                                          double a3, int ea) {
+  if (!(a1 > 0.0 || a2 > 0.0 || a3 != 0.0)) return;
+  if (!(m1 > 0.0 || m2 > 0.0 || m3 != 0.0)) {
+    m1 = a1;
+    m2 = a2;
+    m3 = a3;
     e = ea;
     return;
   }
   if (ea > e) {
-    m = ldexp(m, max(e - ea, -2000)) + a;
+    const int sh = max(e - ea, -2000);
+    m1 = ldexp(m1, sh) + a1;
+    m2 = ldexp(m2, sh) + a2;
+    m3 = ldexp(m3, sh) + a3;
     e = ea;
   } else {
-    m += ldexp(a, max(ea - e, -2000));
+    const int sh = max(ea - e, -2000);
+    m1 += ldexp(a1, sh);
+    m2 += ldexp(a2, sh);
+    m3 += ldexp(a3, sh);
   }
+}
+
+// S = sum_(k>=0) prod_(i=1..k) y/(A+i), so that P(A, y) = t S with
+// t = y^A e^-y / Gamma(A+1) (the power series of the sequential sweeps, for
+// y < A + 1), by the wave: lane l takes term k0 + l + 1 of each chunk of 64,
+// the terms of a chunk are the prefix products of its ratios (a shuffle
+// scan) times the product carried in, and a butterfly sums them.  The
+// ratios fall below 1/2 when A >= 2y, and one chunk then suffices.
+__device__ inline double ncx2_series_wave(double A, double y, int lane) {
+  double sum = 1.0, carry = 1.0;
+  for (int k0 = 0; k0 < 1 << 20; k0 += 64) {
+    double p = y / (A + double(k0 + lane + 1));
+    for (int d = 1; d < 64; d <<= 1) {
+      const double o = __shfl_up(p, d);
+      if (lane >= d) p *= o;
+    }
+    const double term = carry * p;
+    double sc = term;
+    for (int k = 32; k > 0; k >>= 1) sc += __shfl_xor(sc, k);
+    sum += sc;
+    carry = __shfl(term, 63);
+    // the rest is below carry r / (1 - r), r the next ratio (< 1 here)
+    const double r = y / (A + double(k0 + 65));
+    if (!(r < 1.0) || carry * r <= 1e-17 * sum * (1.0 - r)) break;
+  }
+  return sum;
+}
+
+// log w_j (Poisson weight) and log t_A (as ncx2_logw, ncx2_logt), with the
+// two log-gamma values taken by two lanes at once.
+__device__ __forceinline__ void ncx2_logs_wave(double j, double A, double y, double ly, double mu, int lane,
+                                               double& lw, double& lt) {
+  const double lg = ncx2_lgamma(lane == 0 ? j + 1.0 : A + 1.0);
+  const double lgj = __shfl(lg, 0), lgA = __shfl(lg, 1);
+  lw = mu > 0.0 ? -mu + j * log(mu) - lgj : (j == 0.0 ? 0.0 : -1e308);
+  lt = A * ly - y - lgA;
 }
 
 constexpr int kNcx2PassTerms = 64 * 16;
 
 // C(x) and pdf(x), the downward sweep shared by the wave.
 __device__ inline __noinline__ Ncx2Val ncx2_cdf_wave(double x, double nu, double lam) {
-  if (!(x > 0.0)) return Ncx2Val{0.0, 1.0, 0.0};
-  if (x > 1.7976931348623157e308) return Ncx2Val{1.0, 0.0, 0.0};
+  if (!(x > 0.0)) return Ncx2Val{0.0, 1.0, 0.0, 0.0};
+  if (x > 1.7976931348623157e308) return Ncx2Val{1.0, 0.0, 0.0, 0.0};
   const int lane = __lane_id();
   const double y = 0.5 * x, a = 0.5 * nu, mu = 0.5 * lam, ly = log(y);
   double jbd, jed;
@@ -121,9 +172,13 @@ __device__ inline __noinline__ Ncx2Val ncx2_cdf_wave(double x, double nu, double
   // (je = 0: the single term j = 0)
   if (jed > 0.0) jed = fmax(jed, fmin(ceil(2.0 * y - a), jed + 4096.0));
   const double A = a + jed;
-  const double lw = ncx2_logw(jed, mu), lt = ncx2_logt(A, y, ly);
+  double lw, lt;
+  ncx2_logs_wave(jed, A, y, ly, mu, lane, lw, lt);
   double P, Q;
-  inc_gamma_pq(A, y, 1.0, P, Q);
+  if (y < A + 1.0)
+    P = ncx2_series_wave(A, y, lane);
+  else
+    inc_gamma_pq(A, y, 1.0, P, Q);
   const double lc = lw + lt;
   const double lD = (y < A + 1.0) ? lc + log(P) : lw + log(fmax(1.0 - Q * exp(lt), 1e-300));
   const double L = fmax(lD, lc);
@@ -131,7 +186,7 @@ __device__ inline __noinline__ Ncx2Val ncx2_cdf_wave(double x, double nu, double
   double D = exp(lD - L), c = exp(lc - L);
   int E = 0;
   const double inv_mu = 1.0 / mu, inv_y = 1.0 / y;
-  double cdf = 0.0, pa = 0.0;  // totals: (cdf, pa) 2^Et e^L
+  double cdf = 0.0, pa = 0.0, pb = 0.0;  // totals: (cdf, pa, pb) 2^Et e^L
   int Et = 0;
   int jhi = int(jed), jlo = int(jbd);
   for (int pass = 0; pass < 100000; ++pass) {
@@ -139,11 +194,12 @@ __device__ inline __noinline__ Ncx2Val ncx2_cdf_wave(double x, double nu, double
     const int m = (n + 63) / 64;
     const int my_hi = jhi - lane * m, my_lo = max(jlo, my_hi - m + 1);
     Ncx2Tri T{1.0, 0.0, 1.0, 0};
-    double sp = 0.0, sr = 0.0, sq = 0.0;  // sums of T's rows, relative to 2^T.e
+    double sp = 0.0, sr = 0.0, sq = 0.0, sq2 = 0.0;  // sums of T's rows, relative to 2^T.e
     for (int j = my_hi; j >= my_lo; --j) {
       sp += T.p;
       sr += T.r;
       sq = fma(a + j, T.q, sq);
+      sq2 = fma((a + j) * (a + j - 1.0), T.q, sq2);
       if (j == 0) break;
       const double rw = j * inv_mu, f = rw * ((a + j) * inv_y);
       T.r = fma(rw, T.r, f * T.q);
@@ -156,6 +212,7 @@ __device__ inline __noinline__ Ncx2Val ncx2_cdf_wave(double x, double nu, double
         sp *= kNcx2Small;
         sr *= kNcx2Small;
         sq *= kNcx2Small;
+        sq2 *= kNcx2Small;
         T.e += 600;
       }
     }
@@ -165,12 +222,11 @@ __device__ inline __noinline__ Ncx2Val ncx2_cdf_wave(double x, double nu, double
     const Ncx2Tri X = ncx2_scan(T, lane, all);
     // incoming state of this lane's chunk, and its partial sums
     const double Din = fma(X.p, D, X.r * c), cin = X.q * c;
-    const double pc = fma(sp, Din, sr * cin), pp = sq * cin;
-    double s1, s2;
+    const double pc = fma(sp, Din, sr * cin), pp = sq * cin, pp2 = sq2 * cin;
+    double s1, s2, s3;
     int e12;
-    ncx2_wave_sum2(pc, pp, es + X.e + E, s1, s2, e12);
-    ncx2_acc(cdf, Et, s1, e12);
-    ncx2_acc(pa, Et, s2, e12);
+    ncx2_wave_sum3(pc, pp, pp2, es + X.e + E, s1, s2, s3, e12);
+    ncx2_acc3(cdf, pa, pb, Et, s1, s2, s3, e12);
     if (jlo == 0) break;
     // state at jlo - 1
     {
@@ -192,6 +248,7 @@ __device__ inline __noinline__ Ncx2Val ncx2_cdf_wave(double x, double nu, double
         if (log_head <= log(1e-17) + lcdf && Dr <= 1e-17 * cdf && cr * rc / (1.0 - rc) <= 0.5e-17 * pa) {
           cdf += Dr;
           pa = fma(cr, a + jn, pa);
+          pb = fma(cr, (a + jn) * (a + jn - 1.0), pb);
           break;
         }
       }
@@ -199,15 +256,16 @@ __device__ inline __noinline__ Ncx2Val ncx2_cdf_wave(double x, double nu, double
     jhi = jn;
     jlo = max(0, jn - (kNcx2PassTerms - 1));
   }
-  const double e = exp(L + Et * 0.69314718055994531);
-  const double C = cdf * e, f = pa * (0.5 * inv_y) * e;
-  return Ncx2Val{fmin(C, 1.0), fmax(1.0 - C, 0.0), f};
+  const double ls = L + Et * 0.69314718055994531;
+  const double C = ncx2_scale(cdf, ls), f = ncx2_scale(pa * (0.5 * inv_y), ls);
+  const double fp = ncx2_scale(pb * (0.25 * inv_y * inv_y), ls) - 0.5 * f;
+  return Ncx2Val{fmin(C, 1.0), fmax(1.0 - C, 0.0), f, fp};
 }
 
 // 1 - C(x) and pdf(x), the upward sweep shared by the wave.
 __device__ inline __noinline__ Ncx2Val ncx2_sf_wave(double x, double nu, double lam) {
-  if (!(x > 0.0)) return Ncx2Val{0.0, 1.0, 0.0};
-  if (x > 1.7976931348623157e308) return Ncx2Val{1.0, 0.0, 0.0};
+  if (!(x > 0.0)) return Ncx2Val{0.0, 1.0, 0.0, 0.0};
+  if (x > 1.7976931348623157e308) return Ncx2Val{1.0, 0.0, 0.0, 0.0};
   const int lane = __lane_id();
   const double y = 0.5 * x, a = 0.5 * nu, mu = 0.5 * lam, ly = log(y);
   double jbd, jed;
@@ -216,16 +274,20 @@ __device__ inline __noinline__ Ncx2Val ncx2_sf_wave(double x, double nu, double 
   // (A <= y / 2); the longer sweep is spread over the lanes
   if (jed > 0.0) jbd = fmin(jbd, fmax(fmax(0.0, floor(0.5 * y - a)), jbd - 4096.0));
   const double A = a + jbd;
-  const double lw = ncx2_logw(jbd, mu), lt = ncx2_logt(A, y, ly);
+  double lw, lt;
+  ncx2_logs_wave(jbd, A, y, ly, mu, lane, lw, lt);
   double P, Q;
-  inc_gamma_pq(A, y, 1.0, P, Q);
+  if (y < A + 1.0)
+    P = ncx2_series_wave(A, y, lane);
+  else
+    inc_gamma_pq(A, y, 1.0, P, Q);
   const double lc = lw + lt;
   const double lG = (y < A + 1.0) ? lw + log(fmax(1.0 - P * exp(lt), 1e-300)) : lc + log(Q);
   const double L = fmax(lG, lc);
   double G = exp(lG - L), c = exp(lc - L);
   int E = 0;
   const double muy = mu * y;
-  double sf = 0.0, pa = 0.0;
+  double sf = 0.0, pa = 0.0, pb = 0.0;
   int Et = 0;
   int jlo = int(jbd), jhi = int(jed);
   for (int pass = 0; pass < 400; ++pass) {
@@ -233,11 +295,12 @@ __device__ inline __noinline__ Ncx2Val ncx2_sf_wave(double x, double nu, double 
     const int m = (n + 63) / 64;
     const int my_lo = jlo + lane * m, my_hi = min(jhi, my_lo + m - 1);
     Ncx2Tri T{1.0, 0.0, 1.0, 0};
-    double sp = 0.0, sr = 0.0, sq = 0.0;
+    double sp = 0.0, sr = 0.0, sq = 0.0, sq2 = 0.0;
     for (int j = my_lo; j <= my_hi; ++j) {
       sp += T.p;
       sr += T.r;
       sq = fma(a + j, T.q, sq);
+      sq2 = fma((a + j) * (a + j - 1.0), T.q, sq2);
       const double d = 1.0 / ((j + 1.0) * (a + j + 1.0));
       const double rw = mu * (a + j + 1.0) * d, g = muy * d;
       T.r = rw * (T.r + T.q);
@@ -250,6 +313,7 @@ __device__ inline __noinline__ Ncx2Val ncx2_sf_wave(double x, double nu, double 
         sp *= kNcx2Small;
         sr *= kNcx2Small;
         sq *= kNcx2Small;
+        sq2 *= kNcx2Small;
         T.e += 600;
       }
     }
@@ -258,12 +322,11 @@ __device__ inline __noinline__ Ncx2Val ncx2_sf_wave(double x, double nu, double 
     Ncx2Tri all;
     const Ncx2Tri X = ncx2_scan(T, lane, all);
     const double Gin = fma(X.p, G, X.r * c), cin = X.q * c;
-    const double pc = fma(sp, Gin, sr * cin), pp = sq * cin;
-    double s1, s2;
+    const double pc = fma(sp, Gin, sr * cin), pp = sq * cin, pp2 = sq2 * cin;
+    double s1, s2, s3;
     int e12;
-    ncx2_wave_sum2(pc, pp, es + X.e + E, s1, s2, e12);
-    ncx2_acc(sf, Et, s1, e12);
-    ncx2_acc(pa, Et, s2, e12);
+    ncx2_wave_sum3(pc, pp, pp2, es + X.e + E, s1, s2, s3, e12);
+    ncx2_acc3(sf, pa, pb, Et, s1, s2, s3, e12);
     if (jed == 0.0) break;  // the single term j = 0
     {
       const double Gn = fma(all.p, G, all.r * c), cn = all.q * c;
@@ -287,9 +350,10 @@ __device__ inline __noinline__ Ncx2Val ncx2_sf_wave(double x, double nu, double 
     jlo = jn;
     jhi = jn + kNcx2PassTerms - 1;
   }
-  const double e = exp(L + Et * 0.69314718055994531);
-  const double S = sf * e, f = pa * (0.5 / y) * e;
-  return Ncx2Val{fmax(1.0 - S, 0.0), fmin(S, 1.0), f};
+  const double ls = L + Et * 0.69314718055994531;
+  const double S = ncx2_scale(sf, ls), f = ncx2_scale(pa * (0.5 / y), ls);
+  const double fp = ncx2_scale(pb * (0.25 / (y * y)), ls) - 0.5 * f;
+  return Ncx2Val{fmax(1.0 - S, 0.0), fmin(S, 1.0), f, fp};
 }
 
 struct Ncx2Wave {

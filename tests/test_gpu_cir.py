@@ -106,7 +106,7 @@ def test_split_determinism_and_fallbacks(damped):
     # calls of <= 2048 paths run one path per wavefront, whose cooperative
     # exact inverse sums in another order: the same paths to FP64 rounding
     _, c = run(p, 2, 2000, 2, s, 5, 1000)
-    assert np.allclose(c, whole[1000:3000], rtol=1e-12, atol=1e-15)
+    assert np.allclose(c, whole[1000:3000], rtol=1e-11, atol=1e-15)
     st2 = A.mlmc_level_cir(p, 2, 6000, 2, s, 5)
     assert st["sum"] == st2["sum"] and st["fallbacks"] == st2["fallbacks"]
     # a surrogate whose range excludes every lambda falls back on every step
@@ -164,4 +164,4 @@ def test_thread_per_path_launch_parity(damped, kind):
     assert np.all(np.abs(got[pick, 1] - ref[1]) <= tol)
     assert np.all(np.abs(got[pick, 0] - ref[0]) <= tol)
     _, few = run(p, level, 300, kind, s, seed, 99900)
-    assert np.allclose(few, got[99900:100200], rtol=1e-12, atol=1e-15)
+    assert np.allclose(few, got[99900:100200], rtol=1e-11, atol=1e-15)

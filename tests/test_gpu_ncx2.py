@@ -4,7 +4,9 @@ against the oracle's bisection on the Poisson-mixture CDF.
 Tolerance |x - x_oracle| <= 5e-11 x_oracle: both sides carry ~1e-12 relative
 error in C (log-form weights and gamma terms with exponents of size up to
 |a log y| ~ 1e4); in the lower tail d log C / d log x -> nu/2, which
-amplifies it by 2/nu (4x at nu = 0.5).
+amplifies it by 2/nu (4x at nu = 0.5).  The wavefront and thread launches
+round their sums differently, which can change the last step of the root
+iteration: they agree to 1e-11 relative.
 """
 import numpy as np
 import pytest
@@ -103,7 +105,7 @@ def test_wave_and_thread_launches_agree(nu):
     reps = 20
     many = gpu_icdf(nu, np.tile(u, reps), np.tile(lam, reps))[:m]
     assert np.all(np.isfinite(few)) and np.all(few >= 0)
-    assert np.allclose(few, many, rtol=1e-12, atol=0), np.max(np.abs(few - many) / many)
+    assert np.allclose(few, many, rtol=1e-11, atol=0), np.max(np.abs(few - many) / many)
     pick = np.concatenate([np.arange(0, 80, 7), np.arange(m - 12, m)])
     xo = ncx2.icdf(u[pick], nu, lam[pick])
     assert np.all(np.abs(few[pick] - xo) <= 5e-11 * xo)
