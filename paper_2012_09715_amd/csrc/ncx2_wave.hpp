@@ -147,17 +147,68 @@ __device__ inline double ncx2_series_wave(double A, double y, int lane) {
   return sum;
 }
 
+// log Gamma(z): for z >= 16 Stirling's series through the z^-13 term (the
+// first omitted term is below 3e-20 there), else the library routine.
+__host__ __device__ inline double ncx2_lgamma_stirling(double z) {
+  if (!(z >= 16.0)) return ncx2_lgamma(z);
+  const double w = 1.0 / z, w2 = w * w;
+  const double s =
+      w * (1.0 / 12 + w2 * (-1.0 / 360 + w2 * (1.0 / 1260 + w2 * (-1.0 / 1680 + w2 * (1.0 / 1188 +
+                                                                  w2 * (-691.0 / 360360 + w2 * (1.0 / 156)))))));
+  return (z - 0.5) * log(z) - z + 0.91893853320467274 + s;  // 0.918.. = log(2 pi) / 2
+}
+
 // log w_j (Poisson weight) and log t_A (as ncx2_logw, ncx2_logt), with the
 // two log-gamma values taken by two lanes at once.
 __device__ __forceinline__ void ncx2_logs_wave(double j, double A, double y, double ly, double mu, int lane,
                                                double& lw, double& lt) {
-  const double lg = ncx2_lgamma(lane == 0 ? j + 1.0 : A + 1.0);
+  const double lg = ncx2_lgamma_stirling(lane == 0 ? j + 1.0 : A + 1.0);
   const double lgj = __shfl(lg, 0), lgA = __shfl(lg, 1);
   lw = mu > 0.0 ? -mu + j * log(mu) - lgj : (j == 0.0 ? 0.0 : -1e308);
   lt = A * ly - y - lgA;
 }
 
 constexpr int kNcx2PassTerms = 64 * 16;
+
+// One lane's chunk of the downward sweep: the product T of the step
+// matrices of indices j_hi, j_hi - 1, .. (cnt of them) and the sums of its
+// rows.  CHECK rescales by 2^-600 when an entry passes 2^600; callers skip it
+// when the chunk's growth bound shows that no entry can.
+template <bool CHECK>
+__device__ __forceinline__ void ncx2_chunk_down(double jd, int cnt, double a, double inv_mu, double inv_y,
+                                                Ncx2Tri& T, double& sp, double& sr, double& sq, double& sq2) {
+  // the chunk that ends at j = 0 takes no step below it
+  const bool last0 = cnt > 0 && jd - (cnt - 1) == 0.0;
+  const int steps = last0 ? cnt - 1 : cnt;
+#pragma unroll 2
+  for (int i = 0; i < steps; ++i, jd -= 1.0) {
+    const double Aj = a + jd;
+    sp += T.p;
+    sr += T.r;
+    sq = fma(Aj, T.q, sq);
+    sq2 = fma(Aj * (Aj - 1.0), T.q, sq2);
+    const double rw = jd * inv_mu, f = rw * (Aj * inv_y);
+    T.r = fma(rw, T.r, f * T.q);
+    T.p *= rw;
+    T.q *= f;
+    if (CHECK && (T.p > kNcx2Big || T.r > kNcx2Big || T.q > kNcx2Big)) {
+      T.p *= kNcx2Small;
+      T.r *= kNcx2Small;
+      T.q *= kNcx2Small;
+      sp *= kNcx2Small;
+      sr *= kNcx2Small;
+      sq *= kNcx2Small;
+      sq2 *= kNcx2Small;
+      T.e += 600;
+    }
+  }
+  if (last0) {  // the sums of the j = 0 term
+    sp += T.p;
+    sr += T.r;
+    sq = fma(a, T.q, sq);
+    sq2 = fma(a * (a - 1.0), T.q, sq2);
+  }
+}
 
 // C(x) and pdf(x), the downward sweep shared by the wave.
 __device__ inline __noinline__ Ncx2Val ncx2_cdf_wave(double x, double nu, double lam) {
@@ -188,6 +239,8 @@ __device__ inline __noinline__ Ncx2Val ncx2_cdf_wave(double x, double nu, double
   const double inv_mu = 1.0 / mu, inv_y = 1.0 / y;
   double cdf = 0.0, pa = 0.0, pb = 0.0;  // totals: (cdf, pa, pb) 2^Et e^L
   int Et = 0;
+  double wm = 1.0;  // w_(jhi) / w_(jed) = wm 2^we: the scans' products of j/mu
+  int we = 0;
   int jhi = int(jed), jlo = int(jbd);
   for (int pass = 0; pass < 100000; ++pass) {
     const int n = jhi - jlo + 1;
@@ -195,26 +248,15 @@ __device__ inline __noinline__ Ncx2Val ncx2_cdf_wave(double x, double nu, double
     const int my_hi = jhi - lane * m, my_lo = max(jlo, my_hi - m + 1);
     Ncx2Tri T{1.0, 0.0, 1.0, 0};
     double sp = 0.0, sr = 0.0, sq = 0.0, sq2 = 0.0;  // sums of T's rows, relative to 2^T.e
-    for (int j = my_hi; j >= my_lo; --j) {
-      sp += T.p;
-      sr += T.r;
-      sq = fma(a + j, T.q, sq);
-      sq2 = fma((a + j) * (a + j - 1.0), T.q, sq2);
-      if (j == 0) break;
-      const double rw = j * inv_mu, f = rw * ((a + j) * inv_y);
-      T.r = fma(rw, T.r, f * T.q);
-      T.p *= rw;
-      T.q *= f;
-      if (T.p > kNcx2Big || T.r > kNcx2Big || T.q > kNcx2Big) {
-        T.p *= kNcx2Small;
-        T.r *= kNcx2Small;
-        T.q *= kNcx2Small;
-        sp *= kNcx2Small;
-        sr *= kNcx2Small;
-        sq *= kNcx2Small;
-        sq2 *= kNcx2Small;
-        T.e += 600;
-      }
+    {
+      // the step factors j/mu and (j/mu)(a+j)/y grow with j, so every entry
+      // grows by at most 2 g per step, g the larger factor at the top index
+      const int cnt = my_hi - my_lo + 1;
+      const double jt = double(my_hi), g = fmax(jt * inv_mu, jt * inv_mu * ((a + jt) * inv_y));
+      if (cnt * (ilogb(fmin(fmax(2.0 * g, 1.0), 0x1p1000)) + 1) < 500)
+        ncx2_chunk_down<false>(jt, cnt, a, inv_mu, inv_y, T, sp, sr, sq, sq2);
+      else
+        ncx2_chunk_down<true>(jt, cnt, a, inv_mu, inv_y, T, sp, sr, sq, sq2);
     }
     const int es = T.e;
     ncx2_norm(T);
@@ -230,6 +272,11 @@ __device__ inline __noinline__ Ncx2Val ncx2_cdf_wave(double x, double nu, double
     if (jlo == 0) break;
     // state at jlo - 1
     {
+      wm *= all.p;
+      we += all.e;
+      const int kw = wm > 0.0 ? ilogb(wm) : 0;
+      wm = ldexp(wm, -kw);
+      we += kw;
       const double Dn = fma(all.p, D, all.r * c), cn = all.q * c;
       const double mx = fmax(Dn, cn);
       const int k = mx > 0.0 ? ilogb(mx) : 0;
@@ -242,10 +289,10 @@ __device__ inline __noinline__ Ncx2Val ncx2_cdf_wave(double x, double nu, double
       // remaining head below jn: sum w_k P_k <= w_jn r/(1-r); sum c_k <= c_jn rc/(1-rc)
       const double r = jn * inv_mu, rc = r * ((a + jn) * inv_y);
       if (r < 1.0 && rc < 1.0) {
-        const double lcdf = log(cdf) + Et * 0.69314718055994531 + L;
-        const double log_head = ncx2_logw(double(jn), mu) + log(r / (1.0 - r));
+        // w_jn r/(1-r) on the scale 2^Et e^L of the totals
+        const double head = ncx2_scale(wm * (r / (1.0 - r)), lw - L + (we - Et) * 0.69314718055994531);
         const double Dr = ldexp(D, E - Et), cr = ldexp(c, E - Et);
-        if (log_head <= log(1e-17) + lcdf && Dr <= 1e-17 * cdf && cr * rc / (1.0 - rc) <= 0.5e-17 * pa) {
+        if (head <= 1e-17 * cdf && Dr <= 1e-17 * cdf && cr * rc / (1.0 - rc) <= 0.5e-17 * pa) {
           cdf += Dr;
           pa = fma(cr, a + jn, pa);
           pb = fma(cr, (a + jn) * (a + jn - 1.0), pb);
@@ -260,6 +307,36 @@ __device__ inline __noinline__ Ncx2Val ncx2_cdf_wave(double x, double nu, double
   const double C = ncx2_scale(cdf, ls), f = ncx2_scale(pa * (0.5 * inv_y), ls);
   const double fp = ncx2_scale(pb * (0.25 * inv_y * inv_y), ls) - 0.5 * f;
   return Ncx2Val{fmin(C, 1.0), fmax(1.0 - C, 0.0), f, fp};
+}
+
+// One lane's chunk of the upward sweep (indices j_lo, j_lo + 1, ..), as
+// ncx2_chunk_down.
+template <bool CHECK>
+__device__ __forceinline__ void ncx2_chunk_up(double jd, int cnt, double a, double mu, double muy, Ncx2Tri& T,
+                                              double& sp, double& sr, double& sq, double& sq2) {
+#pragma unroll 2
+  for (int i = 0; i < cnt; ++i, jd += 1.0) {
+    const double Aj = a + jd;
+    sp += T.p;
+    sr += T.r;
+    sq = fma(Aj, T.q, sq);
+    sq2 = fma(Aj * (Aj - 1.0), T.q, sq2);
+    const double d = 1.0 / ((jd + 1.0) * (Aj + 1.0));
+    const double rw = mu * (Aj + 1.0) * d, g = muy * d;
+    T.r = rw * (T.r + T.q);
+    T.p *= rw;
+    T.q *= g;
+    if (CHECK && (T.p > kNcx2Big || T.r > kNcx2Big || T.q > kNcx2Big)) {
+      T.p *= kNcx2Small;
+      T.r *= kNcx2Small;
+      T.q *= kNcx2Small;
+      sp *= kNcx2Small;
+      sr *= kNcx2Small;
+      sq *= kNcx2Small;
+      sq2 *= kNcx2Small;
+      T.e += 600;
+    }
+  }
 }
 
 // 1 - C(x) and pdf(x), the upward sweep shared by the wave.
@@ -289,6 +366,8 @@ __device__ inline __noinline__ Ncx2Val ncx2_sf_wave(double x, double nu, double 
   const double muy = mu * y;
   double sf = 0.0, pa = 0.0, pb = 0.0;
   int Et = 0;
+  double wm = 1.0;  // w_(jlo) / w_(jbd) = wm 2^we: the scans' products of mu/(j+1)
+  int we = 0;
   int jlo = int(jbd), jhi = int(jed);
   for (int pass = 0; pass < 400; ++pass) {
     const int n = jhi - jlo + 1;
@@ -296,26 +375,16 @@ __device__ inline __noinline__ Ncx2Val ncx2_sf_wave(double x, double nu, double 
     const int my_lo = jlo + lane * m, my_hi = min(jhi, my_lo + m - 1);
     Ncx2Tri T{1.0, 0.0, 1.0, 0};
     double sp = 0.0, sr = 0.0, sq = 0.0, sq2 = 0.0;
-    for (int j = my_lo; j <= my_hi; ++j) {
-      sp += T.p;
-      sr += T.r;
-      sq = fma(a + j, T.q, sq);
-      sq2 = fma((a + j) * (a + j - 1.0), T.q, sq2);
-      const double d = 1.0 / ((j + 1.0) * (a + j + 1.0));
-      const double rw = mu * (a + j + 1.0) * d, g = muy * d;
-      T.r = rw * (T.r + T.q);
-      T.p *= rw;
-      T.q *= g;
-      if (T.p > kNcx2Big || T.r > kNcx2Big || T.q > kNcx2Big) {
-        T.p *= kNcx2Small;
-        T.r *= kNcx2Small;
-        T.q *= kNcx2Small;
-        sp *= kNcx2Small;
-        sr *= kNcx2Small;
-        sq *= kNcx2Small;
-        sq2 *= kNcx2Small;
-        T.e += 600;
-      }
+    {
+      // the step factors mu/(j+1) and mu y/((j+1)(a+j+1)) fall with j: every
+      // entry grows by at most 2 g per step, g the larger factor at the bottom
+      const int cnt = my_hi - my_lo + 1;
+      const double jb = double(my_lo);
+      const double g = fmax(mu / (jb + 1.0), muy / ((jb + 1.0) * (a + jb + 1.0)));
+      if (cnt * (ilogb(fmin(fmax(2.0 * g, 1.0), 0x1p1000)) + 1) < 500)
+        ncx2_chunk_up<false>(jb, cnt, a, mu, muy, T, sp, sr, sq, sq2);
+      else
+        ncx2_chunk_up<true>(jb, cnt, a, mu, muy, T, sp, sr, sq, sq2);
     }
     const int es = T.e;
     ncx2_norm(T);
@@ -329,6 +398,11 @@ __device__ inline __noinline__ Ncx2Val ncx2_sf_wave(double x, double nu, double 
     ncx2_acc3(sf, pa, pb, Et, s1, s2, s3, e12);
     if (jed == 0.0) break;  // the single term j = 0
     {
+      wm *= all.p;
+      we += all.e;
+      const int kw = wm > 0.0 ? ilogb(wm) : 0;
+      wm = ldexp(wm, -kw);
+      we += kw;
       const double Gn = fma(all.p, G, all.r * c), cn = all.q * c;
       const double mx = fmax(Gn, cn);
       const int k = mx > 0.0 ? ilogb(mx) : 0;
@@ -341,10 +415,10 @@ __device__ inline __noinline__ Ncx2Val ncx2_sf_wave(double x, double nu, double 
       // remaining tail from jn: sum w_k Q_k <= w_jn r/(1-r), r = mu/(jn+1)
       const double r = mu / (jn + 1.0), rc = r * (y / (a + jn + 1.0));
       if (rc < 1.0) {
-        const double lsf = log(sf) + Et * 0.69314718055994531 + L;
-        const double log_tail = ncx2_logw(double(jn), mu) + log(r / (1.0 - r));
+        // w_jn r/(1-r) on the scale 2^Et e^L of the totals
+        const double tail = ncx2_scale(wm * (r / (1.0 - r)), lw - L + (we - Et) * 0.69314718055994531);
         const double Gr = ldexp(G, E - Et), cr = ldexp(c, E - Et);
-        if (log_tail <= log(1e-17) + lsf && Gr <= 1e-17 * sf && cr * rc / (1.0 - rc) <= 0.5e-17 * pa) break;
+        if (tail <= 1e-17 * sf && Gr <= 1e-17 * sf && cr * rc / (1.0 - rc) <= 0.5e-17 * pa) break;
       }
     }
     jlo = jn;
