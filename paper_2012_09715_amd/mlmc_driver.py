@@ -129,6 +129,22 @@ def _streams(k):
     return _STREAMS[:k]
 
 
+def warm_streams(job, n_streams=4):
+    """Runs `job` once on each of the n_streams pool streams (each from its own
+    thread): the library creates a stream's workspace on its first level call,
+    which should not fall inside a timed pass."""
+    def worker(st):
+        with torch.cuda.stream(st):
+            job()
+
+    threads = [threading.Thread(target=worker, args=(st,)) for st in _streams(n_streams)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+
+
 def run_concurrent(jobs, n_streams=4):
     """Runs zero-argument level calls on n_streams streams, one host thread
     per stream taking the next job in list order (put the dearest first); the
@@ -190,6 +206,7 @@ def run_estimators(model, params, L, eps, approx, seed, accs, alloc, n_streams=4
             time_ms[k] += r.ms
             calls[(l, k)] += (s,)
     # the same calls again, each estimator's levels concurrently, dearest first
+    warm_streams(lambda: level_call(model, params, 0, 2, A.KIND_APPROX, approx, seed, 0), n_streams)
     wall = {}
     same = True
     for name, kinds in (("hat", (A.KIND_EXACT,)), ("tilde", (A.KIND_APPROX, A.KIND_CORRECTION))):
