@@ -96,11 +96,26 @@ __host__ __device__ inline double ncx2_scale(double m, double ls) {
   return copysign(exp(log(fabs(m)) + ls), m);
 }
 
+__host__ __device__ inline __noinline__ double ncx2_lgamma(double x) { return lgamma(x); }
+
+// log Gamma(z): for z >= 16 Stirling's series through the z^-13 term (the
+// first omitted term is below 3e-20 there), else the library routine.
+__host__ __device__ inline double ncx2_lgamma_stirling(double z) {
+  if (!(z >= 16.0)) return ncx2_lgamma(z);
+  const double w = 1.0 / z, w2 = w * w;
+  const double s =
+      w * (1.0 / 12 + w2 * (-1.0 / 360 + w2 * (1.0 / 1260 + w2 * (-1.0 / 1680 + w2 * (1.0 / 1188 +
+                                                                  w2 * (-691.0 / 360360 + w2 * (1.0 / 156)))))));
+  return (z - 0.5) * log(z) - z + 0.91893853320467274 + s;  // 0.918.. = log(2 pi) / 2
+}
+
 // log w_j and log t_j.
 __host__ __device__ inline double ncx2_logw(double j, double mu) {
-  return mu > 0.0 ? -mu + j * log(mu) - lgamma(j + 1.0) : (j == 0.0 ? 0.0 : -1e308);
+  return mu > 0.0 ? -mu + j * log(mu) - ncx2_lgamma_stirling(j + 1.0) : (j == 0.0 ? 0.0 : -1e308);
 }
-__host__ __device__ inline double ncx2_logt(double A, double y, double ly) { return A * ly - y - lgamma(A + 1.0); }
+__host__ __device__ inline double ncx2_logt(double A, double y, double ly) {
+  return A * ly - y - ncx2_lgamma_stirling(A + 1.0);
+}
 
 // The carried terms start at O(1) (scaled by e^-L); whenever one exceeds
 // 2^600 every carried value and partial sum is multiplied by 2^-600 and the
@@ -263,8 +278,6 @@ __host__ __device__ inline __noinline__ double ncx2_guess(double t, bool upper, 
 // after it is of the order of the cube (square) of the step, far below the
 // FP64 resolution, so the confirming evaluation is skipped.  `iters`
 // receives the number of CDF evaluations.
-__host__ __device__ inline __noinline__ double ncx2_lgamma(double x) { return lgamma(x); }
-
 // The Halley step if usable, else the Newton step; `halley` tells which.
 __host__ __device__ inline double ncx2_step(double g, double dg, double d2g, bool& halley) {
   const double newton = g / dg;

@@ -147,17 +147,6 @@ __device__ inline double ncx2_series_wave(double A, double y, int lane) {
   return sum;
 }
 
-// log Gamma(z): for z >= 16 Stirling's series through the z^-13 term (the
-// first omitted term is below 3e-20 there), else the library routine.
-__host__ __device__ inline double ncx2_lgamma_stirling(double z) {
-  if (!(z >= 16.0)) return ncx2_lgamma(z);
-  const double w = 1.0 / z, w2 = w * w;
-  const double s =
-      w * (1.0 / 12 + w2 * (-1.0 / 360 + w2 * (1.0 / 1260 + w2 * (-1.0 / 1680 + w2 * (1.0 / 1188 +
-                                                                  w2 * (-691.0 / 360360 + w2 * (1.0 / 156)))))));
-  return (z - 0.5) * log(z) - z + 0.91893853320467274 + s;  // 0.918.. = log(2 pi) / 2
-}
-
 // log w_j (Poisson weight) and log t_A (as ncx2_logw, ncx2_logt), with the
 // two log-gamma values taken by two lanes at once.
 __device__ __forceinline__ void ncx2_logs_wave(double j, double A, double y, double ly, double mu, int lane,
