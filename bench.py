@@ -161,9 +161,9 @@ def chi2_sweep(A, torch, u, stream):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
         log("bench.py: only --gpus 1 is supported (the method's work shards by path/sample range; "
-            "a multi-GPU run is not part of this build)")
+            "multi-GPU runs are not implemented)")
         return 2
     import torch
     import paper_2012_09715_amd as A
