@@ -362,8 +362,10 @@ aicdf_status mlmc_allocate(uint32_t n_levels, double eps, const double* v_hat, c
  * central chi-squared CDFs (Abramowitz & Stegun 26.4.25, which Section 5
  * cites), summed outward from the Poisson mode with incomplete-gamma
  * recurrences; the root is found by safeguarded Halley steps (with the
- * density and its derivative from the same sweep) in log x on log C
- * (u <= 1/2) or in x on log(1 - C) (u > 1/2), inside a maintained bracket.
+ * density and its derivative from the same sweep) in log x on log C, or,
+ * for 1 - u < 2^-10 (any u > 1/2 when lambda > 4096), in x on log(1 - C)
+ * with 1 - C from the upward sweep,
+ * inside a maintained bracket.
  * u, lambda, x: device arrays of n doubles; nu > 0; lambda >= 0.
  * u = 0 gives 0, u = 1 gives +inf.  Batches of n <= 8192 run one inverse per
  * wavefront (the sweeps split over the 64 lanes, for latency); larger ones

@@ -261,9 +261,11 @@ __host__ __device__ inline __noinline__ double ncx2_guess(double t, bool upper, 
 //   upper: the Chernoff bound 1 - C(x) <= 2^(nu/2) e^(lambda/2) e^(-x/4)
 //          (moment generating function at s = 1/4), so
 //          x_hi = 2 nu log 2 + 2 lambda - 4 log(1-u) has 1 - C(x_hi) <= 1-u.
-// The target is given as a tail probability t in (0, 1/2]: u = t (lower
-// tail, upper = false) or 1 - u = t (upper tail, upper = true), so that
-// upper-tail targets below the FP64 spacing near 1 keep full precision.
+// The target is given as u = t (upper = false) or as the tail probability
+// 1 - u = t (upper = true), so that upper-tail targets below the FP64
+// spacing near 1 keep full precision; ncx2_icdf takes the upper form only for
+// 1 - u < 2^-10 (or lambda > 4096), where 1 - C computed from C would lose
+// digits, so that nearly every lane of a batch runs the same (downward) sweep.
 // lower: g(w) = log C(e^w) - log t in w = log x (the lower tail of C is
 //        close to a power of x, so g is close to linear in w),
 //        g' = x f / C,  g'' = g' + x^2 f' / C - g'^2;
@@ -305,7 +307,9 @@ __host__ __device__ inline double ncx2_solve(double t, bool upper, double nu, do
   double xlo = 2.0 * exp((lu + ncx2_lgamma(a + 1.0)) / a);
   double xhi = 2.0 * nu * 0.69314718055994531 + 2.0 * lam - 4.0 * lq;
   if (!(xhi > xlo * 1.001)) xhi = xlo * 1.001 + 1e-300;
-  double x = (x0 > xlo && x0 < xhi) ? x0 : ncx2_guess(t, upper, nu, lam);
+  // the built-in start takes the smaller tail probability
+  const bool ug = upper || t > 0.5;
+  double x = (x0 > xlo && x0 < xhi) ? x0 : ncx2_guess(upper || t <= 0.5 ? t : 1.0 - t, ug, nu, lam);
   if (!(x > xlo && x < xhi)) x = sqrt(xlo) * sqrt(xhi);
   int it = 0;
   if (!upper) {
@@ -383,13 +387,23 @@ __host__ __device__ inline double ncx2_icdf_tail(double t, bool upper, double nu
   return ncx2_solve(t, upper, nu, lam, Ncx2Seq{nu, lam}, iters, x0);
 }
 
+// Targets 1 - u below kNcx2UpperTail use the upper-tail form (1 - C by the
+// upward sweep), and so does every u > 1/2 when lambda > kNcx2UpperLam: there
+// the log-form weights carry exponents of size lambda log lambda, whose
+// rounding (relative ~1e-16 of them) is an error of C relative to C, and
+// would cost more than 1e-11 of x when only 1 - C is small.  All other
+// targets solve C(x) = u with the downward sweep, so that nearly every lane
+// of a batch runs the same loop.
+constexpr double kNcx2UpperTail = 0x1p-10;
+constexpr double kNcx2UpperLam = 4096.0;
+
 // C_nu^-1(u; lambda) for u in [0, 1]: 0 at u = 0, +inf at u = 1, NaN outside.
 // x0 > 0: an approximation of the root to start from.
 __host__ __device__ inline double ncx2_icdf(double u, double nu, double lam, int* iters = nullptr,
                                             double x0 = 0.0) {
   if (!(u > 0.0)) return u == 0.0 ? 0.0 : __builtin_nan("");
   if (!(u < 1.0)) return u == 1.0 ? __builtin_inf() : __builtin_nan("");
-  const bool upper = u > 0.5;
+  const bool upper = u > 0.5 && (1.0 - u < kNcx2UpperTail || lam > kNcx2UpperLam);
   return ncx2_icdf_tail(upper ? 1.0 - u : u, upper, nu, lam, iters, x0);
 }
 

@@ -202,7 +202,8 @@ def test_cir_table_split_determinism():
     assert np.array_equal(whole, np.concatenate([first, rest]))
     # one path per wavefront (<= 2048 paths): the same paths to FP64 rounding
     _, few = run_level(p, 4, 700, 2, tab, 8, 4000)
-    assert np.allclose(few, whole[4000:4700], rtol=1e-11, atol=1e-15)
+    scale = np.maximum(np.abs(whole[4000:4700, 1]), np.abs(whole[4000:4700, 2]))[:, None]
+    assert np.all(np.abs(few - whole[4000:4700]) <= 1e-11 * scale + 1e-15)
 
 
 def test_cir_table_errors():

@@ -69,6 +69,15 @@ def run(params, level, n, kind, sur, seed, offset=0):
     return s, out.cpu().numpy().reshape(n, 3)
 
 
+def same_paths(a, b, rel=1e-11):
+    """Per-path agreement of (Y, P_f, P_c) rows from two launch shapes,
+    relative to the row's functional scale max(|P_f|, |P_c|): Y is a
+    difference of the two and carries their absolute error, not a relative
+    one of its own."""
+    scale = np.maximum(np.maximum(np.abs(b[:, 1]), np.abs(b[:, 2])), 1e-300)[:, None]
+    return np.all(np.abs(a - b) <= rel * scale + 1e-15), np.max(np.abs(a - b) / scale)
+
+
 @pytest.mark.parametrize("functional", [0, 1])
 @pytest.mark.parametrize("level", [0, 2])
 def test_exact_kind_parity(functional, level):
@@ -106,7 +115,8 @@ def test_split_determinism_and_fallbacks(damped):
     # calls of <= 2048 paths run one path per wavefront, whose cooperative
     # exact inverse sums in another order: the same paths to FP64 rounding
     _, c = run(p, 2, 2000, 2, s, 5, 1000)
-    assert np.allclose(c, whole[1000:3000], rtol=1e-11, atol=1e-15)
+    ok, worst = same_paths(c, whole[1000:3000])
+    assert ok, worst
     st2 = A.mlmc_level_cir(p, 2, 6000, 2, s, 5)
     assert st["sum"] == st2["sum"] and st["fallbacks"] == st2["fallbacks"]
     # a surrogate whose range excludes every lambda falls back on every step
@@ -164,4 +174,5 @@ def test_thread_per_path_launch_parity(damped, kind):
     assert np.all(np.abs(got[pick, 1] - ref[1]) <= tol)
     assert np.all(np.abs(got[pick, 0] - ref[0]) <= tol)
     _, few = run(p, level, 300, kind, s, seed, 99900)
-    assert np.allclose(few, got[99900:100200], rtol=1e-11, atol=1e-15)
+    ok, worst = same_paths(few, got[99900:100200])
+    assert ok, worst
