@@ -25,7 +25,7 @@
 // of an MLMC allocation, where a level's time is the serial time of one
 // path) run one path per wavefront: all 64 lanes follow the same path and
 // evaluate each exact inverse together (ncx2_wave.hpp), and lane 0 keeps the
-// sums; no path waits for the Newton iterations of 63 others.  Every other
+// sums; no path waits for the root iterations of 63 others.  Every other
 // call runs one path per thread.
 // The coarse path of level l is the fine path
 // observed at even steps (exact in law), so only the functional differs:
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
         u24 = u24_from_word(hi);
       }
       // approximate step first: in CORRECTION its value, moved to the exact
-      // path's lambda, starts the exact inverse's Newton iteration
+      // path's lambda, starts the exact inverse's root iteration
       double x0 = 0.0;
       if (kSurr) {
         const float lam = vs * a.decayf / a.cf;

@@ -21,7 +21,7 @@
 // products w_j P_j (or w_j Q_j) and c_j on a running scale (below), so that
 // no factor underflows or overflows on the way.  The sweeps divide at most
 // once per term (the downward one not at all), and both are kept out of line
-// on the device so that the Newton driver around them stays small in
+// on the device so that the root driver around them stays small in
 // registers.
 #pragma once
 

@@ -23,7 +23,7 @@
 // where the series (continued fraction) that gives its first term converges
 // in a few dozen serial steps; passes continue past the first range while
 // the bound on the remaining head (tail) is not met.  The butterfly gives
-// every lane the same bits, so the Newton driver around it takes identical
+// every lane the same bits, so the root driver around it takes identical
 // decisions in all lanes.
 #pragma once
 
@@ -427,7 +427,7 @@ struct Ncx2Wave {
 
 // C_nu^-1(u; lambda) computed by the whole wavefront; every lane must pass
 // the same (u, nu, lambda, x0) and receives the same result.  x0 > 0: an
-// approximation of the root to start the Newton iteration from.
+// approximation of the root to start the iteration from.
 __device__ inline double ncx2_icdf_wave(double u, double nu, double lam, double x0 = 0.0) {
   if (!(u > 0.0)) return u == 0.0 ? 0.0 : __builtin_nan("");
   if (!(u < 1.0)) return u == 1.0 ? __builtin_inf() : __builtin_nan("");
