@@ -71,7 +71,7 @@ __device__ __forceinline__ uint16_t f32_to_f16_bits(float x) {
 //   z <- z - r / (1 + z r / 2),  r = f / phi(z).
 // Phi(z) - q is formed as erf(z/sqrt2)/2 - (q - 1/2) when q >= 1/4 (the
 // subtraction is exact there) and as erfc(-z/sqrt2)/2 - q otherwise.
-__device__ __forceinline__ double exact_phi_inv(double u) {
+__host__ __device__ __forceinline__ double exact_phi_inv(double u) {
   const bool upper = u > 0.5;
   const double q = upper ? 1.0 - u : u;
   const double t = sqrt(-2.0 * log(q));

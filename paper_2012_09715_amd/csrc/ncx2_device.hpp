@@ -254,6 +254,26 @@ __host__ __device__ inline __noinline__ double ncx2_guess(double t, bool upper, 
   return rho * k * b * b * b;
 }
 
+// Start for large lambda: Sankaran's approximation (the comparator of
+// Section 5.1) in FP64 around the exact normal quantile of the target,
+//   c1 = 1 - (2/3)(nu+lambda)(nu+3 lambda)/(nu+2 lambda)^2,
+//   c2 = (nu+2 lambda)/(nu+lambda)^2,  c3 = (c1-1)(1-3 c1),
+//   B = 1 + c1 c2 (c1 - 1 + (2-c1) c2 c3/2) + c1 sqrt(2 c2)(1 + c2 c3/2) z,
+//   x = (nu+lambda) B^(1/c1);
+// its relative error falls from ~1e-4 at lambda = 100 to ~1e-6 at 1000
+// (against ~3e-4 for the scaled central chi-squared start), which leaves one
+// or two Halley steps.  Returns 0 where B <= 0 (far lower tail).
+__host__ __device__ inline __noinline__ double ncx2_sankaran_start(double t, bool upper, double nu, double lam) {
+  const double z = upper ? -exact_phi_inv(t) : exact_phi_inv(t);
+  const double kl = nu + lam, k2l = nu + 2.0 * lam, k3l = nu + 3.0 * lam;
+  const double c1 = 1.0 - (2.0 / 3.0) * kl * k3l / (k2l * k2l);
+  const double c2 = k2l / (kl * kl);
+  const double c3 = (c1 - 1.0) * (1.0 - 3.0 * c1);
+  const double B = 1.0 + c1 * c2 * (c1 - 1.0 + 0.5 * (2.0 - c1) * c2 * c3) +
+                   c1 * sqrt(2.0 * c2) * (1.0 + 0.5 * c2 * c3) * z;
+  return B > 0.0 ? kl * pow(B, 1.0 / c1) : 0.0;
+}
+
 // Inverse CDF by safeguarded Halley steps, inside a bracket that is valid
 // before any evaluation:
 //   lower: C(x) <= P(a, x/2) <= (x/2)^a / Gamma(a+1), so
@@ -307,9 +327,12 @@ __host__ __device__ inline double ncx2_solve(double t, bool upper, double nu, do
   double xlo = 2.0 * exp((lu + ncx2_lgamma(a + 1.0)) / a);
   double xhi = 2.0 * nu * 0.69314718055994531 + 2.0 * lam - 4.0 * lq;
   if (!(xhi > xlo * 1.001)) xhi = xlo * 1.001 + 1e-300;
-  // the built-in start takes the smaller tail probability
-  const bool ug = upper || t > 0.5;
-  double x = (x0 > xlo && x0 < xhi) ? x0 : ncx2_guess(upper || t <= 0.5 ? t : 1.0 - t, ug, nu, lam);
+  // built-in start: Sankaran's approximation from lambda = 100 on, else (or
+  // outside the bracket) the scaled central chi-squared one on the smaller
+  // tail probability
+  double x = x0;
+  if (!(x > xlo && x < xhi) && lam >= 100.0) x = ncx2_sankaran_start(t, upper, nu, lam);
+  if (!(x > xlo && x < xhi)) x = ncx2_guess(upper || t <= 0.5 ? t : 1.0 - t, upper || t > 0.5, nu, lam);
   if (!(x > xlo && x < xhi)) x = sqrt(xlo) * sqrt(xhi);
   int it = 0;
   if (!upper) {
