@@ -277,3 +277,23 @@ def test_cir_table_nested_mlmc_gain(degree):
     assert abs(r["theta_tilde"] - ref) < 5 * r["se_tilde"] + 1e-12
     for p in r["per_level"]:
         assert p["v4"] < (2.0 ** -8 if degree == 1 else 2.0 ** -12) * p["v_hat"], p
+
+
+@pytest.mark.parametrize("degree", [1, 3])
+def test_transform_benchmark_size_sampled(degree):
+    # the benchmark's workload: 2^28 device-resident pairs (u on the u24 grid
+    # from the device stream, log lambda uniform on [-8, 10]) in the
+    # benchmark's launch, checked on a sample of outputs
+    tab, otab = tables(NU_CIR, degree)
+    n = 1 << 28
+    u = torch.empty(n, dtype=torch.float32, device=DEV)
+    A.uniform_fill(u, 20201217, 3, 0)
+    g = torch.Generator(device=DEV)
+    g.manual_seed(20201217)
+    lam = torch.exp(torch.rand(n, device=DEV, generator=g) * 18.0 - 8.0)
+    x = torch.empty(n, dtype=torch.float32, device=DEV)
+    A.approx_ncx2_icdf(tab, u, lam, x=x)
+    pick = np.unique(np.concatenate([np.random.default_rng(degree).integers(0, n, 40_000), [0, n - 1]]))
+    idx = torch.from_numpy(pick).to(DEV)
+    check_parity(otab, NU_CIR, u[idx].cpu().numpy(), lam[idx].cpu().numpy(), x[idx].cpu().numpy())
+    del u, lam, x

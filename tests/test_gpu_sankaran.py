@@ -43,6 +43,26 @@ def test_transform_parity(nu):
     assert not bad.any(), (int(bad.sum()), u[bad][:4], lam[bad][:4], x[bad][:4], ref[bad][:4])
 
 
+def test_transform_benchmark_size_sampled():
+    # 2^28 device-resident pairs in the benchmark's launch, checked on a sample
+    n = 1 << 28
+    u = torch.empty(n, dtype=torch.float32, device=DEV)
+    A.uniform_fill(u, 20201217, 3, 0)
+    g = torch.Generator(device=DEV)
+    g.manual_seed(20201217)
+    lam = torch.exp(torch.rand(n, device=DEV, generator=g) * 18.0 - 8.0)
+    x = torch.empty(n, dtype=torch.float32, device=DEV)
+    A.approx_ncx2_sankaran(NU_CIR, u, lam, x=x)
+    pick = torch.from_numpy(np.unique(np.concatenate([np.random.default_rng(4).integers(0, n, 40_000),
+                                                      [0, n - 1]]))).to(DEV)
+    us, ls = u[pick].cpu().numpy(), lam[pick].cpu().numpy()
+    xs = x[pick].cpu().numpy().astype(np.float64)
+    ref = sankaran.approx_x(us.astype(np.float64), NU_CIR, ls.astype(np.float64))
+    tol = 1e-5 * ref + 1e-6 * (NU_CIR + ls)
+    assert np.all(np.abs(xs - ref) <= tol)
+    del u, lam, x
+
+
 def test_transform_errors_and_nan():
     u = torch.rand(16, device=DEV)
     lam = torch.rand(16, device=DEV)
