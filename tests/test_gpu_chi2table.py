@@ -297,3 +297,19 @@ def test_transform_benchmark_size_sampled(degree):
     idx = torch.from_numpy(pick).to(DEV)
     check_parity(otab, NU_CIR, u[idx].cpu().numpy(), lam[idx].cpu().numpy(), x[idx].cpu().numpy())
     del u, lam, x
+
+
+def test_cir_table_config_size_sampled():
+    # a level of the benchmark's CIR configuration: 10^6 paths at level 6 (one
+    # path per thread), correction kind, sampled paths against the oracle
+    tab, otab = tables(NU_CIR, 1)
+    p = dict(CIR, functional=1)
+    n, level, seed = 1_000_000, 6, 19
+    st, got = run_level(p, level, n, 2, tab, seed)
+    pick = np.unique(np.concatenate([np.random.default_rng(2).integers(0, n, 20), [0, n - 1]]))
+    ref = cir.level_replay(p, level, 2, seed, pick, surrogate_x=oracle_table_x(otab, NU_CIR))
+    N = 1 << level
+    scale = np.maximum(np.abs(ref[1]), 1e-3)
+    assert np.all(np.abs(got[pick, 1] - ref[1]) <= 2e-4 * N * scale)
+    assert np.all(np.abs(got[pick, 0] - ref[0]) <= 2e-4 * N * scale)
+    assert st["n"] == n

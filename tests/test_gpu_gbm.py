@@ -225,3 +225,17 @@ def test_rademacher_table_and_variance():
         v = lambda s: s["sum"][1] / n - (s["sum"][0] / n) ** 2
         r = np.log2(v(s4) / v(s2))
         assert -2.0 < r < -0.3, (level, r)
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_config_size_sampled(lin16, scheme):
+    # a level of the benchmark's configuration: 10^6 paths at level 8 (one
+    # path per thread, the full grid), checked on paths sampled across the range
+    n, level, seed = 1_000_000, 8, 77
+    p = dict(GBM, scheme=scheme, payoff=1)
+    pick = np.unique(np.concatenate([np.random.default_rng(scheme).integers(0, n, 60), [0, 1, n - 2, n - 1]]))
+    for kind in (0, 1, 2):
+        s, got = run_paths(p, level, n, kind, lin16[0], seed)
+        ref = gbm.level_replay(p, level, kind, seed, pick, table=lin16[1])
+        check_paths(got[pick], ref, kind, level)
+        assert s["n"] == n
