@@ -71,6 +71,8 @@ __device__ __forceinline__ uint16_t f32_to_f16_bits(float x) {
 //   z <- z - r / (1 + z r / 2),  r = f / phi(z).
 // Phi(z) - q is formed as erf(z/sqrt2)/2 - (q - 1/2) when q >= 1/4 (the
 // subtraction is exact there) and as erfc(-z/sqrt2)/2 - q otherwise.
+// ITERS = 1 stops after one Halley step (|error| ~1e-10: a starting value).
+template <int ITERS = 2>
 __host__ __device__ __forceinline__ double exact_phi_inv(double u) {
   const bool upper = u > 0.5;
   const double q = upper ? 1.0 - u : u;
@@ -80,7 +82,7 @@ __host__ __device__ __forceinline__ double exact_phi_inv(double u) {
   double z = num / den - t;
   const bool central = q >= 0.25;
 #pragma unroll
-  for (int it = 0; it < 2; ++it) {
+  for (int it = 0; it < ITERS; ++it) {
     const double f = central ? 0.5 * erf(z * 0.70710678118654752440) - (q - 0.5)
                              : 0.5 * erfc(-z * 0.70710678118654752440) - q;
     const double pdf = 0.39894228040143267794 * exp(-0.5 * z * z);
