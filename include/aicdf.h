@@ -289,9 +289,12 @@ typedef struct aicdf_surrogate aicdf_surrogate;
  * lambda_n = v_n e^(-kappa delta) / c,  v_(n+1) = c C_nu^-1(U_n; lambda_n).
  * The coarse path is the fine path observed at even steps.  kind:
  *   EXACT       exact inverse (FP64), two-word u53 draws
- *   APPROX      the surrogate network (required), one-word u24 draws; steps
- *               whose log(lambda) lies outside the surrogate's range use the
- *               exact inverse on the same u24 (counted in out->fallbacks)
+ *   APPROX      the surrogate network (required), one-word u24 draws; below
+ *               the surrogate's log(lambda) range (lambda = 0 included) the
+ *               network is evaluated at the range's lower end (P depends on
+ *               lambda only through O(lambda) terms there); steps whose
+ *               log(lambda) lies above the range use the exact inverse on
+ *               the same u24 (counted in out->fallbacks)
  *   CORRECTION  both on two-word draws (surrogate on the u24 of the high word)
  *   TWOWAY      both on the draws of CORRECTION, fine paths only:
  *               Y = P^_f - P~_f, sum_pf over P^_f, sum_pc over P~_f

@@ -6,8 +6,12 @@
 //   APX_SURROGATE  P~ = MLP(D(U), g(log lambda)), x = lambda + nu +
 //                  2 sqrt(lambda+nu) P~, clamped at 0.  The network call is a
 //                  wave-wide matrix-core routine, so all 64 lanes step
-//                  together; a lane whose log lambda lies outside the trained
-//                  range takes the exact inverse on the same u24 instead
+//                  together.  Below the trained log-lambda range (lambda = 0
+//                  included, after a step clamped at 0) the network is
+//                  evaluated at the range's lower end: P depends on lambda
+//                  only through O(lambda) terms there, far below the
+//                  network's own error.  A lane whose log lambda lies above
+//                  the range takes the exact inverse on the same u24 instead
 //                  (counted).
 //   APX_POLY1/3    Section 5.1's piecewise-polynomial approximation (two
 //                  dyadic half tables per knot, linear interpolation in
@@ -163,8 +167,8 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
       if (kSurr) {
         const float lam = vs * a.decayf / a.cf;
         const float ll = lam > 0.0f ? __logf(lam) : -1e30f;
-        const bool inr = ll >= a.lo && ll <= a.hi;
-        const float g = inr ? mlp_g(ll, a.lo, a.inv_span2) : 0.0f;
+        const bool inr = ll <= a.hi;
+        const float g = inr ? mlp_g(fmaxf(ll, a.lo), a.lo, a.inv_span2) : 0.0f;
         const float Pt = mlp_wave_forward(L, A, dyadic_w16(u24, tab), g);  // all lanes
         float x;
         if (inr) {

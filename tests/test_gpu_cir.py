@@ -51,9 +51,12 @@ def oracle_surrogate_x(q):
         lam = np.asarray(lam, float)
         with np.errstate(divide="ignore"):
             ll = np.where(lam > 0, np.log(np.where(lam > 0, lam, 1.0)), -np.inf)
-        inr = (ll >= LO) & (ll <= HI)
+        # below the range (lambda = 0 included) the network at the lower end;
+        # above it the exact inverse
+        inr = ll <= HI
+        llc = np.where(inr, np.maximum(ll, LO), 0.0)
         w = dyadic_transform_f32(CUBIC, u.astype(np.float32))[0].astype(np.float64)
-        P = mlp.forward(q, w, np.where(inr, mlp.g_feature(np.where(inr, ll, 0.0), LO, HI), 0.0), bf16=True)
+        P = mlp.forward(q, w, np.where(inr, mlp.g_feature(llc, LO, HI), 0.0), bf16=True)
         s = lam + NU
         x = np.maximum(s + 2 * np.sqrt(s) * P, 0.0)
         out = x.copy()
@@ -119,10 +122,14 @@ def test_split_determinism_and_fallbacks(damped):
     assert ok, worst
     st2 = A.mlmc_level_cir(p, 2, 6000, 2, s, 5)
     assert st["sum"] == st2["sum"] and st["fallbacks"] == st2["fallbacks"]
-    # a surrogate whose range excludes every lambda falls back on every step
-    narrow = A.Surrogate.create(NU, 50.0, 51.0, seed=2)
-    sn = A.mlmc_level_cir(p, 2, 1000, 1, narrow, 5)
+    # a surrogate whose range lies below every lambda falls back on every
+    # step; one whose range lies above every lambda never does (the network
+    # is evaluated at its lower end)
+    low = A.Surrogate.create(NU, -60.0, -59.0, seed=2)
+    sn = A.mlmc_level_cir(p, 2, 1000, 1, low, 5)
     assert sn["fallbacks"] == 1000 * 4
+    high = A.Surrogate.create(NU, 50.0, 51.0, seed=2)
+    assert A.mlmc_level_cir(p, 2, 1000, 1, high, 5)["fallbacks"] == 0
 
 
 def test_exact_mean_and_variance():
