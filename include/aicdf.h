@@ -345,6 +345,43 @@ aicdf_status mlmc_level_cir_sankaran(const aicdf_cir_params* params, uint32_t le
                                      int32_t kind, uint64_t seed, uint64_t path_offset,
                                      aicdf_level_sums* out, double* path_out, void* stream);
 
+/* Stream-ordered variants of the five level calls (Section 4.1's estimators
+ * are sums over many independent level calls; these let one host thread
+ * spread them over several streams).  Same arguments, checks, kernels and
+ * per-path values as the synchronous call, except that the sums go to
+ * sums_dev instead of a host struct: 8 doubles of device memory on the
+ * current device, 8-byte aligned, owned by the caller, written by the device
+ * in stream order as
+ *   [0..3] sum Y, Y^2, Y^3, Y^4   [4] sum P_f   [5] sum P_c
+ *   [6] fallbacks (exact integer)  [7] n_paths
+ * bit-identical to the synchronous call's fields.  The call returns once the
+ * work is enqueued: it neither waits for the device nor times the level
+ * kernel.  sums_dev, path_out and the table or surrogate must stay valid
+ * until `stream` has passed the call.  Calls on one stream use its workspace
+ * one after another in stream order (no host wait between them); calls on
+ * different streams run concurrently.  A zero-path call enqueues all-zero
+ * sums.  Argument errors are returned before anything is enqueued.
+ * Errors: EINVAL, ERANGE, EHIP, ENOMEM. */
+aicdf_status mlmc_level_gbm_async(const aicdf_gbm_params* params, uint32_t level, uint64_t n_paths,
+                                  int32_t kind, const aicdf_table* approx, uint64_t seed,
+                                  uint64_t path_offset, double* sums_dev, double* path_out,
+                                  void* stream);
+aicdf_status mlmc_level_cir_async(const aicdf_cir_params* params, uint32_t level, uint64_t n_paths,
+                                  int32_t kind, const aicdf_surrogate* approx, uint64_t seed,
+                                  uint64_t path_offset, double* sums_dev, double* path_out,
+                                  void* stream);
+aicdf_status mlmc_level_cir_table_async(const aicdf_cir_params* params, uint32_t level,
+                                        uint64_t n_paths, int32_t kind, const aicdf_chi2_table* table,
+                                        uint64_t seed, uint64_t path_offset, double* sums_dev,
+                                        double* path_out, void* stream);
+aicdf_status mlmc_level_cir_em_async(const aicdf_cir_params* params, uint32_t level, uint64_t n_paths,
+                                     int32_t kind, uint64_t seed, uint64_t path_offset,
+                                     double* sums_dev, double* path_out, void* stream);
+aicdf_status mlmc_level_cir_sankaran_async(const aicdf_cir_params* params, uint32_t level,
+                                           uint64_t n_paths, int32_t kind, uint64_t seed,
+                                           uint64_t path_offset, double* sums_dev, double* path_out,
+                                           void* stream);
+
 /* Optimal allocation of the nested estimator at RMSE eps (Section 4.1):
  *   T^ = 2 eps^-2 (sum_l sqrt(v^_l c^_l))^2,
  *   T~ = 2 eps^-2 (sum_l sqrt(v~_l c~_l) + sqrt(V~_l C~_l))^2,

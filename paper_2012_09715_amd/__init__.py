@@ -221,6 +221,67 @@ def mlmc_level_cir_sankaran(params, level, n_paths, kind, seed=0, path_offset=0,
     return _sums_dict(out)
 
 
+def _sums_dev(sums):
+    if not isinstance(sums, torch.Tensor) or sums.dtype != torch.float64 or sums.numel() < 8:
+        raise AicdfError(-1, "sums must be a float64 CUDA tensor of at least 8 elements")
+    return _dev(sums, "sums")
+
+
+def sums_dict(row):
+    """The 8 doubles a stream-ordered level call writes (host array or tensor),
+    as the synchronous calls' result dict (no device time: kernel_ms None)."""
+    r = [float(v) for v in (row.tolist() if hasattr(row, "tolist") else row)]
+    return {"n": r[7], "sum": r[0:4], "sum_pf": r[4], "sum_pc": r[5], "kernel_ms": None, "fallbacks": int(r[6])}
+
+
+def mlmc_level_gbm_async(params, level, n_paths, kind, table, seed, path_offset, sums, path_out=None, stream=None):
+    """Stream-ordered mlmc_level_gbm: enqueues the level on `stream` (default:
+    the current stream) and returns; the device writes the 8 sums into `sums`
+    (a float64 CUDA tensor).  `table`, `sums` and `path_out` must stay alive
+    until the stream has passed the call."""
+    p = GbmParams(params["S0"], params["r"], params["sigma"], params["T"], params.get("K", 1.0),
+                  int(params.get("scheme", 0)), int(params.get("payoff", 0)))
+    po = _dev(path_out, "path_out") if path_out is not None else None
+    check(lib.mlmc_level_gbm_async(C.byref(p), level, n_paths, kind, table.handle if table is not None else None,
+                                   seed, path_offset, _sums_dev(sums), po, _stream(stream)))
+
+
+def mlmc_level_cir_async(params, level, n_paths, kind, surrogate, seed, path_offset, sums, path_out=None,
+                         stream=None):
+    """Stream-ordered mlmc_level_cir (see mlmc_level_gbm_async)."""
+    p = _cir_params(params)
+    po = _dev(path_out, "path_out") if path_out is not None else None
+    check(lib.mlmc_level_cir_async(C.byref(p), level, n_paths, kind,
+                                   surrogate.handle if surrogate is not None else None, seed, path_offset,
+                                   _sums_dev(sums), po, _stream(stream)))
+
+
+def mlmc_level_cir_table_async(params, level, n_paths, kind, table, seed, path_offset, sums, path_out=None,
+                               stream=None):
+    """Stream-ordered mlmc_level_cir_table (see mlmc_level_gbm_async)."""
+    p = _cir_params(params)
+    po = _dev(path_out, "path_out") if path_out is not None else None
+    check(lib.mlmc_level_cir_table_async(C.byref(p), level, n_paths, kind, table.handle if table is not None else None,
+                                         seed, path_offset, _sums_dev(sums), po, _stream(stream)))
+
+
+def mlmc_level_cir_em_async(params, level, n_paths, kind, seed, path_offset, sums, path_out=None, stream=None):
+    """Stream-ordered mlmc_level_cir_em (see mlmc_level_gbm_async)."""
+    p = _cir_params(params)
+    po = _dev(path_out, "path_out") if path_out is not None else None
+    check(lib.mlmc_level_cir_em_async(C.byref(p), level, n_paths, kind, seed, path_offset, _sums_dev(sums), po,
+                                      _stream(stream)))
+
+
+def mlmc_level_cir_sankaran_async(params, level, n_paths, kind, seed, path_offset, sums, path_out=None,
+                                  stream=None):
+    """Stream-ordered mlmc_level_cir_sankaran (see mlmc_level_gbm_async)."""
+    p = _cir_params(params)
+    po = _dev(path_out, "path_out") if path_out is not None else None
+    check(lib.mlmc_level_cir_sankaran_async(C.byref(p), level, n_paths, kind, seed, path_offset, _sums_dev(sums),
+                                            po, _stream(stream)))
+
+
 def approx_ncx2_sankaran(nu, u, lam, x=None, stream=None):
     """The Sankaran approximation x~(u; lambda) in FP32 (u, lambda: float32 device tensors)."""
     if u.dtype != torch.float32 or lam.dtype != torch.float32:

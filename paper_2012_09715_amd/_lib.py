@@ -69,6 +69,11 @@ _PROTOS = {
     "mlmc_level_cir_em": (status, [C.POINTER(CirParams), u32, u64, i32, u64, u64, C.POINTER(LevelSums), vp, vp]),
     "mlmc_level_cir_sankaran": (status, [C.POINTER(CirParams), u32, u64, i32, u64, u64, C.POINTER(LevelSums), vp,
                                          vp]),
+    "mlmc_level_gbm_async": (status, [C.POINTER(GbmParams), u32, u64, i32, vp, u64, u64, vp, vp, vp]),
+    "mlmc_level_cir_async": (status, [C.POINTER(CirParams), u32, u64, i32, vp, u64, u64, vp, vp, vp]),
+    "mlmc_level_cir_table_async": (status, [C.POINTER(CirParams), u32, u64, i32, vp, u64, u64, vp, vp, vp]),
+    "mlmc_level_cir_em_async": (status, [C.POINTER(CirParams), u32, u64, i32, u64, u64, vp, vp, vp]),
+    "mlmc_level_cir_sankaran_async": (status, [C.POINTER(CirParams), u32, u64, i32, u64, u64, vp, vp, vp]),
     "approx_ncx2_sankaran": (status, [dbl, sz, vp, vp, vp, vp]),
     "aicdf_surrogate_create": (status, [dbl, dbl, dbl, u64, C.POINTER(vp)]),
     "aicdf_surrogate_destroy": (None, [vp]),

@@ -285,8 +285,10 @@ void launch_kind(int kind, int func, const CirArgs& a, unsigned grid, size_t lds
 
 // Checks shared by both approximations; fills the common arguments.
 aicdf_status cir_setup(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths, int32_t kind, uint64_t seed,
-                       uint64_t path_offset, aicdf_level_sums* out, CirArgs& a, unsigned& grid) {
-  if (!prm || !out) return fail(AICDF_EINVAL, "params and out must be non-NULL");
+                       uint64_t path_offset, const LevelOut& out, CirArgs& a, unsigned& grid) {
+  if (!prm) return fail(AICDF_EINVAL, "params must be non-NULL");
+  aicdf_status st = check_level_out(out);
+  if (st != AICDF_OK) return st;
   if (level > 12) return fail(AICDF_ERANGE, "level %u > 12", level);
   if (kind < 0 || kind > 3) return fail(AICDF_EINVAL, "kind must be 0, 1, 2 or 3");
   if (prm->functional < 0 || prm->functional > 1 || prm->reserved != 0)
@@ -324,20 +326,15 @@ aicdf_status cir_setup(const aicdf_cir_params* prm, uint32_t level, uint64_t n_p
   return AICDF_OK;
 }
 
-}  // namespace
-
-extern "C" aicdf_status mlmc_level_cir(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths, int32_t kind,
-                                       const aicdf_surrogate* sur, uint64_t seed, uint64_t path_offset,
-                                       aicdf_level_sums* out, double* path_out, void* stream) {
+aicdf_status cir_level_surrogate(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths, int32_t kind,
+                                 const aicdf_surrogate* sur, uint64_t seed, uint64_t path_offset, const LevelOut& out,
+                                 double* path_out, void* stream) {
   CirArgs a;
   unsigned grid = 0;
   aicdf_status st = cir_setup(prm, level, n_paths, kind, seed, path_offset, out, a, grid);
   if (st != AICDF_OK) return st;
   if (kind != AICDF_KIND_EXACT && !sur) return fail(AICDF_EINVAL, "the approximate kinds need a surrogate");
-  if (n_paths == 0) {
-    *out = aicdf_level_sums{};
-    return ok();
-  }
+  if (n_paths == 0) return empty_level(static_cast<hipStream_t>(stream), out);
   double snu = a.nu, lo = 0.0, hi = 0.0;
   int sdev = 0, dev = 0;
   AICDF_HIP(hipGetDevice(&dev));
@@ -361,26 +358,22 @@ extern "C" aicdf_status mlmc_level_cir(const aicdf_cir_params* prm, uint32_t lev
   const float* p = sur ? surrogate_params(sur) : nullptr;
   const uint16_t* w2 = sur ? surrogate_w2b(sur) : nullptr;
   const f32x4* wt = sur ? reinterpret_cast<const f32x4*>(surrogate_wtab(sur)) : nullptr;
-  AICDF_HIP(hipMemsetAsync(ws->counter, 0, sizeof(unsigned long long), s));
-  AICDF_HIP(hipEventRecord(ws->ev0, s));
+  st = begin_level(ws, s, out);
+  if (st != AICDF_OK) return st;
   launch_kind<APX_SURROGATE>(kind, prm->functional, a, grid, 0, s, p, w2, wt, ws->partials, path_out, ws->counter);
   AICDF_HIP(hipGetLastError());
   return finish_level(ws, grid, s, double(n_paths), out);
 }
 
-extern "C" aicdf_status mlmc_level_cir_table(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths,
-                                             int32_t kind, const aicdf_chi2_table* tab, uint64_t seed,
-                                             uint64_t path_offset, aicdf_level_sums* out, double* path_out,
-                                             void* stream) {
+aicdf_status cir_level_table(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths, int32_t kind,
+                             const aicdf_chi2_table* tab, uint64_t seed, uint64_t path_offset, const LevelOut& out,
+                             double* path_out, void* stream) {
   CirArgs a;
   unsigned grid = 0;
   aicdf_status st = cir_setup(prm, level, n_paths, kind, seed, path_offset, out, a, grid);
   if (st != AICDF_OK) return st;
   if (kind != AICDF_KIND_EXACT && !tab) return fail(AICDF_EINVAL, "the approximate kinds need a table");
-  if (n_paths == 0) {
-    *out = aicdf_level_sums{};
-    return ok();
-  }
+  if (n_paths == 0) return empty_level(static_cast<hipStream_t>(stream), out);
   int dev = 0;
   AICDF_HIP(hipGetDevice(&dev));
   Chi2Info ti{};
@@ -404,8 +397,8 @@ extern "C" aicdf_status mlmc_level_cir_table(const aicdf_cir_params* prm, uint32
   if (st != AICDF_OK) return st;
   std::lock_guard<std::mutex> lock(ws->mu);
   const auto* wt = static_cast<const f32x4*>(ti.dev_rows);
-  AICDF_HIP(hipMemsetAsync(ws->counter, 0, sizeof(unsigned long long), s));
-  AICDF_HIP(hipEventRecord(ws->ev0, s));
+  st = begin_level(ws, s, out);
+  if (st != AICDF_OK) return st;
   if (kind == AICDF_KIND_EXACT || ti.degree == 1)
     launch_kind<APX_POLY1>(kind, prm->functional, a, grid, lds, s, nullptr, nullptr, wt, ws->partials, path_out,
                            ws->counter);
@@ -416,50 +409,107 @@ extern "C" aicdf_status mlmc_level_cir_table(const aicdf_cir_params* prm, uint32
   return finish_level(ws, grid, s, double(n_paths), out);
 }
 
-extern "C" aicdf_status mlmc_level_cir_em(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths, int32_t kind,
-                                          uint64_t seed, uint64_t path_offset, aicdf_level_sums* out,
-                                          double* path_out, void* stream) {
+aicdf_status cir_level_em(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths, int32_t kind,
+                          uint64_t seed, uint64_t path_offset, const LevelOut& out, double* path_out, void* stream) {
   CirArgs a;
   unsigned grid = 0;
   aicdf_status st = cir_setup(prm, level, n_paths, kind, seed, path_offset, out, a, grid);
   if (st != AICDF_OK) return st;
-  if (n_paths == 0) {
-    *out = aicdf_level_sums{};
-    return ok();
-  }
+  if (n_paths == 0) return empty_level(static_cast<hipStream_t>(stream), out);
   auto s = static_cast<hipStream_t>(stream);
   Workspace* ws = nullptr;
   st = get_workspace(s, &ws);
   if (st != AICDF_OK) return st;
   std::lock_guard<std::mutex> lock(ws->mu);
-  AICDF_HIP(hipMemsetAsync(ws->counter, 0, sizeof(unsigned long long), s));
-  AICDF_HIP(hipEventRecord(ws->ev0, s));
+  st = begin_level(ws, s, out);
+  if (st != AICDF_OK) return st;
   launch_kind<APX_EM>(kind, prm->functional, a, grid, 0, s, nullptr, nullptr, nullptr, ws->partials, path_out,
                       ws->counter);
   AICDF_HIP(hipGetLastError());
   return finish_level(ws, grid, s, double(n_paths), out);
 }
 
-extern "C" aicdf_status mlmc_level_cir_sankaran(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths,
-                                                int32_t kind, uint64_t seed, uint64_t path_offset,
-                                                aicdf_level_sums* out, double* path_out, void* stream) {
+aicdf_status cir_level_sankaran(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths, int32_t kind,
+                                uint64_t seed, uint64_t path_offset, const LevelOut& out, double* path_out,
+                                void* stream) {
   CirArgs a;
   unsigned grid = 0;
   aicdf_status st = cir_setup(prm, level, n_paths, kind, seed, path_offset, out, a, grid);
   if (st != AICDF_OK) return st;
-  if (n_paths == 0) {
-    *out = aicdf_level_sums{};
-    return ok();
-  }
+  if (n_paths == 0) return empty_level(static_cast<hipStream_t>(stream), out);
   auto s = static_cast<hipStream_t>(stream);
   Workspace* ws = nullptr;
   st = get_workspace(s, &ws);
   if (st != AICDF_OK) return st;
   std::lock_guard<std::mutex> lock(ws->mu);
-  AICDF_HIP(hipMemsetAsync(ws->counter, 0, sizeof(unsigned long long), s));
-  AICDF_HIP(hipEventRecord(ws->ev0, s));
+  st = begin_level(ws, s, out);
+  if (st != AICDF_OK) return st;
   launch_kind<APX_SANKARAN>(kind, prm->functional, a, grid, 0, s, nullptr, nullptr, nullptr, ws->partials, path_out,
                             ws->counter);
   AICDF_HIP(hipGetLastError());
   return finish_level(ws, grid, s, double(n_paths), out);
+}
+
+}  // namespace
+
+extern "C" aicdf_status mlmc_level_cir(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths, int32_t kind,
+                                       const aicdf_surrogate* sur, uint64_t seed, uint64_t path_offset,
+                                       aicdf_level_sums* out, double* path_out, void* stream) {
+  if (!out) return fail(AICDF_EINVAL, "out must be non-NULL");
+  return cir_level_surrogate(prm, level, n_paths, kind, sur, seed, path_offset, LevelOut{out, nullptr}, path_out,
+                             stream);
+}
+
+extern "C" aicdf_status mlmc_level_cir_table(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths,
+                                             int32_t kind, const aicdf_chi2_table* tab, uint64_t seed,
+                                             uint64_t path_offset, aicdf_level_sums* out, double* path_out,
+                                             void* stream) {
+  if (!out) return fail(AICDF_EINVAL, "out must be non-NULL");
+  return cir_level_table(prm, level, n_paths, kind, tab, seed, path_offset, LevelOut{out, nullptr}, path_out, stream);
+}
+
+extern "C" aicdf_status mlmc_level_cir_em(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths, int32_t kind,
+                                          uint64_t seed, uint64_t path_offset, aicdf_level_sums* out,
+                                          double* path_out, void* stream) {
+  if (!out) return fail(AICDF_EINVAL, "out must be non-NULL");
+  return cir_level_em(prm, level, n_paths, kind, seed, path_offset, LevelOut{out, nullptr}, path_out, stream);
+}
+
+extern "C" aicdf_status mlmc_level_cir_sankaran(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths,
+                                                int32_t kind, uint64_t seed, uint64_t path_offset,
+                                                aicdf_level_sums* out, double* path_out, void* stream) {
+  if (!out) return fail(AICDF_EINVAL, "out must be non-NULL");
+  return cir_level_sankaran(prm, level, n_paths, kind, seed, path_offset, LevelOut{out, nullptr}, path_out, stream);
+}
+
+extern "C" aicdf_status mlmc_level_cir_async(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths,
+                                             int32_t kind, const aicdf_surrogate* sur, uint64_t seed,
+                                             uint64_t path_offset, double* sums_dev, double* path_out, void* stream) {
+  if (!sums_dev) return fail(AICDF_EINVAL, "sums_dev must be non-NULL");
+  return cir_level_surrogate(prm, level, n_paths, kind, sur, seed, path_offset, LevelOut{nullptr, sums_dev},
+                             path_out, stream);
+}
+
+extern "C" aicdf_status mlmc_level_cir_table_async(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths,
+                                                   int32_t kind, const aicdf_chi2_table* tab, uint64_t seed,
+                                                   uint64_t path_offset, double* sums_dev, double* path_out,
+                                                   void* stream) {
+  if (!sums_dev) return fail(AICDF_EINVAL, "sums_dev must be non-NULL");
+  return cir_level_table(prm, level, n_paths, kind, tab, seed, path_offset, LevelOut{nullptr, sums_dev}, path_out,
+                         stream);
+}
+
+extern "C" aicdf_status mlmc_level_cir_em_async(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths,
+                                                int32_t kind, uint64_t seed, uint64_t path_offset, double* sums_dev,
+                                                double* path_out, void* stream) {
+  if (!sums_dev) return fail(AICDF_EINVAL, "sums_dev must be non-NULL");
+  return cir_level_em(prm, level, n_paths, kind, seed, path_offset, LevelOut{nullptr, sums_dev}, path_out, stream);
+}
+
+extern "C" aicdf_status mlmc_level_cir_sankaran_async(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths,
+                                                      int32_t kind, uint64_t seed, uint64_t path_offset,
+                                                      double* sums_dev, double* path_out, void* stream) {
+  if (!sums_dev) return fail(AICDF_EINVAL, "sums_dev must be non-NULL");
+  return cir_level_sankaran(prm, level, n_paths, kind, seed, path_offset, LevelOut{nullptr, sums_dev}, path_out,
+                            stream);
 }

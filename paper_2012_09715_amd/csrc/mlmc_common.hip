@@ -1,5 +1,6 @@
 // Per-stream workspaces, the deterministic final pass over the per-block level
 // partials, and the optimal allocation of the nested estimator.
+#include <cstdint>
 #include <cmath>
 #include <map>
 
@@ -11,9 +12,12 @@ namespace {
 
 // One work-group: thread t sums partials t, t+256, ... in order (Neumaier),
 // then a fixed-order tree over the 256 values.  The result does not depend on
-// scheduling, so repeated calls are bit-identical.
+// scheduling, so repeated calls are bit-identical.  Writes the kSumsOut
+// results and clears the fallback counter for the next call on the stream.
 __global__ __launch_bounds__(kLevelBlock) void reduce_partials_kernel(const double* __restrict__ partials,
-                                                                      unsigned nblocks, double* __restrict__ out) {
+                                                                      unsigned nblocks,
+                                                                      unsigned long long* __restrict__ counter,
+                                                                      double n_paths, double* __restrict__ out) {
   __shared__ double red[kSums][kLevelBlock];
   KSum k[kSums];
   for (unsigned b = threadIdx.x; b < nblocks; b += kLevelBlock)
@@ -29,12 +33,24 @@ __global__ __launch_bounds__(kLevelBlock) void reduce_partials_kernel(const doub
     __syncthreads();
   }
   if (threadIdx.x < kSums) out[threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x == kSums) {
+    out[kSums] = counter ? double(*counter) : 0.0;
+    if (counter) *counter = 0ull;
+  }
+  if (threadIdx.x == kSums + 1) out[kSums + 1] = n_paths;
 }
 
 std::mutex g_ws_mutex;
 std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
 
 }  // namespace
+
+aicdf_status check_level_out(const LevelOut& o) {
+  if (!o.host && !o.dev) return fail(AICDF_EINVAL, "the output of the level sums must be non-NULL");
+  if (o.dev && (reinterpret_cast<uintptr_t>(o.dev) & 7u))
+    return fail(AICDF_EINVAL, "sums_dev must be 8-byte aligned");
+  return AICDF_OK;
+}
 
 aicdf_status get_workspace(hipStream_t s, Workspace** out) {
   int dev = 0;
@@ -49,11 +65,13 @@ aicdf_status get_workspace(hipStream_t s, Workspace** out) {
   auto* ws = new (std::nothrow) Workspace();
   if (!ws) return fail(AICDF_ENOMEM, "host allocation failed");
   if (hipMalloc(&ws->partials, sizeof(double) * kMaxLevelBlocks * kSums) != hipSuccess ||
-      hipMalloc(&ws->result, sizeof(double) * kSums) != hipSuccess ||
+      hipMalloc(&ws->result, sizeof(double) * kSumsOut) != hipSuccess ||
       hipMalloc(&ws->counter, sizeof(unsigned long long)) != hipSuccess) {
     delete ws;
     return fail(AICDF_ENOMEM, "hipMalloc of the level workspace failed");
   }
+  // the counter starts at zero; every final pass clears it again
+  AICDF_HIP(hipMemset(ws->counter, 0, sizeof(unsigned long long)));
   AICDF_HIP(hipEventCreate(&ws->ev0));
   AICDF_HIP(hipEventCreate(&ws->ev1));
   g_ws[key] = ws;
@@ -61,25 +79,41 @@ aicdf_status get_workspace(hipStream_t s, Workspace** out) {
   return AICDF_OK;
 }
 
-aicdf_status finish_level(Workspace* ws, unsigned nblocks, hipStream_t s, double n_paths,
-                          aicdf_level_sums* out) {
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kLevelBlock), 0, s, ws->partials, nblocks, ws->result);
+aicdf_status begin_level(Workspace* ws, hipStream_t s, const LevelOut& o) {
+  if (o.host) AICDF_HIP(hipEventRecord(ws->ev0, s));
+  return AICDF_OK;
+}
+
+aicdf_status finish_level(Workspace* ws, unsigned nblocks, hipStream_t s, double n_paths, const LevelOut& o) {
+  double* dst = o.host ? ws->result : o.dev;
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kLevelBlock), 0, s, ws->partials, nblocks, ws->counter,
+                     n_paths, dst);
   AICDF_HIP(hipGetLastError());
+  if (!o.host) return ok();
   AICDF_HIP(hipEventRecord(ws->ev1, s));
-  double res[kSums];
-  unsigned long long fb = 0;
+  double res[kSumsOut];
   AICDF_HIP(hipMemcpyAsync(res, ws->result, sizeof res, hipMemcpyDeviceToHost, s));
-  AICDF_HIP(hipMemcpyAsync(&fb, ws->counter, sizeof fb, hipMemcpyDeviceToHost, s));
   AICDF_HIP(hipStreamSynchronize(s));
   float ms = 0.0f;
   AICDF_HIP(hipEventElapsedTime(&ms, ws->ev0, ws->ev1));
+  aicdf_level_sums* out = o.host;
   out->n = n_paths;
   for (int j = 0; j < 4; ++j) out->sum[j] = res[j];
   out->sum_pf = res[4];
   out->sum_pc = res[5];
   out->kernel_ms = ms;
-  out->fallbacks = fb;
+  out->fallbacks = static_cast<uint64_t>(res[kSums]);
   out->reserved = 0;
+  return ok();
+}
+
+aicdf_status empty_level(hipStream_t s, const LevelOut& o) {
+  if (o.host) {
+    *o.host = aicdf_level_sums{};
+    return ok();
+  }
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kLevelBlock), 0, s, nullptr, 0u, nullptr, 0.0, o.dev);
+  AICDF_HIP(hipGetLastError());
   return ok();
 }
 

@@ -62,20 +62,44 @@ __device__ __forceinline__ void block_reduce_store(const LevelAcc& acc, double* 
 
 // Host side: one workspace per (device, stream) a level call has used
 // (created on first use, kept until the process ends), so that calls on
-// different streams can run concurrently; a call holds its workspace's mutex
-// from the first launch to the copy-out, which serialises calls that share a
-// stream.  Also the final pass over the partials.
+// different streams can run concurrently.  A synchronous call holds its
+// workspace's mutex from the first launch to the copy-out, which serialises
+// calls that share a stream; a stream-ordered call holds it while it enqueues,
+// and the stream's order keeps its partials and counter apart from those of
+// the next call on that stream.  The fallback counter is zero between calls:
+// zeroed at creation, read and cleared by the final pass of each call.
 struct Workspace {
   double* partials = nullptr;  // kMaxLevelBlocks * kSums doubles
-  double* result = nullptr;    // kSums doubles
+  double* result = nullptr;    // kSumsOut doubles
   unsigned long long* counter = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::mutex mu;
 };
 
+// Layout of a level's results in device memory: the kSums sums, then the
+// fallback count and the number of paths (both exact in FP64).
+constexpr int kSumsOut = 8;
+
+// Where a level call delivers its sums: to the host (synchronous call, with
+// the level kernel's device time) or to caller-owned device memory (stream
+// ordered, no wait, no timing).
+struct LevelOut {
+  aicdf_level_sums* host = nullptr;
+  double* dev = nullptr;
+};
+
+aicdf_status check_level_out(const LevelOut& o);
+
 aicdf_status get_workspace(hipStream_t s, Workspace** ws);
 
-aicdf_status finish_level(Workspace* ws, unsigned nblocks, hipStream_t s, double n_paths,
-                          aicdf_level_sums* out);
+// Records the start event of a synchronous call (no-op for a stream-ordered one).
+aicdf_status begin_level(Workspace* ws, hipStream_t s, const LevelOut& o);
+
+// The final pass over the level kernel's nblocks partials; a synchronous call
+// then waits and fills o.host.
+aicdf_status finish_level(Workspace* ws, unsigned nblocks, hipStream_t s, double n_paths, const LevelOut& o);
+
+// A call of zero paths: all-zero results (enqueued for a stream-ordered call).
+aicdf_status empty_level(hipStream_t s, const LevelOut& o);
 
 }  // namespace aicdf

@@ -357,12 +357,12 @@ void launch_kind(int scheme, int payoff, int tab, const GbmArgs& a, unsigned gri
   if (scheme == 1 && payoff == 1) launch_tab<KIND, 1, 1>(tab, a, grid, lds, s, p, po);
 }
 
-}  // namespace
-
-extern "C" aicdf_status mlmc_level_gbm(const aicdf_gbm_params* prm, uint32_t level, uint64_t n_paths, int32_t kind,
-                                       const aicdf_table* approx, uint64_t seed, uint64_t path_offset,
-                                       aicdf_level_sums* out, double* path_out, void* stream) {
-  if (!prm || !out) return fail(AICDF_EINVAL, "params and out must be non-NULL");
+aicdf_status gbm_level(const aicdf_gbm_params* prm, uint32_t level, uint64_t n_paths, int32_t kind,
+                       const aicdf_table* approx, uint64_t seed, uint64_t path_offset, const LevelOut& out,
+                       double* path_out, void* stream) {
+  if (!prm) return fail(AICDF_EINVAL, "params must be non-NULL");
+  aicdf_status st = check_level_out(out);
+  if (st != AICDF_OK) return st;
   if (level > 20) return fail(AICDF_ERANGE, "level %u > 20", level);
   if (kind < 0 || kind > 2) return fail(AICDF_EINVAL, "kind must be 0, 1 or 2");
   if (prm->scheme < 0 || prm->scheme > 1 || prm->payoff < 0 || prm->payoff > 1)
@@ -370,10 +370,7 @@ extern "C" aicdf_status mlmc_level_gbm(const aicdf_gbm_params* prm, uint32_t lev
   if (!(prm->T > 0.0) || !(prm->sigma >= 0.0) || !std::isfinite(prm->S0) || !std::isfinite(prm->r))
     return fail(AICDF_EINVAL, "need T > 0, sigma >= 0, finite S0 and r");
   if (kind != AICDF_KIND_EXACT && !approx) return fail(AICDF_EINVAL, "the approximate kinds need a table");
-  if (n_paths == 0) {
-    *out = aicdf_level_sums{};
-    return ok();
-  }
+  if (n_paths == 0) return empty_level(static_cast<hipStream_t>(stream), out);
   if (n_paths > (uint64_t(1) << 40)) return fail(AICDF_ERANGE, "n_paths > 2^40");
   if (path_offset + n_paths < path_offset) return fail(AICDF_ERANGE, "path_offset + n_paths overflows");
   int dev = 0;
@@ -421,11 +418,11 @@ extern "C" aicdf_status mlmc_level_gbm(const aicdf_gbm_params* prm, uint32_t lev
 
   auto s = static_cast<hipStream_t>(stream);
   Workspace* ws = nullptr;
-  aicdf_status st = get_workspace(s, &ws);
+  st = get_workspace(s, &ws);
   if (st != AICDF_OK) return st;
   std::lock_guard<std::mutex> lock(ws->mu);
-  AICDF_HIP(hipMemsetAsync(ws->counter, 0, sizeof(unsigned long long), s));
-  AICDF_HIP(hipEventRecord(ws->ev0, s));
+  st = begin_level(ws, s, out);
+  if (st != AICDF_OK) return st;
   if (kind == AICDF_KIND_EXACT)
     launch_kind<AICDF_KIND_EXACT>(prm->scheme, prm->payoff, 0, a, grid, 0, s, ws->partials, path_out);
   else if (kind == AICDF_KIND_APPROX)
@@ -434,4 +431,21 @@ extern "C" aicdf_status mlmc_level_gbm(const aicdf_gbm_params* prm, uint32_t lev
     launch_kind<AICDF_KIND_CORRECTION>(prm->scheme, prm->payoff, tab, a, grid, lds, s, ws->partials, path_out);
   AICDF_HIP(hipGetLastError());
   return finish_level(ws, grid, s, double(n_paths), out);
+}
+
+}  // namespace
+
+extern "C" aicdf_status mlmc_level_gbm(const aicdf_gbm_params* prm, uint32_t level, uint64_t n_paths, int32_t kind,
+                                       const aicdf_table* approx, uint64_t seed, uint64_t path_offset,
+                                       aicdf_level_sums* out, double* path_out, void* stream) {
+  if (!out) return fail(AICDF_EINVAL, "out must be non-NULL");
+  return gbm_level(prm, level, n_paths, kind, approx, seed, path_offset, LevelOut{out, nullptr}, path_out, stream);
+}
+
+extern "C" aicdf_status mlmc_level_gbm_async(const aicdf_gbm_params* prm, uint32_t level, uint64_t n_paths,
+                                             int32_t kind, const aicdf_table* approx, uint64_t seed,
+                                             uint64_t path_offset, double* sums_dev, double* path_out, void* stream) {
+  if (!sums_dev) return fail(AICDF_EINVAL, "sums_dev must be non-NULL");
+  return gbm_level(prm, level, n_paths, kind, approx, seed, path_offset, LevelOut{nullptr, sums_dev}, path_out,
+                   stream);
 }

@@ -15,11 +15,12 @@ level the driver
 The speed-up is reported three ways: T^/T~ from the cost formula with the
 measured (v, c); the ratio of the summed device times of the two estimators'
 level calls at the same target RMSE, run one after another; and the ratio of
-their wall-clock times when each estimator's level calls run concurrently on
-a few streams (the latency-bound high levels, a few hundred paths of 2^l
-serial steps each, then overlap instead of adding up).  The concurrent pass
-repeats the same calls on the same paths, so its sums are bit-identical to
-the sequential pass.
+their wall-clock times when each estimator's level calls are enqueued from
+one host thread on a few streams with the library's stream-ordered calls and
+waited for once (the latency-bound high levels, a few hundred paths of 2^l
+serial steps each, then overlap instead of adding up, and no call waits for
+the host).  The concurrent pass repeats the same calls on the same paths, so
+its sums are bit-identical to the sequential pass.
 """
 import math
 import threading
@@ -45,6 +46,20 @@ def level_call(model, params, level, n, kind, approx, seed, offset=0):
     if approx == "em":
         return A.mlmc_level_cir_em(params, level, n, kind, seed, offset)
     return A.mlmc_level_cir(params, level, n, kind, approx, seed, offset)
+
+
+def level_call_async(model, params, level, n, kind, approx, seed, offset, sums):
+    """The stream-ordered form of level_call: enqueues on the current stream,
+    the device writes the 8 sums into `sums`."""
+    if model == "gbm":
+        return A.mlmc_level_gbm_async(params, level, n, kind, approx, seed, offset, sums)
+    if isinstance(approx, A.Chi2Table):
+        return A.mlmc_level_cir_table_async(params, level, n, kind, approx, seed, offset, sums)
+    if approx == "sankaran":
+        return A.mlmc_level_cir_sankaran_async(params, level, n, kind, seed, offset, sums)
+    if approx == "em":
+        return A.mlmc_level_cir_em_async(params, level, n, kind, seed, offset, sums)
+    return A.mlmc_level_cir_async(params, level, n, kind, approx, seed, offset, sums)
 
 
 class Acc:
@@ -87,21 +102,29 @@ def cost_paths(level, steps_budget=1 << 26, floor=1 << 18):
     return max(steps_budget >> level, floor)
 
 
+LATENCY_PATHS = 256
+
+
 def pilot(model, params, L, approx, seed, n_pilot, steps_budget=1 << 26):
     """Per level and kind: variance from n_pilot paths, cost per path from a
-    call large enough to fill the GPU (cost_paths)."""
+    call large enough to fill the GPU (cost_paths), and the device time of a
+    call too small to fill it (LATENCY_PATHS paths: the serial time of one
+    path, the floor under any call's duration)."""
     accs = [[Acc() for _ in KINDS] for _ in range(L + 1)]
     costs = [[0.0 for _ in KINDS] for _ in range(L + 1)]
+    lats = [[0.0 for _ in KINDS] for _ in range(L + 1)]
     for l in range(L + 1):
         for k in KINDS:
             a = accs[l][k]
             a.add(level_call(model, params, l, n_pilot, k, approx, seed, 0))
             nc = cost_paths(l, steps_budget)
-            # warm launch, then a timed one on fresh paths (not used in sums)
+            # warm launch, then timed ones on fresh paths (not used in sums)
             level_call(model, params, l, min(nc, 4096), k, approx, seed + 7919, 0)
             s = level_call(model, params, l, nc, k, approx, seed + 7919, 1 << 36)
             costs[l][k] = s["kernel_ms"] * 1e-3 / nc
-    return accs, costs
+            s = level_call(model, params, l, LATENCY_PATHS, k, approx, seed + 7919, 1 << 37)
+            lats[l][k] = s["kernel_ms"] * 1e-3
+    return accs, costs, lats
 
 
 def allocate(eps, accs, costs):
@@ -184,11 +207,37 @@ def run_concurrent(jobs, n_streams=4):
     return results, wall
 
 
-def run_estimators(model, params, L, eps, approx, seed, accs, alloc, n_streams=4):
+def run_async(jobs, costs, n_streams=4):
+    """Enqueues stream-ordered level calls from this thread on n_streams
+    streams: each job(sums) writes its 8 sums into the given device row; the
+    dearest job (by `costs`) goes first, each to the stream with the least
+    queued cost.  One wait at the end.  Returns the result dicts in job order
+    and the wall-clock milliseconds from the first launch to the last result
+    on the host."""
+    streams = _streams(n_streams)
+    sums = torch.zeros((max(len(jobs), 1), 8), dtype=torch.float64, device="cuda")
+    order = sorted(range(len(jobs)), key=lambda i: -costs[i])
+    load = [0.0] * n_streams
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in order:
+        j = min(range(n_streams), key=load.__getitem__)
+        with torch.cuda.stream(streams[j]):
+            jobs[i](sums[i])
+        load[j] += costs[i]
+    for st in streams:
+        st.synchronize()
+    host = sums.cpu()
+    wall = (time.perf_counter() - t0) * 1e3
+    return [A.sums_dict(host[i]) for i in range(len(jobs))], wall
+
+
+def run_estimators(model, params, L, eps, approx, seed, accs, alloc, lats=None, n_streams=4):
     """Runs the allocated path counts on fresh paths of every stream (the
     pilot paths are not reused, so the estimate is independent of the
     allocation) and returns the two estimators, their standard errors and
-    their measured device times."""
+    their measured device times.  For the concurrent pass a call of m paths
+    is expected to take max(m c, latency) (lats: the pilot's latencies)."""
     out = {}
     plan = {A.KIND_EXACT: alloc["m_hat"], A.KIND_APPROX: alloc["m_tilde"], A.KIND_CORRECTION: alloc["M_tilde"]}
     cost = {A.KIND_EXACT: alloc["c_hat"], A.KIND_APPROX: alloc["c2"], A.KIND_CORRECTION: alloc["c4"]}
@@ -205,18 +254,21 @@ def run_estimators(model, params, L, eps, approx, seed, accs, alloc, n_streams=4
             r.add(s)
             time_ms[k] += r.ms
             calls[(l, k)] += (s,)
-    # the same calls again, each estimator's levels concurrently, dearest first
+    # the same calls again, each estimator's levels enqueued on several
+    # streams at once (stream-ordered calls, one wait per estimator)
     warm_streams(lambda: level_call(model, params, 0, 2, A.KIND_APPROX, approx, seed, 0), n_streams)
     wall = {}
     same = True
     for name, kinds in (("hat", (A.KIND_EXACT,)), ("tilde", (A.KIND_APPROX, A.KIND_CORRECTION))):
-        keys = sorted(((l, k) for l in range(L + 1) for k in kinds),
-                      key=lambda lk: -calls[lk][0] * cost[lk[1]][lk[0]])
-        jobs = [(lambda lk=lk: level_call(model, params, lk[0], calls[lk][0], lk[1], approx, seed, calls[lk][1]))
-                for lk in keys]
-        res, wall[name] = run_concurrent(jobs, n_streams)
+        keys = [(l, k) for l in range(L + 1) for k in kinds]
+        jobs = [(lambda sums, lk=lk: level_call_async(model, params, lk[0], calls[lk][0], lk[1], approx, seed,
+                                                      calls[lk][1], sums)) for lk in keys]
+        est = [max(calls[lk][0] * cost[lk[1]][lk[0]], lats[lk[0]][lk[1]] if lats else 0.0) for lk in keys]
+        res, wall[name] = run_async(jobs, est, n_streams)
         for lk, r in zip(keys, res):
-            same = same and r["sum"] == calls[lk][2]["sum"] and r["sum_pf"] == calls[lk][2]["sum_pf"]
+            ref = calls[lk][2]
+            same = (same and r["n"] == ref["n"] and r["sum"] == ref["sum"] and r["sum_pf"] == ref["sum_pf"]
+                    and r["sum_pc"] == ref["sum_pc"] and r["fallbacks"] == ref["fallbacks"])
     theta_hat = sum(runs[l][A.KIND_EXACT].mean for l in range(L + 1))
     var_hat = sum(runs[l][A.KIND_EXACT].var / runs[l][A.KIND_EXACT].n for l in range(L + 1))
     theta_tilde = sum(runs[l][A.KIND_APPROX].mean + runs[l][A.KIND_CORRECTION].mean for l in range(L + 1))
@@ -241,18 +293,19 @@ def nested_mlmc(model, params, L, eps, approx, seed, n_pilot=1 << 16, steps_budg
     """Pilot, allocate and run both estimators.  With target_paths, eps is
     lowered so that the regular estimator allocates about that many paths in
     total (the allocation scales as eps^-2)."""
-    accs, costs = pilot(model, params, L, approx, seed, n_pilot, steps_budget)
+    accs, costs, lats = pilot(model, params, L, approx, seed, n_pilot, steps_budget)
     alloc = allocate(eps, accs, costs)
     if target_paths:
         eps = eps * math.sqrt(sum(alloc["m_hat"]) / target_paths)
         alloc = allocate(eps, accs, costs)
-    est = run_estimators(model, params, L, eps, approx, seed, accs, alloc)
+    est = run_estimators(model, params, L, eps, approx, seed, accs, alloc, lats)
     per_level = []
     for l in range(L + 1):
         per_level.append({
             "level": l,
             "v_hat": alloc["v_hat"][l], "v2": alloc["v2"][l], "v4": alloc["v4"][l],
             "c_hat_ns": alloc["c_hat"][l] * 1e9, "c2_ns": alloc["c2"][l] * 1e9, "c4_ns": alloc["c4"][l] * 1e9,
+            "latency_us": [lats[l][k] * 1e6 for k in KINDS],
             "log2_v4_over_vhat": math.log2(alloc["v4"][l] / alloc["v_hat"][l]) if alloc["v_hat"][l] > 1e-299 else None,
             "m_hat": alloc["m_hat"][l], "m_tilde": alloc["m_tilde"][l], "M_tilde": alloc["M_tilde"][l],
         })

@@ -85,6 +85,22 @@ def test_transform_argument_errors_need_no_device():
     assert lib.aicdf_bw_probe(0, 17, C.c_void_p(4096), C.c_void_p(8192), None) == -1
 
 
+def test_async_level_argument_errors_need_no_device():
+    from paper_2012_09715_amd._lib import CirParams, GbmParams
+    g = GbmParams(1.0, 0.05, 0.2, 1.0, 1.0, 0, 1)
+    c = CirParams(0.04, 0.5, 0.04, 0.3, 1.0, 1, 0)
+    # NULL or misaligned sums_dev, before any device call
+    assert lib.mlmc_level_gbm_async(C.byref(g), 2, 100, 0, None, 1, 0, None, None, None) == -1
+    assert lib.mlmc_level_gbm_async(C.byref(g), 2, 100, 0, None, 1, 0, C.c_void_p(4100), None, None) == -1
+    assert b"aligned" in lib.aicdf_last_error()
+    assert lib.mlmc_level_cir_async(C.byref(c), 2, 100, 0, None, 1, 0, None, None, None) == -1
+    assert lib.mlmc_level_cir_table_async(C.byref(c), 2, 100, 0, None, 1, 0, C.c_void_p(4097), None, None) == -1
+    assert lib.mlmc_level_cir_em_async(C.byref(c), 2, 100, 0, 1, 0, None, None, None) == -1
+    assert lib.mlmc_level_cir_sankaran_async(None, 2, 100, 0, 1, 0, C.c_void_p(4096), None, None) == -1
+    # the synchronous calls still require their host output
+    assert lib.mlmc_level_gbm(C.byref(g), 2, 100, 0, None, 1, 0, None, None, None) == -1
+
+
 def test_mlmc_allocate_matches_oracle():
     rng = np.random.default_rng(3)
     for _ in range(10):
