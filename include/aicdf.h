@@ -14,8 +14,9 @@
  *    released with their destroy call; destroy(NULL) is a no-op.  A handle is
  *    bound to the device that was current when it was created.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
- *    Transform calls only enqueue work and return; the MLMC level calls and
- *    the calls returning host results synchronise `stream` before returning.
+ *    Transform calls only enqueue work and return; the MLMC level calls (not
+ *    their _async forms) and the calls returning host results synchronise
+ *    `stream` before returning.
  *  - Errors are reported only through the status code; aicdf_last_error()
  *    returns a thread-local text for the last failing call.  No call prints,
  *    throws across the ABI or aborts.
@@ -300,12 +301,15 @@ typedef struct aicdf_surrogate aicdf_surrogate;
  *               Y = P^_f - P~_f, sum_pf over P^_f, sum_pc over P~_f
  * Stream kinds are 4 + kind in the counter tag.  level 0..12.  Other
  * arguments as mlmc_level_gbm, with one qualification of split invariance:
- * EXACT and CORRECTION calls of fewer than 2^17 paths (too few to fill the
- * GPU one path per thread) run one path per wavefront with a
- * wave-cooperative exact inverse that sums in another order; their per-path
- * values agree with those of larger calls to 1e-11 relative (rounding of
- * the sums, which can steer the root iteration to another last step) and
- * are bit-identical between calls of the same launch shape.  Errors: EINVAL, ERANGE, EHIP, ENOMEM. */
+ * EXACT, CORRECTION and TWOWAY calls with few paths run one path per
+ * wavefront with a wave-cooperative exact inverse that sums in another
+ * order: always at most 2048 paths, never 2^17 or more, and in between
+ * below a cost model's crossover (it grows with lambda at the process level
+ * max(v0, theta) and with the waves the kernel keeps resident); their
+ * per-path values agree with those of the other shape to 1e-11 relative
+ * (rounding of the sums, which can steer the root iteration to another last
+ * step; the surrogate's values are bit-identical) and are bit-identical
+ * between calls of the same launch shape.  Errors: EINVAL, ERANGE, EHIP, ENOMEM. */
 aicdf_status mlmc_level_cir(const aicdf_cir_params* params, uint32_t level, uint64_t n_paths,
                             int32_t kind, const aicdf_surrogate* approx, uint64_t seed,
                             uint64_t path_offset, aicdf_level_sums* out, double* path_out,

@@ -30,12 +30,15 @@
 // path) run one path per wavefront: all 64 lanes follow the same path and
 // evaluate each exact inverse together (ncx2_wave.hpp), and lane 0 keeps the
 // sums; no path waits for the root iterations of 63 others.  Every other
-// call runs one path per thread.
+// call runs one path per thread; the crossover is a cost model (below).
 // The coarse path of level l is the fine path
 // observed at even steps (exact in law), so only the functional differs:
 //   FUNC 0  P = v_T
 //   FUNC 1  P = trapezoidal time average on the level's grid.
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "chi2_device.hpp"
 #include "mlmc_common.hpp"
@@ -63,13 +66,52 @@ struct CirArgs {
   uint32_t sparse;      // 1: one path per wavefront
 };
 
-// One path per wavefront when one path per thread would not fill the GPU
-// (fewer than 2^17 paths = 256 CUs x 4 SIMDs x 2 waves x 64 lanes).  Above
-// that, 64 paths per wavefront win even where the exact sweeps are long
-// (level 10: 262144 paths take about 9 s one per wavefront against 4 s one
-// per thread), and the surrogate's wave-wide network call serves 64 paths
-// instead of one.
-constexpr uint64_t kDenseFillPaths = uint64_t(1) << 17;
+// Launch shape of the exact, correction and two-way kinds.  One path per
+// thread gives a call of n paths n/64 waves, each as slow per step as its
+// slowest lane's root iteration; one path per wavefront gives n waves, each
+// evaluating one inverse with all its lanes, and costs about n/W times one
+// wave's serial time once the n waves exceed the W the GPU keeps resident.
+// The ratio r of the two per-step times grows with lambda (a thread's sweep
+// has ~18 sqrt(mu) terms and lanes diverge; the wave splits the sweep 64
+// ways), so a call runs one path per wavefront below n* = W r(lambda), with
+// lambda at the process level max(v0, theta) and r measured on MI355X for the
+// exact kind (nu = 0.89, levels 0..10; the last two points extrapolated):
+constexpr float kShapeRatio[12] = {4.0f, 4.8f, 6.0f, 7.6f, 9.1f, 10.5f, 11.7f, 14.1f, 21.8f, 33.3f, 45.0f, 57.0f};
+constexpr int kShapeLog2Lo = 2;  // kShapeRatio[k] at log2 lambda = k + 2
+// n* is kept within [2049, 2^17]: calls of at most 2048 paths always run one
+// path per wavefront and calls of 2^17 or more one path per thread.
+constexpr uint64_t kSparseAlways = 2048, kDenseAlways = uint64_t(1) << 17;
+
+float shape_ratio(double lam) {
+  const double x = std::log2(std::fmax(lam, 1e-300)) - kShapeLog2Lo;
+  if (!(x > 0.0)) return kShapeRatio[0];
+  if (x >= 11.0) return kShapeRatio[11];
+  const int k = int(x);
+  const float f = float(x - k);
+  return kShapeRatio[k] + f * (kShapeRatio[k + 1] - kShapeRatio[k]);
+}
+
+// Waves of `kernel` the current device keeps resident (blocks per CU from the
+// occupancy calculator x CUs x 4), cached per (device, kernel, LDS bytes).
+aicdf_status resident_waves(const void* kernel, size_t lds, uint64_t* waves) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, const void*, size_t>, uint64_t> cache;
+  int dev = 0;
+  AICDF_HIP(hipGetDevice(&dev));
+  const auto key = std::make_tuple(dev, kernel, lds);
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) {
+    *waves = it->second;
+    return AICDF_OK;
+  }
+  int blocks = 0, cus = 0;
+  AICDF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernel, kLevelBlock, lds));
+  AICDF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  *waves = uint64_t(blocks > 0 ? blocks : 1) * uint64_t(cus > 0 ? cus : 1) * (kLevelBlock / 64);
+  cache[key] = *waves;
+  return AICDF_OK;
+}
 
 __device__ __forceinline__ float dyadic_w16(float u, const f32x4* __restrict__ tab) {
   const bool p = u < 0.5f;
@@ -115,6 +157,7 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
   constexpr bool kEm = kApx && APX == APX_EM;
   constexpr bool kSank = kApx && APX == APX_SANKARAN;
   __shared__ MlpLds L;
+  __shared__ MlpXchg xch[kLevelBlock / 64];  // SPARSE surrogate: one per wave
   __shared__ f32x4 tab[16];
   extern __shared__ f32x4 ctab[];  // APX_POLY*: the chi-squared table (dynamic LDS)
   bf16x8 A[2][4];
@@ -169,7 +212,9 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
         const float ll = lam > 0.0f ? __logf(lam) : -1e30f;
         const bool inr = ll <= a.hi;
         const float g = inr ? mlp_g(fmaxf(ll, a.lo), a.lo, a.inv_span2) : 0.0f;
-        const float Pt = mlp_wave_forward(L, A, dyadic_w16(u24, tab), g);  // all lanes
+        // all lanes; one path per wavefront: one sample spread over the wave
+        const float Pt = SPARSE ? mlp_wave_forward_one(L, xch[threadIdx.x / 64], A, dyadic_w16(u24, tab), g)
+                                : mlp_wave_forward(L, A, dyadic_w16(u24, tab), g);
         float x;
         if (inr) {
           const float s = lam + a.nuf;
@@ -253,39 +298,50 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
   }
 }
 
+using LevelKernel = void (*)(CirArgs, const float*, const uint16_t*, const f32x4*, double*, double*,
+                            unsigned long long*);
+
+// Chooses the launch shape (above), sets a.sparse and the grid, launches.
 template <int KIND, int APX>
-void launch_func(int func, const CirArgs& a, unsigned grid, size_t lds, hipStream_t s, const float* p,
-                 const uint16_t* w2, const f32x4* wt, double* part, double* po, unsigned long long* fb) {
-  const dim3 g(grid), b(kLevelBlock);
-  if (a.sparse) {
-    if (func == 0)
-      hipLaunchKernelGGL((cir_level_kernel<KIND, 0, APX, true>), g, b, lds, s, a, p, w2, wt, part, po, fb);
-    else
-      hipLaunchKernelGGL((cir_level_kernel<KIND, 1, APX, true>), g, b, lds, s, a, p, w2, wt, part, po, fb);
-  } else {
-    if (func == 0)
-      hipLaunchKernelGGL((cir_level_kernel<KIND, 0, APX, false>), g, b, lds, s, a, p, w2, wt, part, po, fb);
-    else
-      hipLaunchKernelGGL((cir_level_kernel<KIND, 1, APX, false>), g, b, lds, s, a, p, w2, wt, part, po, fb);
+aicdf_status launch_func(int func, CirArgs a, size_t lds, hipStream_t s, const float* p, const uint16_t* w2,
+                         const f32x4* wt, double* part, double* po, unsigned long long* fb, unsigned* grid) {
+  const LevelKernel ks = func == 0 ? cir_level_kernel<KIND, 0, APX, true> : cir_level_kernel<KIND, 1, APX, true>;
+  const LevelKernel kd = func == 0 ? cir_level_kernel<KIND, 0, APX, false> : cir_level_kernel<KIND, 1, APX, false>;
+  bool sparse = false;
+  if (KIND != AICDF_KIND_APPROX && a.n_paths < kDenseAlways) {
+    sparse = a.n_paths <= kSparseAlways;
+    if (!sparse) {
+      uint64_t w = 0;
+      aicdf_status st = resident_waves(reinterpret_cast<const void*>(ks), lds, &w);
+      if (st != AICDF_OK) return st;
+      const double lam = std::fmax(a.v0, double(a.theta)) * a.decay / a.c;
+      sparse = double(a.n_paths) < double(w) * shape_ratio(lam);
+    }
   }
+  a.sparse = sparse ? 1u : 0u;
+  const uint64_t per_block = sparse ? kLevelBlock / 64 : kLevelBlock;
+  const uint64_t need = (a.n_paths + per_block - 1) / per_block;
+  *grid = unsigned(need < uint64_t(kMaxLevelBlocks) ? need : kMaxLevelBlocks);
+  hipLaunchKernelGGL(sparse ? ks : kd, dim3(*grid), dim3(kLevelBlock), lds, s, a, p, w2, wt, part, po, fb);
+  return AICDF_OK;
 }
 
 template <int APX>
-void launch_kind(int kind, int func, const CirArgs& a, unsigned grid, size_t lds, hipStream_t s, const float* p,
-                 const uint16_t* w2, const f32x4* wt, double* part, double* po, unsigned long long* fb) {
+aicdf_status launch_kind(int kind, int func, const CirArgs& a, size_t lds, hipStream_t s, const float* p,
+                         const uint16_t* w2, const f32x4* wt, double* part, double* po, unsigned long long* fb,
+                         unsigned* grid) {
   if (kind == AICDF_KIND_EXACT)
-    launch_func<AICDF_KIND_EXACT, APX_SURROGATE>(func, a, grid, 0, s, p, w2, wt, part, po, fb);
-  else if (kind == AICDF_KIND_APPROX)
-    launch_func<AICDF_KIND_APPROX, APX>(func, a, grid, lds, s, p, w2, wt, part, po, fb);
-  else if (kind == AICDF_KIND_CORRECTION)
-    launch_func<AICDF_KIND_CORRECTION, APX>(func, a, grid, lds, s, p, w2, wt, part, po, fb);
-  else
-    launch_func<KIND_TWOWAY, APX>(func, a, grid, lds, s, p, w2, wt, part, po, fb);
+    return launch_func<AICDF_KIND_EXACT, APX_SURROGATE>(func, a, 0, s, p, w2, wt, part, po, fb, grid);
+  if (kind == AICDF_KIND_APPROX)
+    return launch_func<AICDF_KIND_APPROX, APX>(func, a, lds, s, p, w2, wt, part, po, fb, grid);
+  if (kind == AICDF_KIND_CORRECTION)
+    return launch_func<AICDF_KIND_CORRECTION, APX>(func, a, lds, s, p, w2, wt, part, po, fb, grid);
+  return launch_func<KIND_TWOWAY, APX>(func, a, lds, s, p, w2, wt, part, po, fb, grid);
 }
 
 // Checks shared by both approximations; fills the common arguments.
 aicdf_status cir_setup(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths, int32_t kind, uint64_t seed,
-                       uint64_t path_offset, const LevelOut& out, CirArgs& a, unsigned& grid) {
+                       uint64_t path_offset, const LevelOut& out, CirArgs& a) {
   if (!prm) return fail(AICDF_EINVAL, "params must be non-NULL");
   aicdf_status st = check_level_out(out);
   if (st != AICDF_OK) return st;
@@ -319,10 +375,6 @@ aicdf_status cir_setup(const aicdf_cir_params* prm, uint32_t level, uint64_t n_p
   a.kdt = float(prm->kappa * dt);
   a.theta = float(prm->theta);
   a.xi_sqdt = float(prm->xi * std::sqrt(dt));
-  a.sparse = (kind != AICDF_KIND_APPROX && n_paths < kDenseFillPaths) ? 1u : 0u;
-  const uint64_t per_block = a.sparse ? kLevelBlock / 64 : kLevelBlock;
-  const uint64_t need = (n_paths + per_block - 1) / per_block;
-  grid = unsigned(need < uint64_t(kMaxLevelBlocks) ? need : kMaxLevelBlocks);
   return AICDF_OK;
 }
 
@@ -331,7 +383,7 @@ aicdf_status cir_level_surrogate(const aicdf_cir_params* prm, uint32_t level, ui
                                  double* path_out, void* stream) {
   CirArgs a;
   unsigned grid = 0;
-  aicdf_status st = cir_setup(prm, level, n_paths, kind, seed, path_offset, out, a, grid);
+  aicdf_status st = cir_setup(prm, level, n_paths, kind, seed, path_offset, out, a);
   if (st != AICDF_OK) return st;
   if (kind != AICDF_KIND_EXACT && !sur) return fail(AICDF_EINVAL, "the approximate kinds need a surrogate");
   if (n_paths == 0) return empty_level(static_cast<hipStream_t>(stream), out);
@@ -360,7 +412,9 @@ aicdf_status cir_level_surrogate(const aicdf_cir_params* prm, uint32_t level, ui
   const f32x4* wt = sur ? reinterpret_cast<const f32x4*>(surrogate_wtab(sur)) : nullptr;
   st = begin_level(ws, s, out);
   if (st != AICDF_OK) return st;
-  launch_kind<APX_SURROGATE>(kind, prm->functional, a, grid, 0, s, p, w2, wt, ws->partials, path_out, ws->counter);
+  st = launch_kind<APX_SURROGATE>(kind, prm->functional, a, 0, s, p, w2, wt, ws->partials, path_out, ws->counter,
+                                  &grid);
+  if (st != AICDF_OK) return st;
   AICDF_HIP(hipGetLastError());
   return finish_level(ws, grid, s, double(n_paths), out);
 }
@@ -370,7 +424,7 @@ aicdf_status cir_level_table(const aicdf_cir_params* prm, uint32_t level, uint64
                              double* path_out, void* stream) {
   CirArgs a;
   unsigned grid = 0;
-  aicdf_status st = cir_setup(prm, level, n_paths, kind, seed, path_offset, out, a, grid);
+  aicdf_status st = cir_setup(prm, level, n_paths, kind, seed, path_offset, out, a);
   if (st != AICDF_OK) return st;
   if (kind != AICDF_KIND_EXACT && !tab) return fail(AICDF_EINVAL, "the approximate kinds need a table");
   if (n_paths == 0) return empty_level(static_cast<hipStream_t>(stream), out);
@@ -400,11 +454,12 @@ aicdf_status cir_level_table(const aicdf_cir_params* prm, uint32_t level, uint64
   st = begin_level(ws, s, out);
   if (st != AICDF_OK) return st;
   if (kind == AICDF_KIND_EXACT || ti.degree == 1)
-    launch_kind<APX_POLY1>(kind, prm->functional, a, grid, lds, s, nullptr, nullptr, wt, ws->partials, path_out,
-                           ws->counter);
+    st = launch_kind<APX_POLY1>(kind, prm->functional, a, lds, s, nullptr, nullptr, wt, ws->partials, path_out,
+                                ws->counter, &grid);
   else
-    launch_kind<APX_POLY3>(kind, prm->functional, a, grid, lds, s, nullptr, nullptr, wt, ws->partials, path_out,
-                           ws->counter);
+    st = launch_kind<APX_POLY3>(kind, prm->functional, a, lds, s, nullptr, nullptr, wt, ws->partials, path_out,
+                                ws->counter, &grid);
+  if (st != AICDF_OK) return st;
   AICDF_HIP(hipGetLastError());
   return finish_level(ws, grid, s, double(n_paths), out);
 }
@@ -413,7 +468,7 @@ aicdf_status cir_level_em(const aicdf_cir_params* prm, uint32_t level, uint64_t 
                           uint64_t seed, uint64_t path_offset, const LevelOut& out, double* path_out, void* stream) {
   CirArgs a;
   unsigned grid = 0;
-  aicdf_status st = cir_setup(prm, level, n_paths, kind, seed, path_offset, out, a, grid);
+  aicdf_status st = cir_setup(prm, level, n_paths, kind, seed, path_offset, out, a);
   if (st != AICDF_OK) return st;
   if (n_paths == 0) return empty_level(static_cast<hipStream_t>(stream), out);
   auto s = static_cast<hipStream_t>(stream);
@@ -423,8 +478,9 @@ aicdf_status cir_level_em(const aicdf_cir_params* prm, uint32_t level, uint64_t 
   std::lock_guard<std::mutex> lock(ws->mu);
   st = begin_level(ws, s, out);
   if (st != AICDF_OK) return st;
-  launch_kind<APX_EM>(kind, prm->functional, a, grid, 0, s, nullptr, nullptr, nullptr, ws->partials, path_out,
-                      ws->counter);
+  st = launch_kind<APX_EM>(kind, prm->functional, a, 0, s, nullptr, nullptr, nullptr, ws->partials, path_out,
+                           ws->counter, &grid);
+  if (st != AICDF_OK) return st;
   AICDF_HIP(hipGetLastError());
   return finish_level(ws, grid, s, double(n_paths), out);
 }
@@ -434,7 +490,7 @@ aicdf_status cir_level_sankaran(const aicdf_cir_params* prm, uint32_t level, uin
                                 void* stream) {
   CirArgs a;
   unsigned grid = 0;
-  aicdf_status st = cir_setup(prm, level, n_paths, kind, seed, path_offset, out, a, grid);
+  aicdf_status st = cir_setup(prm, level, n_paths, kind, seed, path_offset, out, a);
   if (st != AICDF_OK) return st;
   if (n_paths == 0) return empty_level(static_cast<hipStream_t>(stream), out);
   auto s = static_cast<hipStream_t>(stream);
@@ -444,8 +500,9 @@ aicdf_status cir_level_sankaran(const aicdf_cir_params* prm, uint32_t level, uin
   std::lock_guard<std::mutex> lock(ws->mu);
   st = begin_level(ws, s, out);
   if (st != AICDF_OK) return st;
-  launch_kind<APX_SANKARAN>(kind, prm->functional, a, grid, 0, s, nullptr, nullptr, nullptr, ws->partials, path_out,
-                            ws->counter);
+  st = launch_kind<APX_SANKARAN>(kind, prm->functional, a, 0, s, nullptr, nullptr, nullptr, ws->partials,
+                                 path_out, ws->counter, &grid);
+  if (st != AICDF_OK) return st;
   AICDF_HIP(hipGetLastError());
   return finish_level(ws, grid, s, double(n_paths), out);
 }

@@ -121,6 +121,68 @@ __device__ __forceinline__ float mlp_wave_forward(const MlpLds& L, const bf16x8 
   return w + (half ? part[1] : part[0]) + L.b3;
 }
 
+// Per-wave LDS exchange of mlp_wave_forward_one.
+struct alignas(16) MlpXchg {
+  uint16_t h[kHidden];  // bf16 bits of the layer-1 values
+  float s[kHidden];     // silu of the layer-2 values
+};
+
+// Forward pass of ONE sample held by the whole wave (w and g equal in every
+// lane, as when all lanes follow one path): the arithmetic of
+// mlp_wave_forward for that sample, bit for bit, with the per-unit work
+// spread over the lanes instead of repeated in each.  Layer 1: lane l
+// computes unit l; the BF16 values meet in LDS, from which every lane reads
+// its B fragments (all 32 sample columns are then the same, so only the
+// nt = 0 tiles are computed).  After layer 2 the 32 lanes of a half hold the
+// same 32 output units; lane l takes the slot (mt, j) = (l%32 / 16, l%16) of
+// its half, so every unit's silu is evaluated once, and the values meet in
+// LDS again.  Each lane then runs both halves' FMA chains in the order of
+// mlp_wave_forward.  Every lane of the wave must call it, with wave-uniform
+// control flow.
+__device__ __forceinline__ float mlp_wave_forward_one(const MlpLds& L, MlpXchg& X, const bf16x8 (&A)[2][4], float w,
+                                                      float g) {
+  const int l = __lane_id(), half = l >> 5, r = l & 31;
+  const f32x4 c = L.u1[l];
+  X.h[l] = f32_to_bf16_bits(mlp_silu(fmaf(c[0], w, fmaf(c[1], g, c[2]))));
+  __syncwarp();
+  bf16x8 B[4];
+#pragma unroll
+  for (int kt = 0; kt < 4; ++kt) B[kt] = *reinterpret_cast<const bf16x8*>(&X.h[16 * kt + 8 * half]);
+  f32x16 acc[2];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) {
+    f32x16 a = {};
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt) a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[mt][kt], B[kt], a, 0, 0, 0);
+    acc[mt] = a;
+  }
+  // acc[r / 16][r % 16] by a select tree on the bits of r
+  float t[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) t[j] = (r & 16) ? acc[1][j] : acc[0][j];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) t[j] = (r & 8) ? t[j + 8] : t[j];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) t[j] = (r & 4) ? t[j + 4] : t[j];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) t[j] = (r & 2) ? t[j + 2] : t[j];
+  const float v = (r & 1) ? t[1] : t[0];
+  const int u = mlp_unit(r >> 4, r & 15, half);
+  X.s[u] = mlp_silu(v + L.u2[u][0]);
+  __syncwarp();
+  float p0 = 0.0f, p1 = 0.0f;
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int u0 = mlp_unit(mt, j, 0), u1 = mlp_unit(mt, j, 1);
+      p0 = fmaf(L.u2[u0][1], X.s[u0], p0);
+      p1 = fmaf(L.u2[u1][1], X.s[u1], p1);
+    }
+  __syncwarp();  // X is rewritten by the next call
+  return w + (p0 + p1) + L.b3;
+}
+
 // The input feature g of the network.
 __device__ __forceinline__ float mlp_g(float loglam, float lo, float inv_span2) {
   return fmaf(loglam - lo, inv_span2, -1.0f);

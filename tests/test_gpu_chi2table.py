@@ -196,9 +196,11 @@ def test_cir_table_exact_kind_matches_surrogate_entry():
 def test_cir_table_split_determinism():
     tab, _ = tables(NU_CIR, 3)
     p = dict(CIR, functional=1)
-    _, whole = run_level(p, 4, 6000, 2, tab, 8)
-    _, first = run_level(p, 4, 2500, 2, tab, 8, 0)
-    _, rest = run_level(p, 4, 3500, 2, tab, 8, 2500)
+    # splits within one launch shape (>= 2^17 paths: one path per thread) are bit-exact
+    n1, n2 = (1 << 17) + 500, (1 << 17) + 1000
+    _, whole = run_level(p, 4, n1 + n2, 2, tab, 8)
+    _, first = run_level(p, 4, n1, 2, tab, 8, 0)
+    _, rest = run_level(p, 4, n2, 2, tab, 8, n1)
     assert np.array_equal(whole, np.concatenate([first, rest]))
     # one path per wavefront (<= 2048 paths): the same paths to FP64 rounding
     _, few = run_level(p, 4, 700, 2, tab, 8, 4000)

@@ -110,17 +110,20 @@ def test_surrogate_kinds_parity(damped, kind, level):
 def test_split_determinism_and_fallbacks(damped):
     s, _ = damped
     p = dict(CIR, functional=1)
-    # splits within one launch shape (> 2048 paths: one path per thread) are bit-exact
-    st, whole = run(p, 2, 6000, 2, s, 5)
-    _, a = run(p, 2, 2500, 2, s, 5, 0)
-    _, b = run(p, 2, 3500, 2, s, 5, 2500)
+    # splits within one launch shape (>= 2^17 paths: one path per thread) are bit-exact
+    n1, n2 = (1 << 17) + 400, (1 << 17) + 600
+    st, whole = run(p, 2, n1 + n2, 2, s, 5)
+    _, a = run(p, 2, n1, 2, s, 5, 0)
+    _, b = run(p, 2, n2, 2, s, 5, n1)
     assert np.array_equal(whole, np.concatenate([a, b]))
     # calls of <= 2048 paths run one path per wavefront, whose cooperative
     # exact inverse sums in another order: the same paths to FP64 rounding
     _, c = run(p, 2, 2000, 2, s, 5, 1000)
     ok, worst = same_paths(c, whole[1000:3000])
     assert ok, worst
-    st2 = A.mlmc_level_cir(p, 2, 6000, 2, s, 5)
+    _, c2 = run(p, 2, 1000, 2, s, 5, 1500)
+    assert np.array_equal(c2, c[500:1500])
+    st2 = A.mlmc_level_cir(p, 2, n1 + n2, 2, s, 5)
     assert st["sum"] == st2["sum"] and st["fallbacks"] == st2["fallbacks"]
     # a surrogate whose range lies below every lambda falls back on every
     # step; one whose range lies above every lambda never does (the network
@@ -183,3 +186,20 @@ def test_thread_per_path_launch_parity(damped, kind):
     _, few = run(p, level, 300, kind, s, seed, 99900)
     ok, worst = same_paths(few, got[99900:100200])
     assert ok, worst
+
+
+def test_one_path_per_wavefront_surrogate_is_bit_exact(damped):
+    # TWOWAY returns P_c = P~_f, the surrogate path alone: its network calls
+    # spread one sample over a wavefront when the call runs one path per
+    # wavefront, with the per-sample arithmetic of the 64-sample call, so
+    # the two launch shapes give the same bits (no fallbacks at these lambda)
+    s, _ = damped
+    for functional, level in ((1, 2), (0, 3)):
+        p = dict(CIR, functional=functional)
+        n = (1 << 17) + 5
+        st, dense = run(p, level, n, 3, s, 71)
+        _, sparse = run(p, level, 300, 3, s, 71, 5000)
+        assert st["fallbacks"] == 0
+        assert np.array_equal(sparse[:, 2], dense[5000:5300, 2])
+        ok, worst = same_paths(sparse, dense[5000:5300])
+        assert ok, worst
