@@ -143,6 +143,23 @@ struct FuncAcc {
   }
 };
 
+// The exact inverse behind a function call, for kernels that also run an
+// approximation: inlined, its registers add to those the approximation keeps
+// live (the network's weight fragments above all) and leave one wave per SIMD;
+// behind a call the kernel needs the larger of the two.
+__device__ __noinline__ double ncx2_icdf_call(double u, double nu, double lam, double x0) {
+  return ncx2_icdf(u, nu, lam, nullptr, x0);
+}
+__device__ __noinline__ double ncx2_icdf_wave_call(double u, double nu, double lam, double x0) {
+  return ncx2_icdf_wave(u, nu, lam, x0);
+}
+
+template <bool SPARSE, bool CALL>
+__device__ __forceinline__ double exact_inverse(double u, double nu, double lam, double x0) {
+  if (CALL) return SPARSE ? ncx2_icdf_wave_call(u, nu, lam, x0) : ncx2_icdf_call(u, nu, lam, x0);
+  return SPARSE ? ncx2_icdf_wave(u, nu, lam, x0) : ncx2_icdf(u, nu, lam, nullptr, x0);
+}
+
 template <int KIND, int FUNC, int APX, bool SPARSE>
 __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const float* __restrict__ params,
                                                                const uint16_t* __restrict__ w2b,
@@ -156,6 +173,7 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
   constexpr bool kPoly = kApx && (APX == APX_POLY1 || APX == APX_POLY3);
   constexpr bool kEm = kApx && APX == APX_EM;
   constexpr bool kSank = kApx && APX == APX_SANKARAN;
+  constexpr bool kCall = kSurr || kEm || kSank;
   __shared__ MlpLds L;
   __shared__ MlpXchg xch[kLevelBlock / 64];  // SPARSE surrogate: one per wave
   __shared__ f32x4 tab[16];
@@ -220,11 +238,7 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
           const float s = lam + a.nuf;
           x = fmaxf(fmaf(2.0f * sqrtf(s), Pt, s), 0.0f);
         } else {
-          if (work)
-            x = float(SPARSE ? ncx2_icdf_wave(double(u24), a.nu, double(lam))
-                             : ncx2_icdf(double(u24), a.nu, double(lam)));
-          else
-            x = 0.0f;
+          x = work ? float(exact_inverse<SPARSE, kCall>(double(u24), a.nu, double(lam), 0.0)) : 0.0f;
           fb += act ? 1 : 0;
         }
         if (kExact) x0 = double(x) + (ve * a.decay / a.c - double(lam));
@@ -254,7 +268,7 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
         // start (relative error ~1e-2 at 30, ~3e-4 at 1000) beats the
         // approximations' (~1e-2), and it is used instead
         if (lam >= 32.0) x0 = 0.0;
-        ve = a.c * (SPARSE ? ncx2_icdf_wave(u53, a.nu, lam, x0) : ncx2_icdf(u53, a.nu, lam, nullptr, x0));
+        ve = a.c * exact_inverse<SPARSE, kCall>(u53, a.nu, lam, x0);
         if (FUNC == 1) fe.node(n + 1, N, ve);
       }
     }

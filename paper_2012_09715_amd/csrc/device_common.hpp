@@ -49,12 +49,11 @@ __device__ __forceinline__ double u53_from_words(uint32_t hi, uint32_t lo) {
   return u == 1.0 ? 1.0 - 0x1p-53 : u;
 }
 
-// FP32 -> BF16 bits, round to nearest even (NaN stays NaN).
+// FP32 -> BF16 bits, round to nearest even (NaN stays NaN): the gfx950
+// conversion instruction (v_cvt_pk_bf16_f32, two values per instruction when
+// the compiler pairs them) instead of integer rounding with a NaN branch.
 __device__ __forceinline__ uint16_t f32_to_bf16_bits(float x) {
-  uint32_t b = __float_as_uint(x);
-  if ((b & 0x7FFFFFFFu) > 0x7F800000u) return uint16_t((b >> 16) | 0x40u);
-  b += 0x7FFFu + ((b >> 16) & 1u);
-  return uint16_t(b >> 16);
+  return __builtin_bit_cast(uint16_t, static_cast<__bf16>(x));
 }
 
 __device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }

@@ -98,26 +98,34 @@ __device__ __forceinline__ int mlp_unit(int mt, int j, int half) { return 32 * m
 // Full forward pass; every lane of the wave must call it.  Returns P~ of the
 // lane's own sample.
 __device__ __forceinline__ float mlp_wave_forward(const MlpLds& L, const bf16x8 (&A)[2][4], float w, float g) {
+  // the parameters are read from LDS at every call: hoisted out of a caller's
+  // loop they would hold ~200 VGPRs and leave one wave per SIMD
+  asm volatile("" ::: "memory");
   const int l = __lane_id(), half = l >> 5;
   const float wo = __shfl_xor(w, 32), go = __shfl_xor(g, 32);
   const float ws[2] = {half ? wo : w, half ? w : wo};
   const float gs[2] = {half ? go : g, half ? g : go};
   bf16x8 B[2][4];
   mlp_layer1(L, ws, gs, B);
-  f32x16 acc[2][2];
-  mlp_layer2(A, B, acc);
-  float part[2] = {0.0f, 0.0f};
+  // layer 2 and 3 one (sample tile, unit tile) at a time: the sums of one
+  // sample tile run over mt, then j, as in a single pass
+  float part[2];
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
+  for (int nt = 0; nt < 2; ++nt) {
+    float p = 0.0f;
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
+    for (int mt = 0; mt < 2; ++mt) {
+      f32x16 acc = {};
+#pragma unroll
+      for (int kt = 0; kt < 4; ++kt) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[mt][kt], B[nt][kt], acc, 0, 0, 0);
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const f32x2 p = L.u2[mlp_unit(mt, j, half)];
-        part[nt] = fmaf(p[1], mlp_silu(acc[mt][nt][j] + p[0]), part[nt]);
+        const f32x2 q = L.u2[mlp_unit(mt, j, half)];
+        p = fmaf(q[1], mlp_silu(acc[j] + q[0]), p);
       }
-  part[0] += __shfl_xor(part[0], 32);
-  part[1] += __shfl_xor(part[1], 32);
+    }
+    part[nt] = p + __shfl_xor(p, 32);
+  }
   return w + (half ? part[1] : part[0]) + L.b3;
 }
 
@@ -141,6 +149,7 @@ struct alignas(16) MlpXchg {
 // control flow.
 __device__ __forceinline__ float mlp_wave_forward_one(const MlpLds& L, MlpXchg& X, const bf16x8 (&A)[2][4], float w,
                                                       float g) {
+  asm volatile("" ::: "memory");  // parameters from LDS at every call (as above)
   const int l = __lane_id(), half = l >> 5, r = l & 31;
   const f32x4 c = L.u1[l];
   X.h[l] = f32_to_bf16_bits(mlp_silu(fmaf(c[0], w, fmaf(c[1], g, c[2]))));

@@ -247,3 +247,22 @@ def test_full_size_u24_stream_sampled():
     assert abs(m) < 5.0 / np.sqrt(n) * 1.0
     del u, z
     torch.cuda.empty_cache()
+
+
+def test_half_outputs_are_rne_of_the_f32_output():
+    # the F16/BF16 outputs are the FP32 result rounded to nearest even (the
+    # BF16 one by the hardware conversion): checked bit for bit against the
+    # oracle's integer RNE on about 2^20 values, ties included
+    from oracle.dtypes import bf16_bits_from_f64
+    tab = A.Table.dyadic(16, 3)
+    u = torch.from_numpy(inputs("f32", 1 << 20, seed=99)).to(DEV)
+    z32 = A.approx_icdf_linear(tab, u).cpu().numpy()
+    zb = A.approx_icdf_linear(tab, u, out_dtype=torch.bfloat16).view(torch.int16).cpu().numpy().view(np.uint16)
+    zh = A.approx_icdf_linear(tab, u, out_dtype=torch.float16).cpu().numpy()
+    ok = np.isfinite(z32) & ((z32 == 0) | (np.abs(z32) >= 2.0 ** -126))
+    assert ok.sum() > (1 << 20) - 16
+    want = bf16_bits_from_f64(z32[ok].astype(np.float64))
+    assert np.array_equal(zb[ok], want)
+    assert np.sum((z32[ok].view(np.uint32) & 0xFFFF) == 0x8000) >= 1  # a tie was exercised
+    assert np.array_equal(zh[ok].view(np.uint16), z32[ok].astype(np.float64).astype(np.float16).view(np.uint16))
+    assert np.array_equal((zb & 0x7FFF) > 0x7F80, np.isnan(z32))
