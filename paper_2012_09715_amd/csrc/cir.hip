@@ -143,10 +143,12 @@ struct FuncAcc {
   }
 };
 
-// The exact inverse behind a function call, for kernels that also run an
-// approximation: inlined, its registers add to those the approximation keeps
-// live (the network's weight fragments above all) and leave one wave per SIMD;
-// behind a call the kernel needs the larger of the two.
+// The exact inverse behind a function call, for the one-path-per-thread
+// kernels that also run an approximation: inlined, its registers add to those
+// the approximation keeps live (the network's weight fragments above all) and
+// leave one wave per SIMD; behind a call the kernel needs the larger of the
+// two.  (One path per wavefront the network reads its weights from LDS and
+// the inverse stays inline: there a call's register saves cost more.)
 __device__ __noinline__ double ncx2_icdf_call(double u, double nu, double lam, double x0) {
   return ncx2_icdf(u, nu, lam, nullptr, x0);
 }
@@ -173,17 +175,21 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
   constexpr bool kPoly = kApx && (APX == APX_POLY1 || APX == APX_POLY3);
   constexpr bool kEm = kApx && APX == APX_EM;
   constexpr bool kSank = kApx && APX == APX_SANKARAN;
-  constexpr bool kCall = kSurr || kEm || kSank;
+  constexpr bool kCall = !SPARSE && (kSurr || kEm || kSank);
   __shared__ MlpLds L;
   __shared__ MlpXchg xch[kLevelBlock / 64];  // SPARSE surrogate: one per wave
+  __shared__ __align__(16) uint16_t w2s[SPARSE && kSurr ? kHidden * kW2Stride : 8];  // SPARSE surrogate: W2
   __shared__ f32x4 tab[16];
   extern __shared__ f32x4 ctab[];  // APX_POLY*: the chi-squared table (dynamic LDS)
   bf16x8 A[2][4];
   if (kSurr) {
     mlp_stage_params(L, params, threadIdx.x, kLevelBlock);
     if (threadIdx.x < 16) tab[threadIdx.x] = wtab[threadIdx.x];
+    if (SPARSE) mlp_stage_w2(w2s, w2b, threadIdx.x, kLevelBlock);
     __syncthreads();
-    mlp_load_w2(w2b, A);
+    // one path per wavefront: the W2 fragments come from LDS at each call,
+    // which leaves the wave-cooperative exact inverse its registers
+    if (!SPARSE) mlp_load_w2(w2b, A);
   }
   if (kPoly) {
     for (uint32_t r = threadIdx.x; r < a.table_rows; r += kLevelBlock) ctab[r] = wtab[r];
@@ -231,13 +237,14 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
         const bool inr = ll <= a.hi;
         const float g = inr ? mlp_g(fmaxf(ll, a.lo), a.lo, a.inv_span2) : 0.0f;
         // all lanes; one path per wavefront: one sample spread over the wave
-        const float Pt = SPARSE ? mlp_wave_forward_one(L, xch[threadIdx.x / 64], A, dyadic_w16(u24, tab), g)
+        const float Pt = SPARSE ? mlp_wave_forward_one(L, xch[threadIdx.x / 64], w2s, dyadic_w16(u24, tab), g)
                                 : mlp_wave_forward(L, A, dyadic_w16(u24, tab), g);
         float x;
         if (inr) {
           const float s = lam + a.nuf;
           x = fmaxf(fmaf(2.0f * sqrtf(s), Pt, s), 0.0f);
         } else {
+          // (rare: behind a call in every shape)
           x = work ? float(exact_inverse<SPARSE, kCall>(double(u24), a.nu, double(lam), 0.0)) : 0.0f;
           fb += act ? 1 : 0;
         }

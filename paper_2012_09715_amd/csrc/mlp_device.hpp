@@ -129,6 +129,20 @@ __device__ __forceinline__ float mlp_wave_forward(const MlpLds& L, const bf16x8 
   return w + (half ? part[1] : part[0]) + L.b3;
 }
 
+// W2 in LDS for mlp_wave_forward_one: BF16 rows of kHidden inputs padded to
+// kW2Stride, so that the 16-byte fragment reads of 8 consecutive rows fall in
+// distinct banks.
+constexpr int kW2Stride = kHidden + 8;
+
+__device__ __forceinline__ void mlp_stage_w2(uint16_t* __restrict__ w2s, const uint16_t* __restrict__ w2b, int tid,
+                                             int nthreads) {
+  for (int c = tid; c < kHidden * kHidden / 8; c += nthreads) {
+    const int row = c / (kHidden / 8), col = 8 * (c % (kHidden / 8));
+    *reinterpret_cast<bf16x8*>(w2s + row * kW2Stride + col) =
+        *reinterpret_cast<const bf16x8*>(w2b + row * kHidden + col);
+  }
+}
+
 // Per-wave LDS exchange of mlp_wave_forward_one.
 struct alignas(16) MlpXchg {
   uint16_t h[kHidden];  // bf16 bits of the layer-1 values
@@ -147,10 +161,18 @@ struct alignas(16) MlpXchg {
 // LDS again.  Each lane then runs both halves' FMA chains in the order of
 // mlp_wave_forward.  Every lane of the wave must call it, with wave-uniform
 // control flow.
-__device__ __forceinline__ float mlp_wave_forward_one(const MlpLds& L, MlpXchg& X, const bf16x8 (&A)[2][4], float w,
-                                                      float g) {
+__device__ __forceinline__ float mlp_wave_forward_one(const MlpLds& L, MlpXchg& X, const uint16_t* __restrict__ w2s,
+                                                      float w, float g) {
   asm volatile("" ::: "memory");  // parameters from LDS at every call (as above)
   const int l = __lane_id(), half = l >> 5, r = l & 31;
+  // the W2 fragments of mlp_load_w2, from the padded LDS copy (the caller
+  // keeps no registers for them between calls)
+  bf16x8 A[2][4];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt)
+      A[mt][kt] = *reinterpret_cast<const bf16x8*>(w2s + (32 * mt + r) * kW2Stride + 16 * kt + 8 * half);
   const f32x4 c = L.u1[l];
   X.h[l] = f32_to_bf16_bits(mlp_silu(fmaf(c[0], w, fmaf(c[1], g, c[2]))));
   __syncwarp();
