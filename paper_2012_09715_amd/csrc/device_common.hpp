@@ -63,34 +63,53 @@ __device__ __forceinline__ uint16_t f32_to_f16_bits(float x) {
   return __builtin_bit_cast(uint16_t, h);
 }
 
-// Exact inverse normal CDF in FP64.  q = min(u, 1 - u); initial value from
-// Abramowitz & Stegun 26.2.23 (Hastings' rational approximation in
-// t = sqrt(-2 log q), |error| < 4.5e-4), then two Halley steps on
-// f(z) = Phi(z) - q, f' = phi(z), f'' = -z phi(z):
-//   z <- z - r / (1 + z r / 2),  r = f / phi(z).
-// Phi(z) - q is formed as erf(z/sqrt2)/2 - (q - 1/2) when q >= 1/4 (the
-// subtraction is exact there) and as erfc(-z/sqrt2)/2 - q otherwise.
-// ITERS = 1 stops after one Halley step (|error| ~1e-10: a starting value).
-template <int ITERS = 2>
-__host__ __device__ __forceinline__ double exact_phi_inv(double u) {
-  const bool upper = u > 0.5;
-  const double q = upper ? 1.0 - u : u;
-  const double t = sqrt(-2.0 * log(q));
-  const double num = 2.515517 + t * (0.802853 + t * 0.010328);
-  const double den = 1.0 + t * (1.432788 + t * (0.189269 + t * 0.001308));
-  double z = num / den - t;
-  const bool central = q >= 0.25;
+// Exact inverse normal CDF in FP64: Wichura's algorithm AS 241 (PPND16,
+// Applied Statistics 37 (1988) 477-484).  With q = u - 1/2:
+//   |q| <= 0.425   z = q A(r) / B(r),  r = 0.180625 - q^2
+//   otherwise      s = sqrt(-log(min(u, 1 - u)));  z = +-C(s - 1.6) / D(s - 1.6)
+//                  for s <= 5, +-E(s - 5) / F(s - 5) beyond (sign of q)
+// with A..F polynomials of degree 7 (published coefficients).  Relative
+// error about 1e-16 by design, below 1e-15 measured against 50-digit roots;
+// a few FMAs and one division in the centre, one log and one sqrt more in
+// the tails (no iteration).  u = 0 and u = 1 give -inf and +inf.
+__host__ __device__ __forceinline__ double phi_inv_poly7(const double (&c)[8], double x) {
+  double s = c[7];
 #pragma unroll
-  for (int it = 0; it < ITERS; ++it) {
-    const double f = central ? 0.5 * erf(z * 0.70710678118654752440) - (q - 0.5)
-                             : 0.5 * erfc(-z * 0.70710678118654752440) - q;
-    const double pdf = 0.39894228040143267794 * exp(-0.5 * z * z);
-    const double r = f / pdf;
-    z = z - r / fma(0.5 * z, r, 1.0);
+  for (int k = 6; k >= 0; --k) s = fma(s, x, c[k]);
+  return s;
+}
+
+__host__ __device__ __forceinline__ double exact_phi_inv(double u) {
+  constexpr double A[8] = {3.3871328727963666080e0, 1.3314166789178437745e+2, 1.9715909503065514427e+3,
+                           1.3731693765509461125e+4, 4.5921953931549871457e+4, 6.7265770927008700853e+4,
+                           3.3430575583588128105e+4, 2.5090809287301226727e+3};
+  constexpr double B[8] = {1.0, 4.2313330701600911252e+1, 6.8718700749205790830e+2, 5.3941960214247511077e+3,
+                           2.1213794301586595867e+4, 3.9307895800092710610e+4, 2.8729085735721942674e+4,
+                           5.2264952788528545610e+3};
+  constexpr double C[8] = {1.42343711074968357734e0, 4.63033784615654529590e0, 5.76949722146069140550e0,
+                           3.64784832476320460504e0, 1.27045825245236838258e0, 2.41780725177450611770e-1,
+                           2.27238449892691845833e-2, 7.74545014278341407640e-4};
+  constexpr double D[8] = {1.0, 2.05319162663775882187e0, 1.67638483018380384940e0, 6.89767334985100004550e-1,
+                           1.48103976427480074590e-1, 1.51986665636164571966e-2, 5.47593808499534494600e-4,
+                           1.05075007164441684324e-9};
+  constexpr double E[8] = {6.65790464350110377720e0, 5.46378491116411436990e0, 1.78482653991729133580e0,
+                           2.96560571828504891230e-1, 2.65321895265761230930e-2, 1.24266094738807843860e-3,
+                           2.71155556874348757815e-5, 2.01033439929228813265e-7};
+  constexpr double F[8] = {1.0, 5.99832206555887937690e-1, 1.36929880922735805310e-1, 1.48753612908506148525e-2,
+                           7.86869131145613259100e-4, 1.84631831751005468180e-5, 1.42151175831644588870e-7,
+                           2.04426310338993978564e-15};
+  const double q = u - 0.5;
+  if (fabs(q) <= 0.425) {
+    const double r = fma(-q, q, 0.180625);
+    return q * phi_inv_poly7(A, r) / phi_inv_poly7(B, r);
   }
-  z = (q == 0.5) ? 0.0 : z;
-  z = (q == 0.0) ? -__builtin_inf() : z;
-  return upper ? -z : z;
+  if (u == 0.0) return -__builtin_inf();
+  if (u == 1.0) return __builtin_inf();
+  const double s = sqrt(-log(fmin(u, 1.0 - u)));
+  const bool mid = s <= 5.0;
+  const double x = s - (mid ? 1.6 : 5.0);
+  const double z = mid ? phi_inv_poly7(C, x) / phi_inv_poly7(D, x) : phi_inv_poly7(E, x) / phi_inv_poly7(F, x);
+  return q < 0.0 ? -z : z;
 }
 
 }  // namespace aicdf

@@ -264,7 +264,7 @@ __host__ __device__ inline __noinline__ double ncx2_guess(double t, bool upper, 
 // (against ~3e-4 for the scaled central chi-squared start), which leaves one
 // or two Halley steps.  Returns 0 where B <= 0 (far lower tail).
 __host__ __device__ inline __noinline__ double ncx2_sankaran_start(double t, bool upper, double nu, double lam) {
-  const double z = upper ? -exact_phi_inv<1>(t) : exact_phi_inv<1>(t);
+  const double z = upper ? -exact_phi_inv(t) : exact_phi_inv(t);
   const double kl = nu + lam, k2l = nu + 2.0 * lam, k3l = nu + 3.0 * lam;
   const double c1 = 1.0 - (2.0 / 3.0) * kl * k3l / (k2l * k2l);
   const double c2 = k2l / (kl * kl);
