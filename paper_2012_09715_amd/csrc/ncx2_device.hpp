@@ -41,12 +41,32 @@ struct Ncx2Val {
 // P(A, y) and Q(A, y) with t = y^A e^-y / Gamma(A+1) given (A > 0, y > 0).
 __host__ __device__ inline void inc_gamma_pq(double A, double y, double t, double& P, double& Q) {
   if (y < A + 1.0) {
-    // P = t * sum_k y^k / ((A+1)...(A+k))
+    // P = t * sum_k y^k / ((A+1)...(A+k)), four terms per division: with
+    // d1..d4 the next four denominators and r = 1/(d1 d2 d3 d4), the terms
+    // are T y/d1 = T y (d2 d3 d4 r), T y^2/(d1 d2) = T y^2 (d3 d4 r), ...
+    // (A < 2^60 keeps the product of four denominators far from overflow)
     double term = 1.0, sum = 1.0;
-    for (int k = 1; k < 100000; ++k) {
-      term *= y / (A + k);
-      sum += term;
-      if (term < sum * 1e-17) break;
+    if (A < 0x1p60) {
+      const double y2 = y * y;
+      for (int k = 1; k < 100000; k += 4) {
+        const double d1 = A + k, d3 = d1 + 2.0, d4 = d1 + 3.0;
+        const double d34 = d3 * d4, d234 = (d1 + 1.0) * d34;
+        const double r = 1.0 / (d1 * d234);
+        const double ty = term * y;
+        const double t1 = ty * (d234 * r), t2 = ty * y * (d34 * r), t3 = ty * y2 * (d4 * r);
+        term = ty * y2 * y * r;
+        sum += t1;
+        sum += t2;
+        sum += t3;
+        sum += term;
+        if (term < sum * 1e-17) break;
+      }
+    } else {
+      for (int k = 1; k < 100000; ++k) {
+        term *= y / (A + k);
+        sum += term;
+        if (term < sum * 1e-17) break;
+      }
     }
     P = t * sum;
     Q = 1.0 - P;
