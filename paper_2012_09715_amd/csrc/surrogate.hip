@@ -290,11 +290,14 @@ __global__ __launch_bounds__(256) void mlp_reduce_kernel(const float* __restrict
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (p == kNParams) {
     double s = 0.0;
+#pragma unroll 16
     for (unsigned b = 0; b < nblocks; ++b) s += loss_part[b];
     grad_out[kNParams] += s;  // running loss sum
   }
   if (p >= kNParams) return;
   double g = 0.0;
+  // unrolled so that the loads are in flight together; the sum keeps its order
+#pragma unroll 16
   for (unsigned b = 0; b < nblocks; ++b) g += partials[size_t(b) * kNParams + p];
   if (!adam) {
     grad_out[p] = g;
