@@ -20,6 +20,8 @@ __global__ __launch_bounds__(kLevelBlock) void reduce_partials_kernel(const doub
                                                                       double n_paths, double* __restrict__ out) {
   __shared__ double red[kSums][kLevelBlock];
   KSum k[kSums];
+  // unrolled so that several blocks' loads are in flight together (same order)
+#pragma unroll 8
   for (unsigned b = threadIdx.x; b < nblocks; b += kLevelBlock)
 #pragma unroll
     for (int j = 0; j < kSums; ++j) k[j].add(partials[size_t(b) * kSums + j]);
