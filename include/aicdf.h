@@ -306,10 +306,12 @@ typedef struct aicdf_surrogate aicdf_surrogate;
  * order: always at most 2048 paths, never 2^17 or more, and in between
  * below a cost model's crossover (it grows with lambda at the process level
  * max(v0, theta) and with the waves the kernel keeps resident); their
- * per-path values agree with those of the other shape to 1e-11 relative
- * (rounding of the sums, which can steer the root iteration to another last
- * step; the surrogate's values are bit-identical) and are bit-identical
- * between calls of the same launch shape.  Errors: EINVAL, ERANGE, EHIP, ENOMEM. */
+ * per-path values agree with those of the other shape to 1e-11 relative for
+ * up to 16 steps, growing along longer paths (4e-11 measured at 256 steps):
+ * each exact inverse's sums round differently, which can steer the root
+ * iteration to another last step (the surrogate's values are
+ * bit-identical).  Values are bit-identical between calls of the same
+ * launch shape.  Errors: EINVAL, ERANGE, EHIP, ENOMEM. */
 aicdf_status mlmc_level_cir(const aicdf_cir_params* params, uint32_t level, uint64_t n_paths,
                             int32_t kind, const aicdf_surrogate* approx, uint64_t seed,
                             uint64_t path_offset, aicdf_level_sums* out, double* path_out,

@@ -72,6 +72,15 @@ def run(params, level, n, kind, sur, seed, offset=0):
     return s, out.cpu().numpy().reshape(n, 3)
 
 
+def shape_rel(level):
+    """Agreement of the two launch shapes' exact paths: the sums of each
+    exact inverse round differently (up to ~1e-12 relative, amplified by 2/nu
+    in the lower tail), and the differences add up along the 2^level steps of
+    a path (4e-11 measured at level 8), so 1e-11 up to 16 steps and in
+    proportion beyond."""
+    return 1e-11 * max(1.0, (1 << level) / 16.0)
+
+
 def same_paths(a, b, rel=1e-11):
     """Per-path agreement of (Y, P_f, P_c) rows from two launch shapes,
     relative to the row's functional scale max(|P_f|, |P_c|): Y is a
@@ -203,3 +212,19 @@ def test_one_path_per_wavefront_surrogate_is_bit_exact(damped):
         assert np.array_equal(sparse[:, 2], dense[5000:5300, 2])
         ok, worst = same_paths(sparse, dense[5000:5300])
         assert ok, worst
+
+
+@pytest.mark.parametrize("level", [2, 8])
+def test_mid_size_calls_follow_a_launch_shape(level):
+    # between 2048 and 2^17 paths the launch shape comes from the cost model
+    # (resident waves of the kernel, lambda at the process level); whichever
+    # it picks, the paths agree with both fixed shapes to FP64 rounding
+    p = dict(CIR, functional=1)
+    seed, off = 77, 3000
+    _, dense = run(p, level, (1 << 17) + 3, 0, None, seed)
+    for n in (5000, 40000):
+        _, mid = run(p, level, n, 0, None, seed, off)
+        ok, worst = same_paths(mid, dense[off:off + n], shape_rel(level))
+        assert ok, (n, worst)
+        _, few = run(p, level, 1000, 0, None, seed, off)
+        assert np.array_equal(few, mid[:1000]) or same_paths(few, mid[:1000], shape_rel(level))[0]
