@@ -228,3 +228,18 @@ def test_mid_size_calls_follow_a_launch_shape(level):
         assert ok, (n, worst)
         _, few = run(p, level, 1000, 0, None, seed, off)
         assert np.array_equal(few, mid[:1000]) or same_paths(few, mid[:1000], shape_rel(level))[0]
+
+
+def test_exact_kind_parity_long_paths():
+    # 256 exact steps per path (level 8), both launch shapes, against the
+    # oracle's replay of the same draws (bisection on the series CDF)
+    p = dict(CIR, functional=1)
+    seed, level = 91, 8
+    pick = np.array([12345, 12346])
+    ref = cir.level_replay(p, level, 0, seed, pick)
+    scale = np.maximum(np.abs(ref[1]), 1e-3)
+    _, few = run(p, level, 2, 0, None, seed, int(pick[0]))  # one path per wavefront
+    _, dense = run(p, level, (1 << 17) + 1, 0, None, seed)   # one path per thread
+    for got in (few, dense[pick]):
+        for j in range(3):
+            assert np.all(np.abs(got[:, j] - ref[j]) <= 1e-9 * scale), j
