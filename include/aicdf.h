@@ -181,9 +181,10 @@ aicdf_status approx_icdf_index(const aicdf_table* table, size_t n, const void* u
                                uint32_t* idx, void* stream);
 
 /* Exact inverse normal CDF Phi^-1 in FP64 (Section 3.1 describes the library
- * routines this stands for): an initial value from Abramowitz & Stegun
- * 26.2.23 refined by two Halley steps on Phi(z) - q with q = min(u, 1-u),
- * Phi evaluated through erf (q >= 1/4) or erfc (q < 1/4).
+ * routines this stands for): Wichura's algorithm AS 241 (Applied Statistics
+ * 37, 1988), rational functions of degree 7 in three regions of u, relative
+ * error about 1e-16 (below 1e-15 measured against 50-digit roots).  The same
+ * routine gives the exact normals of the fused GBM levels.
  * (u_t, z_t) in {(F64,F64), (F64,F32), (F32,F64), (F32,F32)}; u = 0 and
  * u = 1 give -inf and +inf.  Errors: EINVAL, EDTYPE, EALIAS, EHIP. */
 aicdf_status exact_icdf(size_t n, const void* u, aicdf_dtype u_t, void* z, aicdf_dtype z_t,
