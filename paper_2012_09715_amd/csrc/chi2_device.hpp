@@ -59,7 +59,8 @@ __device__ __forceinline__ float chi2_approx_x(float u, float lam, const f32x4* 
 }
 
 // The Sankaran approximation, Section 5.1's comparator (Table 6d), in FP32
-// around an FP64 exact normal: with k = nu,
+// (the normal quantile too: AS 241 in FP32, far below the approximation's own
+// error): with k = nu,
 //   c1 = 1 - (2/3)(k+lambda)(k+3 lambda)/(k+2 lambda)^2,
 //   c2 = (k+2 lambda)/(k+lambda)^2,  c3 = (c1-1)(1-3 c1),
 //   B  = 1 + c1 c2 (c1 - 1 + (2-c1) c2 c3/2) + c1 sqrt(2 c2)(1 + c2 c3/2) Phi^-1(u),
@@ -71,7 +72,7 @@ __device__ __forceinline__ float sankaran_x(float u, float lam, float nu) {
   const float c1 = 1.0f - (2.0f / 3.0f) * kl * k3l / (k2l * k2l);
   const float c2 = k2l / (kl * kl);
   const float c3 = (c1 - 1.0f) * (1.0f - 3.0f * c1);
-  const float z = float(exact_phi_inv(double(u)));
+  const float z = approx_phi_inv_f32(u);
   const float a = fmaf(0.5f * (2.0f - c1) * c2, c3, c1 - 1.0f);
   const float g = c1 * sqrtf(2.0f * c2) * fmaf(0.5f * c2, c3, 1.0f);
   const float B = fmaf(g, z, fmaf(c1 * c2, a, 1.0f));

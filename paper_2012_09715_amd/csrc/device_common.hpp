@@ -19,7 +19,7 @@ using u16x4 = vec_t<uint16_t, 4>;
 // Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
 // 32x32->64 multiplications with the round keys bumped by the Weyl constants.
 __device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                               uint32_t k0, uint32_t k1) {
+                                                   uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint32_t lo0 = c0 * 0xD2511F53u, hi0 = __umulhi(c0, 0xD2511F53u);
@@ -72,6 +72,27 @@ __device__ __forceinline__ uint16_t f32_to_f16_bits(float x) {
 // error about 1e-16 by design, below 1e-15 measured against 50-digit roots;
 // a few FMAs and one division in the centre, one log and one sqrt more in
 // the tails (no iteration).  u = 0 and u = 1 give -inf and +inf.
+// The coefficients of AS 241 (PPND16): numerator and denominator of the
+// central region (A, B), the middle tail (C, D) and the far tail (E, F).
+constexpr double kAs241A[8] = {3.3871328727963666080e0, 1.3314166789178437745e+2, 1.9715909503065514427e+3,
+                               1.3731693765509461125e+4, 4.5921953931549871457e+4, 6.7265770927008700853e+4,
+                               3.3430575583588128105e+4, 2.5090809287301226727e+3};
+constexpr double kAs241B[8] = {1.0, 4.2313330701600911252e+1, 6.8718700749205790830e+2, 5.3941960214247511077e+3,
+                               2.1213794301586595867e+4, 3.9307895800092710610e+4, 2.8729085735721942674e+4,
+                               5.2264952788528545610e+3};
+constexpr double kAs241C[8] = {1.42343711074968357734e0, 4.63033784615654529590e0, 5.76949722146069140550e0,
+                               3.64784832476320460504e0, 1.27045825245236838258e0, 2.41780725177450611770e-1,
+                               2.27238449892691845833e-2, 7.74545014278341407640e-4};
+constexpr double kAs241D[8] = {1.0, 2.05319162663775882187e0, 1.67638483018380384940e0, 6.89767334985100004550e-1,
+                               1.48103976427480074590e-1, 1.51986665636164571966e-2, 5.47593808499534494600e-4,
+                               1.05075007164441684324e-9};
+constexpr double kAs241E[8] = {6.65790464350110377720e0, 5.46378491116411436990e0, 1.78482653991729133580e0,
+                               2.96560571828504891230e-1, 2.65321895265761230930e-2, 1.24266094738807843860e-3,
+                               2.71155556874348757815e-5, 2.01033439929228813265e-7};
+constexpr double kAs241F[8] = {1.0, 5.99832206555887937690e-1, 1.36929880922735805310e-1, 1.48753612908506148525e-2,
+                               7.86869131145613259100e-4, 1.84631831751005468180e-5, 1.42151175831644588870e-7,
+                               2.04426310338993978564e-15};
+
 __host__ __device__ __forceinline__ double phi_inv_poly7(const double (&c)[8], double x) {
   double s = c[7];
 #pragma unroll
@@ -80,24 +101,12 @@ __host__ __device__ __forceinline__ double phi_inv_poly7(const double (&c)[8], d
 }
 
 __host__ __device__ __forceinline__ double exact_phi_inv(double u) {
-  constexpr double A[8] = {3.3871328727963666080e0, 1.3314166789178437745e+2, 1.9715909503065514427e+3,
-                           1.3731693765509461125e+4, 4.5921953931549871457e+4, 6.7265770927008700853e+4,
-                           3.3430575583588128105e+4, 2.5090809287301226727e+3};
-  constexpr double B[8] = {1.0, 4.2313330701600911252e+1, 6.8718700749205790830e+2, 5.3941960214247511077e+3,
-                           2.1213794301586595867e+4, 3.9307895800092710610e+4, 2.8729085735721942674e+4,
-                           5.2264952788528545610e+3};
-  constexpr double C[8] = {1.42343711074968357734e0, 4.63033784615654529590e0, 5.76949722146069140550e0,
-                           3.64784832476320460504e0, 1.27045825245236838258e0, 2.41780725177450611770e-1,
-                           2.27238449892691845833e-2, 7.74545014278341407640e-4};
-  constexpr double D[8] = {1.0, 2.05319162663775882187e0, 1.67638483018380384940e0, 6.89767334985100004550e-1,
-                           1.48103976427480074590e-1, 1.51986665636164571966e-2, 5.47593808499534494600e-4,
-                           1.05075007164441684324e-9};
-  constexpr double E[8] = {6.65790464350110377720e0, 5.46378491116411436990e0, 1.78482653991729133580e0,
-                           2.96560571828504891230e-1, 2.65321895265761230930e-2, 1.24266094738807843860e-3,
-                           2.71155556874348757815e-5, 2.01033439929228813265e-7};
-  constexpr double F[8] = {1.0, 5.99832206555887937690e-1, 1.36929880922735805310e-1, 1.48753612908506148525e-2,
-                           7.86869131145613259100e-4, 1.84631831751005468180e-5, 1.42151175831644588870e-7,
-                           2.04426310338993978564e-15};
+  const auto& A = kAs241A;
+  const auto& B = kAs241B;
+  const auto& C = kAs241C;
+  const auto& D = kAs241D;
+  const auto& E = kAs241E;
+  const auto& F = kAs241F;
   const double q = u - 0.5;
   if (fabs(q) <= 0.425) {
     const double r = fma(-q, q, 0.180625);
@@ -110,6 +119,33 @@ __host__ __device__ __forceinline__ double exact_phi_inv(double u) {
   const double x = s - (mid ? 1.6 : 5.0);
   const double z = mid ? phi_inv_poly7(C, x) / phi_inv_poly7(D, x) : phi_inv_poly7(E, x) / phi_inv_poly7(F, x);
   return q < 0.0 ? -z : z;
+}
+
+// Phi^-1 in FP32 for approximations whose own error is far larger (the
+// Sankaran comparator, the truncated Euler-Maruyama step): the rational
+// functions of AS 241 evaluated in FP32 arithmetic (relative error a few FP32
+// ulps).  u = 0 and u = 1 give -inf and +inf.
+__device__ __forceinline__ float phi_inv_poly7f(const double (&c)[8], float x) {
+  float s = float(c[7]);
+#pragma unroll
+  for (int k = 6; k >= 0; --k) s = fmaf(s, x, float(c[k]));
+  return s;
+}
+
+__device__ __forceinline__ float approx_phi_inv_f32(float u) {
+  const float q = u - 0.5f;
+  if (fabsf(q) <= 0.425f) {
+    const float r = fmaf(-q, q, 0.180625f);
+    return q * phi_inv_poly7f(kAs241A, r) / phi_inv_poly7f(kAs241B, r);
+  }
+  if (u == 0.0f) return -__builtin_inff();
+  if (u == 1.0f) return __builtin_inff();
+  const float s = sqrtf(-logf(fminf(u, 1.0f - u)));
+  const bool mid = s <= 5.0f;
+  const float x = s - (mid ? 1.6f : 5.0f);
+  const float z = mid ? phi_inv_poly7f(kAs241C, x) / phi_inv_poly7f(kAs241D, x)
+                      : phi_inv_poly7f(kAs241E, x) / phi_inv_poly7f(kAs241F, x);
+  return q < 0.0f ? -z : z;
 }
 
 }  // namespace aicdf
