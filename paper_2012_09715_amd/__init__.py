@@ -92,10 +92,12 @@ class Table:
         check(lib.aicdf_table_coeffs(self._h, buf, len(buf), None, None))
         return torch.tensor(list(buf), dtype=torch.float64).reshape(rows.value, cols.value)
 
-    def __del__(self):
+    def __del__(self, _lib=lib):
+        # _lib: bound at definition, since module globals may already be
+        # cleared when objects are finalised at interpreter exit
         h, self._h = getattr(self, "_h", None), None
         if h:
-            lib.aicdf_table_destroy(h)
+            _lib.aicdf_table_destroy(h)
 
 
 def table_host_coeffs(kind, n, param, coef_dtype=torch.float32):
@@ -340,10 +342,12 @@ class Chi2Table:
         return torch.tensor(list(buf), dtype=torch.float64).reshape(self.n_knots, 2, self.n_intervals,
                                                                     self.degree + 1)
 
-    def __del__(self):
+    def __del__(self, _lib=lib):
+        # _lib: bound at definition, since module globals may already be
+        # cleared when objects are finalised at interpreter exit
         h, self._h = getattr(self, "_h", None), None
         if h:
-            lib.aicdf_chi2_table_destroy(h)
+            _lib.aicdf_chi2_table_destroy(h)
 
 
 def chi2_host_coeffs(nu, degree=1, n_knots=16, n_intervals=15):
@@ -438,7 +442,9 @@ class Surrogate:
                                         _stream(stream)))
         return loss.value
 
-    def __del__(self):
+    def __del__(self, _lib=lib):
+        # _lib: bound at definition, since module globals may already be
+        # cleared when objects are finalised at interpreter exit
         h, self._h = getattr(self, "_h", None), None
         if h:
-            lib.aicdf_surrogate_destroy(h)
+            _lib.aicdf_surrogate_destroy(h)

@@ -68,6 +68,7 @@ aicdf_status get_workspace(hipStream_t s, Workspace** out) {
   if (!ws) return fail(AICDF_ENOMEM, "host allocation failed");
   if (hipMalloc(&ws->partials, sizeof(double) * kMaxLevelBlocks * kSums) != hipSuccess ||
       hipMalloc(&ws->result, sizeof(double) * kSumsOut) != hipSuccess ||
+      hipHostMalloc(&ws->host_result, sizeof(double) * kSumsOut, hipHostMallocDefault) != hipSuccess ||
       hipMalloc(&ws->counter, sizeof(unsigned long long)) != hipSuccess) {
     delete ws;
     return fail(AICDF_ENOMEM, "hipMalloc of the level workspace failed");
@@ -87,15 +88,17 @@ aicdf_status begin_level(Workspace* ws, hipStream_t s, const LevelOut& o) {
 }
 
 aicdf_status finish_level(Workspace* ws, unsigned nblocks, hipStream_t s, double n_paths, const LevelOut& o) {
-  double* dst = o.host ? ws->result : o.dev;
+  // the host path's final pass writes straight into pinned host memory: no
+  // copy is queued, and the wait for the stream makes its writes visible
+  double* dst = o.host ? ws->host_result : o.dev;
   hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kLevelBlock), 0, s, ws->partials, nblocks, ws->counter,
                      n_paths, dst);
   AICDF_HIP(hipGetLastError());
   if (!o.host) return ok();
   AICDF_HIP(hipEventRecord(ws->ev1, s));
-  double res[kSumsOut];
-  AICDF_HIP(hipMemcpyAsync(res, ws->result, sizeof res, hipMemcpyDeviceToHost, s));
   AICDF_HIP(hipStreamSynchronize(s));
+  double res[kSumsOut];
+  for (int j = 0; j < kSumsOut; ++j) res[j] = ws->host_result[j];
   float ms = 0.0f;
   AICDF_HIP(hipEventElapsedTime(&ms, ws->ev0, ws->ev1));
   aicdf_level_sums* out = o.host;
