@@ -20,7 +20,7 @@
 //   APX_EM         the truncated Euler-Maruyama step of Section 5.2 (the
 //                  Gaussian scheme the approximations are compared with):
 //                  v' = v + kappa (theta - v) delta + xi sqrt(|v| delta) Z,
-//                  Z = Phi^-1(u24) in FP32, the state in FP32 (may go
+//                  Z = Phi^-1(u24) in FP64, the state in FP32 (may go
 //                  negative; |v| under the root).
 // A fourth kind, TWOWAY, runs the exact and the approximate fine paths on the
 // same draws (as CORRECTION) and returns Y = P^_f - P~_f, P_f = P^_f,
@@ -265,7 +265,7 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
         if (FUNC == 1) fs.node(n + 1, N, double(vs));
       }
       if (kEm) {
-        const float z = approx_phi_inv_f32(u24);
+        const float z = float(exact_phi_inv(double(u24)));
         vs = fmaf(a.xi_sqdt * sqrtf(fabsf(vs)), z, fmaf(a.kdt, a.theta - vs, vs));
         if (FUNC == 1) fs.node(n + 1, N, double(vs));
       }

@@ -121,10 +121,10 @@ __host__ __device__ __forceinline__ double exact_phi_inv(double u) {
   return q < 0.0 ? -z : z;
 }
 
-// Phi^-1 in FP32 for approximations whose own error is far larger (the
-// Sankaran comparator, the truncated Euler-Maruyama step): the rational
-// functions of AS 241 evaluated in FP32 arithmetic (relative error a few FP32
-// ulps).  u = 0 and u = 1 give -inf and +inf.
+// Phi^-1 in FP32 for an approximation whose own error is far larger (the
+// Sankaran comparator): the rational functions of AS 241 evaluated in FP32
+// arithmetic (relative error a few FP32 ulps).  u = 0 and u = 1 give -inf and
+// +inf.
 __device__ __forceinline__ float phi_inv_poly7f(const double (&c)[8], float x) {
   float s = float(c[7]);
 #pragma unroll
