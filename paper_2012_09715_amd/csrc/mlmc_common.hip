@@ -66,17 +66,26 @@ aicdf_status get_workspace(hipStream_t s, Workspace** out) {
   }
   auto* ws = new (std::nothrow) Workspace();
   if (!ws) return fail(AICDF_ENOMEM, "host allocation failed");
+  auto release = [ws]() {
+    if (ws->partials) (void)hipFree(ws->partials);
+    if (ws->host_result) (void)hipHostFree(ws->host_result);
+    if (ws->counter) (void)hipFree(ws->counter);
+    if (ws->ev0) (void)hipEventDestroy(ws->ev0);
+    if (ws->ev1) (void)hipEventDestroy(ws->ev1);
+    delete ws;
+  };
   if (hipMalloc(&ws->partials, sizeof(double) * kMaxLevelBlocks * kSums) != hipSuccess ||
-      hipMalloc(&ws->result, sizeof(double) * kSumsOut) != hipSuccess ||
       hipHostMalloc(&ws->host_result, sizeof(double) * kSumsOut, hipHostMallocDefault) != hipSuccess ||
       hipMalloc(&ws->counter, sizeof(unsigned long long)) != hipSuccess) {
-    delete ws;
-    return fail(AICDF_ENOMEM, "hipMalloc of the level workspace failed");
+    release();
+    return fail(AICDF_ENOMEM, "allocation of the level workspace failed");
   }
   // the counter starts at zero; every final pass clears it again
-  AICDF_HIP(hipMemset(ws->counter, 0, sizeof(unsigned long long)));
-  AICDF_HIP(hipEventCreate(&ws->ev0));
-  AICDF_HIP(hipEventCreate(&ws->ev1));
+  if (hipMemset(ws->counter, 0, sizeof(unsigned long long)) != hipSuccess ||
+      hipEventCreate(&ws->ev0) != hipSuccess || hipEventCreate(&ws->ev1) != hipSuccess) {
+    release();
+    return fail(AICDF_EHIP, "set-up of the level workspace failed");
+  }
   g_ws[key] = ws;
   *out = ws;
   return AICDF_OK;

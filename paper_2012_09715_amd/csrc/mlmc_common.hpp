@@ -70,7 +70,6 @@ __device__ __forceinline__ void block_reduce_store(const LevelAcc& acc, double* 
 // zeroed at creation, read and cleared by the final pass of each call.
 struct Workspace {
   double* partials = nullptr;  // kMaxLevelBlocks * kSums doubles
-  double* result = nullptr;    // kSumsOut doubles (device; unused by the host path)
   double* host_result = nullptr;  // kSumsOut doubles of pinned host memory, written by the final pass
   unsigned long long* counter = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
