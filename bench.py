@@ -18,7 +18,7 @@ steps.  The JSON line also carries
   mlmc          nested-MLMC speed-ups over the exact inverse at fixed RMSE:
                 GBM (Euler-Maruyama, Milstein) with the linear-16 table and
                 CIR with the trained BF16 surrogate (skip with --no-mlmc)
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only-main] [--no-mlmc]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only-main] [--no-mlmc] [--profile-levels]
 """
 import argparse
 import json
@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--only-main", action="store_true",
                     help="time the main transform and the copy probe only (for profiler runs)")
     ap.add_argument("--no-mlmc", action="store_true", help="skip the nested MLMC measurements")
+    ap.add_argument("--profile-levels", action="store_true",
+                    help="only one GPU-filling call of each fused level kernel and of the surrogate (for counters)")
     ap.add_argument("--detail", default=None, help="write the full per-level MLMC results to this JSON file")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
@@ -158,6 +160,53 @@ def chi2_sweep(A, torch, u, stream):
     return out
 
 
+def profile_levels(A, torch):
+    """--profile-levels: one GPU-filling call of each fused level kernel and
+    of the surrogate's training and inference, after one untimed warm-up of
+    each, for collecting hardware counters per kernel (run under rocprofv3
+    --pmc).  Calls: GBM Euler-Maruyama, discounted call, level 8, 2^20 paths:
+    exact, approximate (16-row linear dyadic table) and correction kinds; CIR
+    time average, level 6: approximate kind with the linear chi-squared table
+    (2^20 paths), the surrogate (2^20 paths), and the exact kind (2^17 paths);
+    surrogate: one training epoch over 2^20 exact targets (batch 4096) and one
+    forward pass over 2^22 inputs.  Prints one line per call with its kernel
+    time from the library's events."""
+    from paper_2012_09715_amd import mlmc_driver as D
+    lin = A.Table.dyadic(16, 1)
+    chi = A.Chi2Table.create(D.NU_CIR, 1)
+    sur = A.Surrogate.create(D.NU_CIR, *D.SURROGATE_RANGE, seed=1)
+    u, ll, t = sur.make_data(1 << 20, 2)
+    calls = [
+        ("gbm exact l8", lambda: A.mlmc_level_gbm(D.GBM_CALL, 8, 1 << 20, A.KIND_EXACT, None, 3)),
+        ("gbm approx l8", lambda: A.mlmc_level_gbm(D.GBM_CALL, 8, 1 << 20, A.KIND_APPROX, lin, 3)),
+        ("gbm correction l8", lambda: A.mlmc_level_gbm(D.GBM_CALL, 8, 1 << 20, A.KIND_CORRECTION, lin, 3)),
+        ("cir table approx l6", lambda: A.mlmc_level_cir_table(D.CIR_PARAMS, 6, 1 << 20, A.KIND_APPROX, chi, 4)),
+        ("cir surrogate approx l6", lambda: A.mlmc_level_cir(D.CIR_PARAMS, 6, 1 << 20, A.KIND_APPROX, sur, 4)),
+        ("cir exact l6", lambda: A.mlmc_level_cir(D.CIR_PARAMS, 6, 1 << 17, A.KIND_EXACT, None, 4)),
+    ]
+    out = {}
+    for name, fn in calls:
+        fn()
+        out[name] = fn()["kernel_ms"]
+        log(f"{name}: {out[name]:.3f} ms")
+    ue, lle, _ = sur.make_data(1 << 22, 5)
+    for rep in range(2):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        sur.train(u, ll, t, epochs=1, batch=4096, lr=1e-3, seed=rep)
+        ev1.record()
+        torch.cuda.synchronize()
+        out["surrogate training epoch (2^20 samples)"] = ev0.elapsed_time(ev1)
+        ev0.record()
+        sur.forward(ue, lle)
+        ev1.record()
+        torch.cuda.synchronize()
+        out["surrogate forward (2^22 inputs)"] = ev0.elapsed_time(ev1)
+    for k in ("surrogate training epoch (2^20 samples)", "surrogate forward (2^22 inputs)"):
+        log(f"{k}: {out[k]:.3f} ms")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -172,6 +221,9 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
     log(f"device: {torch.cuda.get_device_name(dev)}")
+    if args.profile_levels:
+        print(json.dumps({"profile_levels_ms": profile_levels(A, torch)}), flush=True)
+        return 0
 
     # ---------------------------------------------------------- main workload
     u = torch.empty(N_MAIN, dtype=torch.float32, device=dev)

@@ -413,7 +413,9 @@ aicdf_status mlmc_allocate(uint32_t n_levels, double eps, const double* v_hat, c
  * for 1 - u < 2^-10 (any u > 1/2 when lambda > 4096), in x on log(1 - C)
  * with 1 - C from the upward sweep,
  * inside a maintained bracket.
- * u, lambda, x: device arrays of n doubles; nu > 0; lambda >= 0.
+ * u, lambda, x: device arrays of n doubles; nu > 0; 0 <= lambda <= 1e8
+ * (per element: a lambda outside that range, or NaN, gives x = NaN; the
+ * series then needs more terms than the sweeps index).
  * u = 0 gives 0, u = 1 gives +inf.  Batches of n <= 8192 run one inverse per
  * wavefront (the sweeps split over the 64 lanes, for latency); larger ones
  * one per thread.  The two agree to 1e-11 relative (they round their sums

@@ -31,12 +31,29 @@ def _stream(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
-def _dev(t, name):
+def _dev(t, name, dtype=None, numel=None, like=None):
+    """Device pointer of `t` after checking it: a contiguous CUDA tensor,
+    of `dtype` if given, with at least `numel` elements if given, and on the
+    device of `like` if given.  Raised before anything is launched, so that a
+    wrong buffer never reaches a kernel."""
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise AicdfError(-1, f"{name} must be a CUDA (HIP) tensor")
     if not t.is_contiguous():
         raise AicdfError(-1, f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise AicdfError(-2, f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise AicdfError(-1, f"{name} holds {t.numel()} elements, needs {numel}")
+    if like is not None and t.device != like.device:
+        raise AicdfError(-1, f"{name} is on {t.device}, expected {like.device}")
     return C.c_void_p(t.data_ptr())
+
+
+def _path_out(path_out, n_paths):
+    """Optional per-path output: float64, 3 doubles (Y, P_f, P_c) per path."""
+    if path_out is None:
+        return None
+    return _dev(path_out, "path_out", torch.float64, 3 * int(n_paths))
 
 
 class Table:
@@ -120,6 +137,8 @@ def geometric_host_coeffs(r, n_entries, degree, coef_dtype=torch.float32):
 def _out(u, z, out_dtype):
     if z is None:
         z = torch.empty(u.shape, dtype=out_dtype, device=u.device)
+    else:
+        _dev(z, "z", numel=u.numel(), like=u)
     return z
 
 
@@ -156,8 +175,12 @@ def uniform_fill(u, seed, stream_id=0, offset=0, stream=None):
 
 
 def bw_probe(mode, src, dst, n_bytes=None, stream=None):
-    nb = n_bytes if n_bytes is not None else (dst.numel() * dst.element_size() if mode != 1 else
-                                              src.numel() * src.element_size())
+    nbytes = lambda t: t.numel() * t.element_size()
+    nb = n_bytes if n_bytes is not None else (nbytes(dst) if mode != 1 else nbytes(src))
+    if mode in (0, 1) and (src is None or nbytes(src) < nb):
+        raise AicdfError(-1, f"src must hold {nb} bytes")
+    if (mode != 1 and nbytes(dst) < nb) or nbytes(dst) < 16:
+        raise AicdfError(-1, f"dst must hold {nb if mode != 1 else 16} bytes")
     s_ptr = _dev(src, "src") if src is not None else None
     check(lib.aicdf_bw_probe(mode, nb, s_ptr, _dev(dst, "dst"), _stream(stream)))
 
@@ -171,7 +194,7 @@ def mlmc_level_gbm(params, level, n_paths, kind, table=None, seed=0, path_offset
     p = GbmParams(params["S0"], params["r"], params["sigma"], params["T"], params.get("K", 1.0),
                   int(params.get("scheme", 0)), int(params.get("payoff", 0)))
     out = LevelSums()
-    po = _dev(path_out, "path_out") if path_out is not None else None
+    po = _path_out(path_out, n_paths)
     check(lib.mlmc_level_gbm(C.byref(p), level, n_paths, kind, table.handle if table is not None else None,
                              seed, path_offset, C.byref(out), po, _stream(stream)))
     return _sums_dict(out)
@@ -181,7 +204,7 @@ def mlmc_level_cir(params, level, n_paths, kind, surrogate=None, seed=0, path_of
                    stream=None):
     p = _cir_params(params)
     out = LevelSums()
-    po = _dev(path_out, "path_out") if path_out is not None else None
+    po = _path_out(path_out, n_paths)
     check(lib.mlmc_level_cir(C.byref(p), level, n_paths, kind, surrogate.handle if surrogate is not None else None,
                              seed, path_offset, C.byref(out), po, _stream(stream)))
     return _sums_dict(out)
@@ -197,7 +220,7 @@ def mlmc_level_cir_table(params, level, n_paths, kind, table=None, seed=0, path_
     """mlmc_level_cir with the piecewise-polynomial chi-squared table (Chi2Table) as the approximation."""
     p = _cir_params(params)
     out = LevelSums()
-    po = _dev(path_out, "path_out") if path_out is not None else None
+    po = _path_out(path_out, n_paths)
     check(lib.mlmc_level_cir_table(C.byref(p), level, n_paths, kind, table.handle if table is not None else None,
                                    seed, path_offset, C.byref(out), po, _stream(stream)))
     return _sums_dict(out)
@@ -207,7 +230,7 @@ def mlmc_level_cir_em(params, level, n_paths, kind, seed=0, path_offset=0, path_
     """mlmc_level_cir with the truncated Euler-Maruyama scheme as the approximation."""
     p = _cir_params(params)
     out = LevelSums()
-    po = _dev(path_out, "path_out") if path_out is not None else None
+    po = _path_out(path_out, n_paths)
     check(lib.mlmc_level_cir_em(C.byref(p), level, n_paths, kind, seed, path_offset, C.byref(out), po,
                                 _stream(stream)))
     return _sums_dict(out)
@@ -217,7 +240,7 @@ def mlmc_level_cir_sankaran(params, level, n_paths, kind, seed=0, path_offset=0,
     """mlmc_level_cir with the Sankaran approximation as the approximate transition."""
     p = _cir_params(params)
     out = LevelSums()
-    po = _dev(path_out, "path_out") if path_out is not None else None
+    po = _path_out(path_out, n_paths)
     check(lib.mlmc_level_cir_sankaran(C.byref(p), level, n_paths, kind, seed, path_offset, C.byref(out), po,
                                       _stream(stream)))
     return _sums_dict(out)
@@ -243,7 +266,7 @@ def mlmc_level_gbm_async(params, level, n_paths, kind, table, seed, path_offset,
     until the stream has passed the call."""
     p = GbmParams(params["S0"], params["r"], params["sigma"], params["T"], params.get("K", 1.0),
                   int(params.get("scheme", 0)), int(params.get("payoff", 0)))
-    po = _dev(path_out, "path_out") if path_out is not None else None
+    po = _path_out(path_out, n_paths)
     check(lib.mlmc_level_gbm_async(C.byref(p), level, n_paths, kind, table.handle if table is not None else None,
                                    seed, path_offset, _sums_dev(sums), po, _stream(stream)))
 
@@ -252,7 +275,7 @@ def mlmc_level_cir_async(params, level, n_paths, kind, surrogate, seed, path_off
                          stream=None):
     """Stream-ordered mlmc_level_cir (see mlmc_level_gbm_async)."""
     p = _cir_params(params)
-    po = _dev(path_out, "path_out") if path_out is not None else None
+    po = _path_out(path_out, n_paths)
     check(lib.mlmc_level_cir_async(C.byref(p), level, n_paths, kind,
                                    surrogate.handle if surrogate is not None else None, seed, path_offset,
                                    _sums_dev(sums), po, _stream(stream)))
@@ -262,7 +285,7 @@ def mlmc_level_cir_table_async(params, level, n_paths, kind, table, seed, path_o
                                stream=None):
     """Stream-ordered mlmc_level_cir_table (see mlmc_level_gbm_async)."""
     p = _cir_params(params)
-    po = _dev(path_out, "path_out") if path_out is not None else None
+    po = _path_out(path_out, n_paths)
     check(lib.mlmc_level_cir_table_async(C.byref(p), level, n_paths, kind, table.handle if table is not None else None,
                                          seed, path_offset, _sums_dev(sums), po, _stream(stream)))
 
@@ -270,7 +293,7 @@ def mlmc_level_cir_table_async(params, level, n_paths, kind, table, seed, path_o
 def mlmc_level_cir_em_async(params, level, n_paths, kind, seed, path_offset, sums, path_out=None, stream=None):
     """Stream-ordered mlmc_level_cir_em (see mlmc_level_gbm_async)."""
     p = _cir_params(params)
-    po = _dev(path_out, "path_out") if path_out is not None else None
+    po = _path_out(path_out, n_paths)
     check(lib.mlmc_level_cir_em_async(C.byref(p), level, n_paths, kind, seed, path_offset, _sums_dev(sums), po,
                                       _stream(stream)))
 
@@ -279,7 +302,7 @@ def mlmc_level_cir_sankaran_async(params, level, n_paths, kind, seed, path_offse
                                   stream=None):
     """Stream-ordered mlmc_level_cir_sankaran (see mlmc_level_gbm_async)."""
     p = _cir_params(params)
-    po = _dev(path_out, "path_out") if path_out is not None else None
+    po = _path_out(path_out, n_paths)
     check(lib.mlmc_level_cir_sankaran_async(C.byref(p), level, n_paths, kind, seed, path_offset, _sums_dev(sums),
                                             po, _stream(stream)))
 
@@ -294,7 +317,8 @@ def approx_ncx2_sankaran(nu, u, lam, x=None, stream=None):
         x = torch.empty_like(u)
     elif x.dtype != torch.float32 or x.numel() != u.numel():
         raise AicdfError(-2, "x must be float32 with as many elements as u")
-    check(lib.approx_ncx2_sankaran(nu, u.numel(), _dev(u, "u"), _dev(lam, "lambda"), _dev(x, "x"), _stream(stream)))
+    check(lib.approx_ncx2_sankaran(nu, u.numel(), _dev(u, "u"), _dev(lam, "lambda", like=u), _dev(x, "x", like=u),
+                                   _stream(stream)))
     return x
 
 
@@ -309,9 +333,16 @@ def mlmc_allocate(eps, v_hat, c_hat, v2, c2, v4, c4):
 
 
 def ncx2_icdf_exact(nu, u, lam, x=None, stream=None):
+    """x = C_nu^-1(u; lambda) in FP64 (u, lambda, x: float64 device tensors of one size)."""
+    n = u.numel()
+    pu = _dev(u, "u", torch.float64)
+    if lam.numel() != n:
+        raise AicdfError(-1, "u and lambda must have the same number of elements")
+    pl = _dev(lam, "lambda", torch.float64, like=u)
     if x is None:
         x = torch.empty_like(u)
-    check(lib.ncx2_icdf_exact(nu, u.numel(), _dev(u, "u"), _dev(lam, "lambda"), _dev(x, "x"), _stream(stream)))
+    px = _dev(x, "x", torch.float64, n, like=u)
+    check(lib.ncx2_icdf_exact(nu, n, pu, pl, px, _stream(stream)))
     return x
 
 
@@ -368,8 +399,8 @@ def approx_ncx2_icdf(table, u, lam, x=None, stream=None):
         x = torch.empty_like(u)
     elif x.dtype != torch.float32 or x.numel() != u.numel():
         raise AicdfError(-2, "x must be float32 with as many elements as u")
-    check(lib.approx_ncx2_icdf(table.handle, u.numel(), _dev(u, "u"), _dev(lam, "lambda"), _dev(x, "x"),
-                               _stream(stream)))
+    check(lib.approx_ncx2_icdf(table.handle, u.numel(), _dev(u, "u"), _dev(lam, "lambda", like=u),
+                               _dev(x, "x", like=u), _stream(stream)))
     return x
 
 
@@ -413,18 +444,29 @@ class Surrogate:
         buf = (C.c_float * len(flat))(*flat)
         check(lib.aicdf_surrogate_set_params(self._h, buf, len(flat)))
 
+    @staticmethod
+    def _f32(u, **others):
+        """Pointers of float32 device tensors of u's size (u first)."""
+        n = u.numel()
+        ptrs = [_dev(u, "u", torch.float32)]
+        for name, t in others.items():
+            if t.numel() != n:
+                raise AicdfError(-1, f"{name} must have as many elements as u")
+            ptrs.append(_dev(t, name, torch.float32, like=u))
+        return ptrs
+
     def forward(self, u, loglam, p=None, stream=None):
         if p is None:
             p = torch.empty_like(u)
-        check(lib.aicdf_surrogate_forward(self._h, u.numel(), _dev(u, "u"), _dev(loglam, "loglam"), _dev(p, "p"),
-                                          _stream(stream)))
+        pu, pg, pp = self._f32(u, loglam=loglam, p=p)
+        check(lib.aicdf_surrogate_forward(self._h, u.numel(), pu, pg, pp, _stream(stream)))
         return p
 
     def loss_grad(self, u, loglam, target, stream=None):
         loss = C.c_double()
         g = (C.c_float * SURROGATE_NPARAMS)()
-        check(lib.aicdf_surrogate_loss_grad(self._h, u.numel(), _dev(u, "u"), _dev(loglam, "loglam"),
-                                            _dev(target, "target"), C.byref(loss), g, _stream(stream)))
+        pu, pg, pt = self._f32(u, loglam=loglam, target=target)
+        check(lib.aicdf_surrogate_loss_grad(self._h, u.numel(), pu, pg, pt, C.byref(loss), g, _stream(stream)))
         return loss.value, torch.tensor(list(g), dtype=torch.float32)
 
     def make_data(self, n, seed, device="cuda", stream=None):
@@ -437,8 +479,8 @@ class Surrogate:
 
     def train(self, u, loglam, target, epochs, batch=4096, lr=1e-3, seed=0, stream=None):
         loss = C.c_double()
-        check(lib.aicdf_surrogate_train(self._h, u.numel(), _dev(u, "u"), _dev(loglam, "loglam"),
-                                        _dev(target, "target"), epochs, batch, lr, seed, C.byref(loss),
+        pu, pg, pt = self._f32(u, loglam=loglam, target=target)
+        check(lib.aicdf_surrogate_train(self._h, u.numel(), pu, pg, pt, epochs, batch, lr, seed, C.byref(loss),
                                         _stream(stream)))
         return loss.value
 

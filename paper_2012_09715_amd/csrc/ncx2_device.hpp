@@ -440,12 +440,20 @@ __host__ __device__ inline double ncx2_icdf_tail(double t, bool upper, double nu
 constexpr double kNcx2UpperTail = 0x1p-10;
 constexpr double kNcx2UpperLam = 4096.0;
 
-// C_nu^-1(u; lambda) for u in [0, 1]: 0 at u = 0, +inf at u = 1, NaN outside.
+// Largest lambda the exact inverse accepts.  The sweeps index their terms
+// with int and visit about 18 sqrt(lambda/2) + 32 of them (the upward one at
+// most 400000): both stay far within range up to here (127k terms per sweep
+// at the bound).  Larger lambda, negative lambda and NaN give NaN.
+constexpr double kNcx2MaxLam = 1e8;
+
+// C_nu^-1(u; lambda) for u in [0, 1]: 0 at u = 0, +inf at u = 1, NaN outside
+// (and NaN for lambda outside [0, kNcx2MaxLam]).
 // x0 > 0: an approximation of the root to start from.
 __host__ __device__ inline double ncx2_icdf(double u, double nu, double lam, int* iters = nullptr,
                                             double x0 = 0.0) {
   if (!(u > 0.0)) return u == 0.0 ? 0.0 : __builtin_nan("");
   if (!(u < 1.0)) return u == 1.0 ? __builtin_inf() : __builtin_nan("");
+  if (!(lam >= 0.0 && lam <= kNcx2MaxLam)) return __builtin_nan("");
   const bool upper = u > 0.5 && (1.0 - u < kNcx2UpperTail || lam > kNcx2UpperLam);
   return ncx2_icdf_tail(upper ? 1.0 - u : u, upper, nu, lam, iters, x0);
 }

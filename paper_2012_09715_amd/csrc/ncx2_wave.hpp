@@ -431,6 +431,7 @@ struct Ncx2Wave {
 __device__ inline double ncx2_icdf_wave(double u, double nu, double lam, double x0 = 0.0) {
   if (!(u > 0.0)) return u == 0.0 ? 0.0 : __builtin_nan("");
   if (!(u < 1.0)) return u == 1.0 ? __builtin_inf() : __builtin_nan("");
+  if (!(lam >= 0.0 && lam <= kNcx2MaxLam)) return __builtin_nan("");
   const bool upper = u > 0.5 && (1.0 - u < kNcx2UpperTail || lam > kNcx2UpperLam);
   return ncx2_solve(upper ? 1.0 - u : u, upper, nu, lam, Ncx2Wave{nu, lam}, nullptr, x0);
 }
