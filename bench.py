@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--only-main", action="store_true",
                     help="time the main transform and the copy probe only (for profiler runs)")
     ap.add_argument("--no-mlmc", action="store_true", help="skip the nested MLMC measurements")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
+                    help="write the headline kernel's HBM traffic from two rocprofv3 --pmc counter files (no GPU)")
     ap.add_argument("--profile-levels", action="store_true",
                     help="only one GPU-filling call of each fused level kernel and of the surrogate (for counters)")
     ap.add_argument("--detail", default=None, help="write the full per-level MLMC results to this JSON file")
@@ -207,8 +209,77 @@ def profile_levels(A, torch):
     return out
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_transform_linear16_f32.json")
+# the sources the headline kernel is compiled from (and its build flags): a
+# stored traffic figure counts only while they are unchanged
+KERNEL_SOURCES = ("paper_2012_09715_amd/csrc/transform.hip", "paper_2012_09715_amd/csrc/device_common.hpp",
+                  "paper_2012_09715_amd/csrc/internal.hpp", "include/aicdf.h", "paper_2012_09715_amd/build.py")
+
+
+def kernel_fingerprint():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(rel.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_counters(fetch_csv, write_csv):
+    """--traffic-from: HBM bytes per launch of the headline transform from two
+    rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of
+    `bench.py --only-main`, each scaled by what the same counter reads for the
+    copy kernel bw_kernel<0>, which moves exactly 4 GiB in and 4 GiB out.
+    Writes the result with the kernel sources' fingerprint."""
+    import csv
+
+    def per_kernel(path, counter):
+        vals = {"transform": [], "copy": []}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                name = r["Kernel_Name"]
+                key = "transform" if "transform_kernel<" in name and "DyadicF32<1>" in name else \
+                      "copy" if "bw_kernel<0>" in name else None
+                if key:
+                    vals[key].append(float(r["Counter_Value"]))
+        return {k: float(np.median(v)) for k, v in vals.items()}
+
+    fetch, write = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    copy_bytes = float(N_MAIN * 4)
+    f_scale = copy_bytes / (fetch["copy"] * 1024.0)
+    w_scale = copy_bytes / (write["copy"] * 1024.0)
+    fb, wb = fetch["transform"] * 1024.0 * f_scale, write["transform"] * 1024.0 * w_scale
+    out = {"kernel": "transform_kernel<DyadicF32<1>, OUT_F32>",
+           "workload": "2^30 FP32 u24 uniforms -> dyadic 16x2 FP32 table -> FP32",
+           "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write,
+           "fetch_scale_factor": f_scale, "write_scale_factor": w_scale,
+           "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "traffic_bytes_per_launch": fb + wb,
+           "algorithmic_bytes_per_launch": N_MAIN * 8, "kernel_sources_fingerprint": kernel_fingerprint()}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+    return 0
+
+
+def stored_traffic():
+    """Traffic bytes per launch from the stored counter summary, or None when
+    the kernel's sources have changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("kernel_sources_fingerprint") != kernel_fingerprint():
+        log("stored traffic figure is stale (kernel sources changed): traffic = null")
+        return None
+    return t.get("traffic_bytes_per_launch")
+
+
 def main():
     args = parse()
+    if args.traffic_from:
+        return traffic_from_counters(*args.traffic_from)
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
         log("bench.py: only --gpus 1 is supported (the method's work shards by path/sample range; "
@@ -255,11 +326,7 @@ def main():
     copy_gbs = bytes_per_launch / (cms * 1e-3) / 1e9
     log(f"copy probe: {cms:.4f} ms, {copy_gbs:.1f} GB/s")
 
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", "traffic_transform_linear16_f32.json")
-    if os.path.exists(tfile):
-        with open(tfile) as f:
-            traffic = json.load(f).get("traffic_bytes_per_launch")
+    traffic = stored_traffic()
 
     result = {
         "metric": METRIC,

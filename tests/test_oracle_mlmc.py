@@ -107,5 +107,43 @@ def test_gbm_variance_structure():
     assert -15.5 < drop < -12.5
 
 
+def test_gbm_two_step_hand_case():
+    # Level 1 (two fine steps of h = 1/2, one coarse step of 1) with normals
+    # Z = (1, -1/2): dW = (sqrt(1/2), -sqrt(1/2)/2), coarse dW = sqrt(1/2)/2.
+    # Milstein, g = 1 + r h + sigma dW + sigma^2 (dW^2 - h)/2, worked by hand:
+    #   fine   (1.025 + 0.2 sqrt(1/2) + 0) (1.025 - 0.1 sqrt(1/2) - 0.0075)
+    #   coarse 1.05 + 0.1 sqrt(1/2) - 0.0175
+    # Euler-Maruyama drops the sigma^2 terms:
+    #   fine   (1.025 + 0.2 sqrt(1/2)) (1.025 - 0.1 sqrt(1/2)),  coarse 1.05 + 0.1 sqrt(1/2)
+    Z = np.array([[1.0, -0.5]])
+    Xf, Xc = gbm._paths(dict(GBM, scheme=1), 1, Z)
+    assert Xf[0] == pytest.approx(1.1043552848998413, rel=1e-15)
+    assert Xc[0] == pytest.approx(1.1032106781186548, rel=1e-15)
+    Xf, Xc = gbm._paths(dict(GBM, scheme=0), 1, Z)
+    assert Xf[0] == pytest.approx(1.1131034450716211, rel=1e-15)
+    assert Xc[0] == pytest.approx(1.1207106781186548, rel=1e-15)
+    # level 0: one step of h = 1 and no coarse path
+    Xf, Xc = gbm._paths(dict(GBM, scheme=1), 0, np.array([[1.0]]))
+    assert Xf[0] == pytest.approx(1.0 + 0.05 + 0.2, rel=1e-15) and Xc is None
+
+
+@pytest.mark.slow
+def test_gbm_milstein_variance_slope():
+    # Milstein has strong order 1 for GBM: v^_l = Var(P_l - P_(l-1)) falls as
+    # 2^-2l with P = X (Section 4.1, Figure 3), against 2^-l for
+    # Euler-Maruyama on the same draws
+    n = 4000
+    vm, ve = [], []
+    for level in (2, 4, 6):
+        Y, _, _ = gbm.level_replay(dict(GBM, scheme=1), level, 0, 41, np.arange(n))
+        vm.append(Y.var())
+        Y, _, _ = gbm.level_replay(GBM, level, 0, 41, np.arange(n))
+        ve.append(Y.var())
+    sm = np.polyfit([2, 4, 6], np.log2(vm), 1)[0]
+    se = np.polyfit([2, 4, 6], np.log2(ve), 1)[0]
+    assert -2.3 < sm < -1.7
+    assert -1.3 < se < -0.7
+
+
 def test_black_scholes_value():
     assert gbm.black_scholes_call(GBM) == pytest.approx(0.10450583572185568, rel=1e-12)

@@ -113,6 +113,49 @@ def test_cir_coarse_is_even_subsample():
     assert t == pytest.approx(0.04)
 
 
+def test_time_average_is_trapezoidal():
+    # Section 5.2's path-dependent functional on the level's grid, checked on
+    # deterministic paths against closed forms of the trapezoidal rule (a
+    # plain mean over the 2^l + 1 nodes, or a missing half weight at either
+    # end, gives different values on every path below):
+    #   v(t) = t^2 on [0, 1]: (1/N) sum'' (n/N)^2 = 1/3 + 1/(6 N^2)
+    #   v(t) = e^(-a t):      (1/N) sum'' q^n = (1 - q^N)(1 + q) / (2 N (1 - q)),  q = e^(-a/N)
+    # (sum'' halves the end terms); the coarse value is the same rule on the
+    # even nodes (N/2 intervals).
+    p = dict(CIR, functional=1)
+    for level in (1, 2, 3, 5):
+        N = 1 << level
+        t = np.linspace(0.0, 1.0, N + 1)
+        v = np.stack([t * t, np.exp(-0.7 * t), 0.09 + 0.0 * t])
+        Pf, Pc = cir.functional_pair(p, level, v)
+
+        def expo(M, a=0.7):
+            q = np.exp(-a / M)
+            return (1.0 - q ** M) * (1.0 + q) / (2.0 * M * (1.0 - q))
+
+        M = N // 2
+        assert Pf[0] == pytest.approx(1.0 / 3.0 + 1.0 / (6.0 * N * N), rel=1e-13)
+        assert Pf[1] == pytest.approx(expo(N), rel=1e-13)
+        assert Pf[2] == pytest.approx(0.09, rel=1e-14)
+        assert Pc[0] == pytest.approx(1.0 / 3.0 + 1.0 / (6.0 * M * M), rel=1e-13)
+        assert Pc[1] == pytest.approx(expo(M), rel=1e-13)
+    # level 0: one step, P_f = (v_0 + v_1)/2 and no coarse path
+    Pf, Pc = cir.functional_pair(p, 0, np.array([[0.09, 0.05]]))
+    assert Pf[0] == pytest.approx(0.07) and Pc[0] == 0.0
+
+
+def test_time_average_closed_form_off_equilibrium():
+    # v0 = 0.09 != theta: the mean of the time average is the trapezoidal
+    # rule applied to E v_t = theta + (v0 - theta) e^(-kappa t); at level 0
+    # (one transition) it is (v0 + E v_T) / 2, and it differs from the plain
+    # mean over the nodes at every level >= 1
+    p = dict(CIR, functional=1, v0=0.09)
+    assert cir.mean_time_average(p, 0) == pytest.approx(0.5 * (0.09 + cir.mean_v(p, 1.0)), rel=1e-15)
+    for level in (1, 2, 4):
+        t = np.linspace(0.0, 1.0, (1 << level) + 1)
+        assert abs(cir.mean_time_average(p, level) - cir.mean_v(p, t).mean()) > 1e-5
+
+
 # ---------------------------------------------------------------- MLP
 def test_mlp_finite_differences():
     p = mlp.init_params(5)

@@ -114,3 +114,41 @@ def test_path_streams_share_hi_word():
     u53, u24 = rng.path_u53_u24(5, np.arange(10), rng.stream_tag(3, 2), 8)
     k = np.floor(u53 * 2.0 ** 23)
     assert np.array_equal(((k + 0.5) * 2.0 ** -23).astype(np.float32), u24)
+
+
+# ---------------------------------------------------- single-precision form
+@pytest.mark.parametrize("T,d", [(8, 1), (16, 1), (32, 1), (8, 3), (16, 3), (32, 3)])
+def test_dyadic_transform_f32_against_fp64(T, d):
+    # Algorithm 1 in FP32 (dyadic_transform_f32) against the FP64 evaluation
+    # of the same FP32-rounded table, on 2^20 inputs that populate every row
+    # (a plain + log-uniform-tail mix) plus every Table 1 boundary and its
+    # neighbours.  Row indices agree exactly.  Degree 1 is one fused
+    # multiply-add: the result is the FP64 value rounded once, so the error is
+    # at most half an FP32 ulp.  Degree 3 is Horner's rule with three FMAs:
+    # each rounds once, so |z32 - z| <= gamma_3 sum_j |c_j| s^j with
+    # gamma_3 = 3u/(1 - 3u), u = 2^-24 (the standard bound for Horner's rule
+    # with fused multiply-adds).
+    from tests.inputs import edge_uniforms, random_uniforms
+    tab = np.asarray(tables.dyadic_table(T, d), np.float64).astype(np.float32).astype(np.float64)
+    u = np.concatenate([random_uniforms(1 << 20, 100 + T + d, np.float32), edge_uniforms(np.float32)])
+    u = u[~np.isnan(u)]
+    z32, e32 = transform.dyadic_transform_f32(tab, u)
+    z64, e64 = transform.dyadic_transform(tab, u.astype(np.float64))
+    assert np.array_equal(e32, e64)
+    assert set(np.unique(e64)) == set(range(T))  # every row visited
+    err = np.abs(z32.astype(np.float64) - z64)
+    if d == 1:
+        half_ulp = 0.5 * np.spacing(np.abs(z64).astype(np.float32)).astype(np.float64)
+        assert np.all(err <= half_ulp * (1.0 + 2.0 ** -28))
+    else:
+        _, p, ur = transform.dyadic_index(T, u.astype(np.float64))
+        s = np.ldexp(ur, e64 + 1)
+        absval = sum(np.abs(tab[e64, j]) * s ** j for j in range(d + 1))
+        g3 = 3 * 2.0 ** -24 / (1 - 3 * 2.0 ** -24)
+        assert np.all(err <= g3 * absval)
+        assert err.max() > 0.0  # the FP32 path does round
+    # sign handling: z(1 - u) = -z(u) bit for bit where 1 - u is exact in FP32
+    v = (np.float32(1.0) - u.astype(np.float32))
+    ok = (np.float32(1.0) - v) == u.astype(np.float32)
+    zv, _ = transform.dyadic_transform_f32(tab, v[ok])
+    assert np.array_equal(zv, -z32[ok])
