@@ -373,6 +373,26 @@ aicdf_status mlmc_level_gbm_async(const aicdf_gbm_params* params, uint32_t level
                                   int32_t kind, const aicdf_table* approx, uint64_t seed,
                                   uint64_t path_offset, double* sums_dev, double* path_out,
                                   void* stream);
+
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): mlmc_level_gbm_async with
+ * the same arguments, checks, kernels and results (sums and per-path values
+ * bit-identical), except that the level's per-work-group partial sums live in
+ * a fixed array of device memory inside the library (192 KiB per GPU, at most
+ * 4096 work-groups of 6 doubles, which every call's launch respects; a launch
+ * needing more is rejected with ERANGE) instead of a per-stream workspace,
+ * and that the fallback count (always 0 for GBM) is reported as 0.  The call
+ * allocates nothing: no hipMalloc, hipFree, pinned or host allocation; on its
+ * first call on a device it looks up that device's array (hipGetSymbolAddress).
+ * Every call on one GPU shares that GPU's array, whatever the stream: calls
+ * that overlap in time on one GPU (several streams, or host threads) race
+ * and give wrong sums; serialise them, for example on one stream.  The final
+ * pass reads only what the level kernel of the same call wrote.
+ * Errors: EINVAL, ERANGE, EHIP. */
+aicdf_status mlmc_level_gbm_noalloc(const aicdf_gbm_params* params, uint32_t level, uint64_t n_paths,
+                                    int32_t kind, const aicdf_table* approx, uint64_t seed,
+                                    uint64_t path_offset, double* sums_dev, double* path_out,
+                                    void* stream);
 aicdf_status mlmc_level_cir_async(const aicdf_cir_params* params, uint32_t level, uint64_t n_paths,
                                   int32_t kind, const aicdf_surrogate* approx, uint64_t seed,
                                   uint64_t path_offset, double* sums_dev, double* path_out,

@@ -271,6 +271,18 @@ def mlmc_level_gbm_async(params, level, n_paths, kind, table, seed, path_offset,
                                    seed, path_offset, _sums_dev(sums), po, _stream(stream)))
 
 
+def mlmc_level_gbm_noalloc(params, level, n_paths, kind, table, seed, path_offset, sums, path_out=None,
+                           stream=None):
+    """mlmc_level_gbm_async without any allocation: the level's partial sums
+    live in the library's fixed per-GPU scratch array, shared by every call on
+    that GPU (calls that overlap in time on one GPU race)."""
+    p = GbmParams(params["S0"], params["r"], params["sigma"], params["T"], params.get("K", 1.0),
+                  int(params.get("scheme", 0)), int(params.get("payoff", 0)))
+    po = _path_out(path_out, n_paths)
+    check(lib.mlmc_level_gbm_noalloc(C.byref(p), level, n_paths, kind, table.handle if table is not None else None,
+                                     seed, path_offset, _sums_dev(sums), po, _stream(stream)))
+
+
 def mlmc_level_cir_async(params, level, n_paths, kind, surrogate, seed, path_offset, sums, path_out=None,
                          stream=None):
     """Stream-ordered mlmc_level_cir (see mlmc_level_gbm_async)."""

@@ -70,6 +70,7 @@ _PROTOS = {
     "mlmc_level_cir_sankaran": (status, [C.POINTER(CirParams), u32, u64, i32, u64, u64, C.POINTER(LevelSums), vp,
                                          vp]),
     "mlmc_level_gbm_async": (status, [C.POINTER(GbmParams), u32, u64, i32, vp, u64, u64, vp, vp, vp]),
+    "mlmc_level_gbm_noalloc": (status, [C.POINTER(GbmParams), u32, u64, i32, vp, u64, u64, vp, vp, vp]),
     "mlmc_level_cir_async": (status, [C.POINTER(CirParams), u32, u64, i32, vp, u64, u64, vp, vp, vp]),
     "mlmc_level_cir_table_async": (status, [C.POINTER(CirParams), u32, u64, i32, vp, u64, u64, vp, vp, vp]),
     "mlmc_level_cir_em_async": (status, [C.POINTER(CirParams), u32, u64, i32, u64, u64, vp, vp, vp]),

@@ -131,6 +131,14 @@ aicdf_status empty_level(hipStream_t s, const LevelOut& o) {
   return ok();
 }
 
+aicdf_status reduce_partials_to(const double* partials, unsigned nblocks, double n_paths, double* out,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kLevelBlock), 0, s, partials, nblocks, nullptr, n_paths,
+                     out);
+  AICDF_HIP(hipGetLastError());
+  return ok();
+}
+
 }  // namespace aicdf
 
 using namespace aicdf;

@@ -102,4 +102,10 @@ aicdf_status finish_level(Workspace* ws, unsigned nblocks, hipStream_t s, double
 // A call of zero paths: all-zero results (enqueued for a stream-ordered call).
 aicdf_status empty_level(hipStream_t s, const LevelOut& o);
 
+// The final pass over nblocks partials at `partials` (device memory the
+// caller provides), writing the kSumsOut results to `out` (device memory) in
+// stream order; no fallback counter (reported as 0).  Allocates nothing.
+aicdf_status reduce_partials_to(const double* partials, unsigned nblocks, double n_paths, double* out,
+                                hipStream_t s);
+
 }  // namespace aicdf

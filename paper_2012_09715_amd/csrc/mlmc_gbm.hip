@@ -21,10 +21,21 @@
 // steps (draws and normals included) and an ordered tree of shuffles
 // multiplies the 64 lane products; lane 0 applies the result to (S0, 0).
 #include <cmath>
+#include <mutex>
 
 #include "mlmc_common.hpp"
 
 using namespace aicdf;
+
+// Device memory of the no-allocation entry point (mlmc_level_gbm_noalloc):
+// the per-work-group partials of one level call, at most kMaxLevelBlocks
+// work-groups of kSums doubles (192 KiB).  Each GPU the library runs on holds
+// its own copy until the process ends.  Host code never passes `scratch`
+// itself to a kernel or a copy (in host code the name is a stand-in, not a
+// device address): the device address comes from hipGetSymbolAddress, taken
+// once per device with that device current.
+static constexpr size_t kScratchDoubles = size_t(kMaxLevelBlocks) * kSums;
+static __device__ __align__(256) double scratch[kScratchDoubles];
 
 namespace {
 
@@ -357,9 +368,32 @@ void launch_kind(int scheme, int payoff, int tab, const GbmArgs& a, unsigned gri
   if (scheme == 1 && payoff == 1) launch_tab<KIND, 1, 1>(tab, a, grid, lds, s, p, po);
 }
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch` (looked up on the device's first
+// call, with that device current).
+aicdf_status scratch_address(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(AICDF_EINVAL, "device %d beyond the supported %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(AICDF_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return AICDF_OK;
+}
+
+// scratch_partials: when non-NULL the level's partials go there and the sums
+// to out.dev with no workspace (nothing allocated, no lock); else the
+// per-stream workspace is used.
 aicdf_status gbm_level(const aicdf_gbm_params* prm, uint32_t level, uint64_t n_paths, int32_t kind,
                        const aicdf_table* approx, uint64_t seed, uint64_t path_offset, const LevelOut& out,
-                       double* path_out, void* stream) {
+                       double* path_out, void* stream, bool no_alloc = false) {
   if (!prm) return fail(AICDF_EINVAL, "params must be non-NULL");
   aicdf_status st = check_level_out(out);
   if (st != AICDF_OK) return st;
@@ -370,7 +404,8 @@ aicdf_status gbm_level(const aicdf_gbm_params* prm, uint32_t level, uint64_t n_p
   if (!(prm->T > 0.0) || !(prm->sigma >= 0.0) || !std::isfinite(prm->S0) || !std::isfinite(prm->r))
     return fail(AICDF_EINVAL, "need T > 0, sigma >= 0, finite S0 and r");
   if (kind != AICDF_KIND_EXACT && !approx) return fail(AICDF_EINVAL, "the approximate kinds need a table");
-  if (n_paths == 0) return empty_level(static_cast<hipStream_t>(stream), out);
+  if (n_paths == 0) return no_alloc ? reduce_partials_to(nullptr, 0, 0.0, out.dev, static_cast<hipStream_t>(stream))
+                                    : empty_level(static_cast<hipStream_t>(stream), out);
   if (n_paths > (uint64_t(1) << 40)) return fail(AICDF_ERANGE, "n_paths > 2^40");
   if (path_offset + n_paths < path_offset) return fail(AICDF_ERANGE, "path_offset + n_paths overflows");
   int dev = 0;
@@ -417,6 +452,22 @@ aicdf_status gbm_level(const aicdf_gbm_params* prm, uint32_t level, uint64_t n_p
   const unsigned grid = unsigned(need < uint64_t(kMaxLevelBlocks) ? need : kMaxLevelBlocks);
 
   auto s = static_cast<hipStream_t>(stream);
+  if (no_alloc) {
+    double* partials = nullptr;
+    st = scratch_address(dev, &partials);
+    if (st != AICDF_OK) return st;
+    if (size_t(grid) * kSums > kScratchDoubles)
+      return fail(AICDF_ERANGE, "%u work-groups need %zu doubles of scratch, the maximum is %zu", grid,
+                  size_t(grid) * kSums, kScratchDoubles);
+    if (kind == AICDF_KIND_EXACT)
+      launch_kind<AICDF_KIND_EXACT>(prm->scheme, prm->payoff, 0, a, grid, 0, s, partials, path_out);
+    else if (kind == AICDF_KIND_APPROX)
+      launch_kind<AICDF_KIND_APPROX>(prm->scheme, prm->payoff, tab, a, grid, lds, s, partials, path_out);
+    else
+      launch_kind<AICDF_KIND_CORRECTION>(prm->scheme, prm->payoff, tab, a, grid, lds, s, partials, path_out);
+    AICDF_HIP(hipGetLastError());
+    return reduce_partials_to(partials, grid, double(n_paths), out.dev, s);
+  }
   Workspace* ws = nullptr;
   st = get_workspace(s, &ws);
   if (st != AICDF_OK) return st;
@@ -448,4 +499,13 @@ extern "C" aicdf_status mlmc_level_gbm_async(const aicdf_gbm_params* prm, uint32
   if (!sums_dev) return fail(AICDF_EINVAL, "sums_dev must be non-NULL");
   return gbm_level(prm, level, n_paths, kind, approx, seed, path_offset, LevelOut{nullptr, sums_dev}, path_out,
                    stream);
+}
+
+extern "C" aicdf_status mlmc_level_gbm_noalloc(const aicdf_gbm_params* prm, uint32_t level, uint64_t n_paths,
+                                               int32_t kind, const aicdf_table* approx, uint64_t seed,
+                                               uint64_t path_offset, double* sums_dev, double* path_out,
+                                               void* stream) {
+  if (!sums_dev) return fail(AICDF_EINVAL, "sums_dev must be non-NULL");
+  return gbm_level(prm, level, n_paths, kind, approx, seed, path_offset, LevelOut{nullptr, sums_dev}, path_out,
+                   stream, true);
 }
