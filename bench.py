@@ -58,6 +58,17 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def sig(x, n=4):
+    """x rounded to n significant digits (for the compact JSON line)."""
+    if isinstance(x, float) and x != 0.0 and np.isfinite(x):
+        return float(f"{x:.{n}g}")
+    return x
+
+
+def compact_row(r):
+    return {k: sig(v) for k, v in r.items()}
+
+
 def time_kernel(fn, reps, stream):
     """Average device time of fn() over reps launches (after one untimed
     launch), by HIP events on the stream the library launches on (torch's
@@ -75,23 +86,133 @@ def time_kernel(fn, reps, stream):
     return float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
 
 
+def host_cpu():
+    """The host's CPU model and the worker count the oracle may use: the
+    process's CPU affinity, capped at the OMP_NUM_THREADS share (16 when
+    unset)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    share = int(os.environ.get("OMP_NUM_THREADS", "16") or 16)
+    return {"cpu_model": model, "nproc": avail, "workers": max(1, min(avail, share, 16))}
+
+
+def _oracle_chunk(args):
+    """One worker's share of the oracle baseline: the FP64 dyadic transform of
+    `reps` passes over the stream's uniforms [offset, offset + n); returns
+    the time of the passes."""
+    tab, offset, n, reps = args
+    from oracle import rng, transform
+    u = rng.uniform_fill_f32(SEED, 3, offset, n).astype(np.float64)
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        transform.dyadic_transform(tab, u)
+    return time.perf_counter() - t1
+
+
 def cpu_baseline(seconds):
-    """The oracle's dyadic transform (FP64 numpy, one thread) timed on 2^22
-    uniforms of the same stream, repeated until `seconds` of CPU work."""
-    from oracle import rng, tables, transform
+    """The oracle's dyadic transform (FP64 numpy) on the benchmark stream:
+    one process on 2^22 uniforms, repeated until `seconds` of CPU work, and
+    then the host's workers (one process each, numpy being single-threaded
+    here) on consecutive 2^22-uniform slices with the same repetitions;
+    value = the all-worker rate."""
+    import multiprocessing as mp
+    from oracle import tables
     from oracle.dtypes import round_f32
     tab = round_f32(tables.dyadic_table(16, 1))
     chunk = 1 << 22
-    u = rng.uniform_fill_f32(SEED, 3, 0, chunk).astype(np.float64)
     reps, t = 0, 0.0
     while t < seconds:
-        t1 = time.perf_counter()
-        transform.dyadic_transform(tab, u)
-        t += time.perf_counter() - t1
+        t += _oracle_chunk((tab, 0, chunk, 1))
         reps += 1
-    return {"value": reps * chunk / t, "unit": "samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"the first 2^22 uniforms of the benchmark stream through the oracle's FP64 dyadic "
-                      f"transform (16 rows, degree 1, FP32-rounded coefficients), {reps} repetitions, {t:.1f} s"}
+    one = reps * chunk / t
+    host = host_cpu()
+    w = host["workers"]
+    ctx = mp.get_context("spawn")
+    reps_w = max(1, reps // 2)
+    with ctx.Pool(w) as pool:
+        pool.map(_oracle_chunk, [(tab, k * chunk, 1 << 12, 1) for k in range(w)])  # start-up outside the timing
+        t0 = time.perf_counter()
+        pool.map(_oracle_chunk, [(tab, k * chunk, chunk, reps_w) for k in range(w)])
+        tw = time.perf_counter() - t0
+    allc = w * reps_w * chunk / tw
+    return {"value": allc, "unit": "samples/s", "cores": w, "kind": "oracle",
+            "single_core_value": one, "cpu_model": host["cpu_model"], "nproc": host["nproc"],
+            "sample": f"the oracle's FP64 dyadic transform (16 rows, degree 1, FP32-rounded coefficients) on the "
+                      f"benchmark stream: 1 process x {reps} passes over 2^22 uniforms ({t:.1f} s), then {w} "
+                      f"processes x {reps_w} passes over their own 2^22 uniforms ({tw:.1f} s)"}
+
+
+def c1_leg(A, torch, stream):
+    """The small correctness configuration of Section 3.2 (Code 1) and 3.3
+    (Code 2): 2^20 FP64 uniforms on the u53 grid from the Philox stream
+    (seed 20201217, stream 1), through the 1024-interval constant table and
+    the 16-row linear dyadic table (FP32 coefficients) to FP32 normals.
+    Reports, per table: interval-index mismatches against the oracle (must
+    be 0), the largest difference from the oracle's transform of the same
+    inputs, the L2 and max error against the oracle's FP64 Phi^-1 (bisection
+    on erf/erfc), the device time per call, and the oracle's time for the
+    same transform on 1 process and on the host's workers."""
+    import multiprocessing as mp
+    from oracle import normal, rng, tables, transform
+    from oracle.dtypes import round_f32
+    n = 1 << 20
+    u = torch.empty(n, dtype=torch.float64, device="cuda")
+    A.uniform_fill(u, SEED, 1, 0)
+    uo = rng.uniform_fill_f64(SEED, 1, 0, n)
+    assert np.array_equal(u.cpu().numpy(), uo), "uniforms differ from the oracle's Philox"
+    zx = normal.Phi_inv(uo)
+    tabs = {"const1024": A.Table.const(1024, 0, torch.float32), "linear16": A.Table.dyadic(16, 1, torch.float32)}
+    otab = {"const1024": round_f32(tables.const_table(1024)), "linear16": round_f32(tables.dyadic_table(16, 1))}
+    out = {"n": n, "input": "u53 grid, FP64", "output": "FP32"}
+    host = host_cpu()
+    for name, tab in tabs.items():
+        fn = (lambda: A.approx_icdf_const(tab, u)) if name == "const1024" else (lambda: A.approx_icdf_linear(tab, u))
+        z = fn().cpu().numpy().astype(np.float64)
+        idx = A.approx_icdf_index(tab, u).cpu().numpy().astype(np.int64)
+        t1 = time.perf_counter()
+        if name == "const1024":
+            io = transform.const_index(1024, uo)
+            zo = transform.const_transform(otab[name], uo)
+        else:
+            zo, io = transform.dyadic_transform(otab[name], uo)
+        t_one = time.perf_counter() - t1
+        w = host["workers"]
+        ctx = mp.get_context("spawn")
+        with ctx.Pool(w) as pool:
+            # each worker times its own slice; the slowest one is the wall time
+            t_all = max(pool.map(_c1_oracle_slice, [(name, otab[name], k * (n // w), n // w) for k in range(w)]))
+        ms = time_kernel(fn, 20, stream)
+        d = z - zx
+        out[name] = {"index_mismatches": int(np.count_nonzero(idx != io)),
+                     "max_diff_vs_oracle_transform": float(np.max(np.abs(z - zo) / np.maximum(1.0, np.abs(zo)))),
+                     "rmse_vs_oracle_phi_inv": float(np.sqrt(np.mean(d * d))), "max_err_vs_oracle_phi_inv":
+                     float(np.max(np.abs(d))), "gpu_us_per_call": ms * 1e3,
+                     "oracle_ns_per_sample_1core": t_one / n * 1e9,
+                     "oracle_ns_per_sample_all_workers": t_all / n * 1e9, "oracle_workers": w}
+        log(f"C1 {name}: {out[name]}")
+    return out
+
+
+def _c1_oracle_slice(args):
+    """One worker's slice of the C1 oracle transform; returns its time."""
+    name, tab, off, m = args
+    from oracle import rng, transform
+    uo = rng.uniform_fill_f64(SEED, 1, off, m)
+    t1 = time.perf_counter()
+    if name == "const1024":
+        transform.const_index(len(tab), uo)
+        transform.const_transform(tab, uo)
+    else:
+        transform.dyadic_transform(tab, uo)
+    return time.perf_counter() - t1
 
 
 def exact_error_on_grid(A, torch, tab, out_dtype, kind):
@@ -397,9 +518,15 @@ def main():
     ms = time_kernel(lambda: A.uniform_fill(u, SEED, 3, 0), 3, stream)
     sweep.append({"table": "uniform_fill_f32", "samples_per_s": N_MAIN / (ms * 1e-3), "ms": ms,
                   "GBs": 4 * N_MAIN / (ms * 1e-3) / 1e9})
-    result["sweep"] = sweep
+    result["sweep"] = [compact_row(r) for r in sweep]
+    result["sweep_error_reference"] = ("rmse / max_err: against the library's FP64 exact_icdf (Wichura's AS 241) "
+                                       "on every point of the u24 grid; exact_icdf is pinned to the oracle's "
+                                       "Phi^-1 at 4e-15 max(1, |z|) by the GPU tests")
     del u, z
     torch.cuda.empty_cache()
+
+    # ---------------------------------------------------------- C1
+    result["c1"] = c1_leg(A, torch, stream)
 
     # ---------------------------------------------------------- MLMC
     if not args.no_mlmc:
@@ -408,8 +535,7 @@ def main():
         if args.detail:
             with open(args.detail, "w") as f:
                 json.dump(full, f, indent=1)
-        result["mlmc"] = {k: (v if k in ("surrogate", "fig4b", "fig4b_time_average") else mlmc_driver._short(v))
-                          for k, v in full.items()}
+        result["mlmc"] = mlmc_driver.compact(full)
 
     # ---------------------------------------------------------- CPU baseline
     log("cpu baseline (oracle) ...")

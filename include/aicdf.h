@@ -260,12 +260,12 @@ typedef struct {
  * approx_icdf_linear / approx_icdf_const on the same u24 values.
  * Paths path_offset .. path_offset+n_paths-1
  * of the stream (seed, level, kind) are simulated; any split of a path range
- * over calls gives the same per-path values, except that calls of at most
- * 8192 paths with 2^level >= 128 run one path per wavefront (each lane
- * multiplies the linear step maps of 2^level/64 consecutive steps, and an
- * ordered shuffle tree multiplies the lane products), whose FP32 products
- * round in another order: their per-path values agree with the other launch
- * shape to FP32 rounding.
+ * over calls gives the same per-path values, except that calls with
+ * 2^level >= 4 and n_paths x G <= 2^19, G = min(64, 2^level / 2), run one
+ * path per group of G lanes (each lane multiplies the linear step maps of
+ * 2^level/G consecutive steps, and an ordered shuffle tree multiplies the
+ * lane products), whose FP32 products round in another order: their per-path
+ * values agree with the other launch shape to FP32 rounding.
  * Draws (Philox counter (block, lo32(path), hi32(path), level | kind << 8),
  * key seed): APPROX takes one 32-bit word per fine step (u24 grid as in
  * aicdf_uniform_fill F32); EXACT and CORRECTION take two words per step
@@ -393,6 +393,32 @@ aicdf_status mlmc_level_gbm_noalloc(const aicdf_gbm_params* params, uint32_t lev
                                     int32_t kind, const aicdf_table* approx, uint64_t seed,
                                     uint64_t path_offset, double* sums_dev, double* path_out,
                                     void* stream);
+
+/* One level job of a batched call: the arguments of one level call. */
+typedef struct {
+  uint32_t level;
+  int32_t kind;         /* AICDF_KIND_EXACT, _APPROX or _CORRECTION */
+  uint64_t n_paths;
+  uint64_t path_offset;
+} aicdf_level_job;
+
+/* Several levels of one estimator in ONE launch (Section 4.1: an estimator is
+ * a sum over levels and kinds, each level call a sum over its paths): the
+ * level kernel runs every job, each on exactly the work-groups and paths its
+ * own mlmc_level_gbm_async call would use, followed by one final pass with a
+ * work-group per job, so every job's 8 sums are bit-identical to that call's
+ * (per-path output is not offered).  Stream-ordered like
+ * mlmc_level_gbm_async; sums_dev: device, n_jobs x 8 doubles in job order,
+ * each row laid out as in that call.  jobs: host array of n_jobs <= 24
+ * entries, read before the call returns; jobs of 0 paths give all-zero rows.
+ * The jobs share params, approx and seed; kinds may be mixed (a nested
+ * estimator's APPROX and CORRECTION levels in one launch).  Work-groups are
+ * dispatched in job order, so put the longest jobs (the few-path high levels,
+ * whose time is one path's serial time) first.  Uses the stream's workspace
+ * (4.7 MB of batch partials, allocated on the first batched call).
+ * Errors: EINVAL, ERANGE, EDTYPE, EHIP, ENOMEM (an error in job j names it). */
+aicdf_status mlmc_levels_gbm(const aicdf_gbm_params* params, const aicdf_level_job* jobs, uint32_t n_jobs,
+                             const aicdf_table* approx, uint64_t seed, double* sums_dev, void* stream);
 aicdf_status mlmc_level_cir_async(const aicdf_cir_params* params, uint32_t level, uint64_t n_paths,
                                   int32_t kind, const aicdf_surrogate* approx, uint64_t seed,
                                   uint64_t path_offset, double* sums_dev, double* path_out,

@@ -9,7 +9,7 @@ import ctypes as C
 
 import torch
 
-from ._lib import (AicdfError, CirParams, GbmParams, LevelSums, check, lib)
+from ._lib import (AicdfError, CirParams, GbmParams, LevelJob, LevelSums, check, lib)
 
 F64, F32, F16, BF16 = 0, 1, 2, 3
 KIND_EXACT, KIND_APPROX, KIND_CORRECTION, KIND_TWOWAY = 0, 1, 2, 3
@@ -269,6 +269,36 @@ def mlmc_level_gbm_async(params, level, n_paths, kind, table, seed, path_offset,
     po = _path_out(path_out, n_paths)
     check(lib.mlmc_level_gbm_async(C.byref(p), level, n_paths, kind, table.handle if table is not None else None,
                                    seed, path_offset, _sums_dev(sums), po, _stream(stream)))
+
+
+MAX_JOBS = 24
+
+
+def _jobs(jobs):
+    """(level, kind, n_paths, path_offset) tuples -> a ctypes LevelJob array."""
+    jobs = list(jobs)
+    arr = (LevelJob * max(len(jobs), 1))()
+    for i, (level, kind, n, off) in enumerate(jobs):
+        arr[i] = LevelJob(int(level), int(kind), int(n), int(off))
+    return arr, len(jobs)
+
+
+def _batch_sums(sums, n_jobs):
+    if not isinstance(sums, torch.Tensor) or sums.dtype != torch.float64 or sums.numel() < 8 * n_jobs:
+        raise AicdfError(-1, f"sums must be a float64 CUDA tensor of at least {8 * n_jobs} elements")
+    return _dev(sums, "sums")
+
+
+def mlmc_levels_gbm(params, jobs, table, seed, sums, stream=None):
+    """Several GBM levels in one launch (stream-ordered): jobs is a list of
+    (level, kind, n_paths, path_offset); row j of `sums` (n_jobs x 8 float64
+    on the device) receives job j's 8 sums, bit-identical to its
+    mlmc_level_gbm_async call."""
+    p = GbmParams(params["S0"], params["r"], params["sigma"], params["T"], params.get("K", 1.0),
+                  int(params.get("scheme", 0)), int(params.get("payoff", 0)))
+    arr, n = _jobs(jobs)
+    check(lib.mlmc_levels_gbm(C.byref(p), arr, n, table.handle if table is not None else None, seed,
+                              _batch_sums(sums, n), _stream(stream)))
 
 
 def mlmc_level_gbm_noalloc(params, level, n_paths, kind, table, seed, path_offset, sums, path_out=None,

@@ -31,6 +31,10 @@ class CirParams(C.Structure):
                 ("functional", i32), ("reserved", i32)]
 
 
+class LevelJob(C.Structure):
+    _fields_ = [("level", u32), ("kind", i32), ("n_paths", u64), ("path_offset", u64)]
+
+
 class LevelSums(C.Structure):
     _fields_ = [("n", dbl), ("sum", dbl * 4), ("sum_pf", dbl), ("sum_pc", dbl),
                 ("kernel_ms", dbl), ("fallbacks", u64), ("reserved", u64)]
@@ -70,6 +74,7 @@ _PROTOS = {
     "mlmc_level_cir_sankaran": (status, [C.POINTER(CirParams), u32, u64, i32, u64, u64, C.POINTER(LevelSums), vp,
                                          vp]),
     "mlmc_level_gbm_async": (status, [C.POINTER(GbmParams), u32, u64, i32, vp, u64, u64, vp, vp, vp]),
+    "mlmc_levels_gbm": (status, [C.POINTER(GbmParams), C.POINTER(LevelJob), u32, vp, u64, vp, vp]),
     "mlmc_level_gbm_noalloc": (status, [C.POINTER(GbmParams), u32, u64, i32, vp, u64, u64, vp, vp, vp]),
     "mlmc_level_cir_async": (status, [C.POINTER(CirParams), u32, u64, i32, vp, u64, u64, vp, vp, vp]),
     "mlmc_level_cir_table_async": (status, [C.POINTER(CirParams), u32, u64, i32, vp, u64, u64, vp, vp, vp]),

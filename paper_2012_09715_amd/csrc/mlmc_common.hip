@@ -14,10 +14,9 @@ namespace {
 // then a fixed-order tree over the 256 values.  The result does not depend on
 // scheduling, so repeated calls are bit-identical.  Writes the kSumsOut
 // results and clears the fallback counter for the next call on the stream.
-__global__ __launch_bounds__(kLevelBlock) void reduce_partials_kernel(const double* __restrict__ partials,
-                                                                      unsigned nblocks,
-                                                                      unsigned long long* __restrict__ counter,
-                                                                      double n_paths, double* __restrict__ out) {
+__device__ __forceinline__ void reduce_partials_block(const double* __restrict__ partials, unsigned nblocks,
+                                                      unsigned long long* __restrict__ counter, double n_paths,
+                                                      double* __restrict__ out) {
   __shared__ double red[kSums][kLevelBlock];
   KSum k[kSums];
   // unrolled so that several blocks' loads are in flight together (same order)
@@ -40,6 +39,22 @@ __global__ __launch_bounds__(kLevelBlock) void reduce_partials_kernel(const doub
     if (counter) *counter = 0ull;
   }
   if (threadIdx.x == kSums + 1) out[kSums + 1] = n_paths;
+}
+
+__global__ __launch_bounds__(kLevelBlock) void reduce_partials_kernel(const double* __restrict__ partials,
+                                                                      unsigned nblocks,
+                                                                      unsigned long long* __restrict__ counter,
+                                                                      double n_paths, double* __restrict__ out) {
+  reduce_partials_block(partials, nblocks, counter, n_paths, out);
+}
+
+// Work-group j: job j of a batch.
+__global__ __launch_bounds__(kLevelBlock) void reduce_batch_kernel(const double* __restrict__ partials, JobSpans sp,
+                                                                   unsigned long long* __restrict__ counters,
+                                                                   double* __restrict__ out) {
+  const uint32_t j = blockIdx.x;
+  reduce_partials_block(partials + size_t(sp.start[j]) * kSums, sp.start[j + 1] - sp.start[j],
+                        counters ? counters + j : nullptr, sp.n_paths[j], out + size_t(j) * kSumsOut);
 }
 
 std::mutex g_ws_mutex;
@@ -68,6 +83,8 @@ aicdf_status get_workspace(hipStream_t s, Workspace** out) {
   if (!ws) return fail(AICDF_ENOMEM, "host allocation failed");
   auto release = [ws]() {
     if (ws->partials) (void)hipFree(ws->partials);
+    if (ws->batch_partials) (void)hipFree(ws->batch_partials);
+    if (ws->batch_counters) (void)hipFree(ws->batch_counters);
     if (ws->host_result) (void)hipHostFree(ws->host_result);
     if (ws->counter) (void)hipFree(ws->counter);
     if (ws->ev0) (void)hipEventDestroy(ws->ev0);
@@ -89,6 +106,32 @@ aicdf_status get_workspace(hipStream_t s, Workspace** out) {
   g_ws[key] = ws;
   *out = ws;
   return AICDF_OK;
+}
+
+aicdf_status get_batch_buffers(Workspace* ws) {
+  if (ws->batch_partials) return AICDF_OK;
+  double* p = nullptr;
+  unsigned long long* c = nullptr;
+  if (hipMalloc(&p, sizeof(double) * size_t(kMaxJobs) * kMaxLevelBlocks * kSums) != hipSuccess) {
+    return fail(AICDF_ENOMEM, "allocation of the batch partials failed");
+  }
+  if (hipMalloc(&c, sizeof(unsigned long long) * kMaxJobs) != hipSuccess ||
+      hipMemset(c, 0, sizeof(unsigned long long) * kMaxJobs) != hipSuccess) {
+    (void)hipFree(p);
+    if (c) (void)hipFree(c);
+    return fail(AICDF_ENOMEM, "allocation of the batch counters failed");
+  }
+  ws->batch_partials = p;
+  ws->batch_counters = c;
+  return AICDF_OK;
+}
+
+aicdf_status reduce_batch(const double* partials, const JobSpans& spans, unsigned long long* counters, double* out,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(reduce_batch_kernel, dim3(spans.n_jobs), dim3(kLevelBlock), 0, s, partials, spans, counters,
+                     out);
+  AICDF_HIP(hipGetLastError());
+  return ok();
 }
 
 aicdf_status begin_level(Workspace* ws, hipStream_t s, const LevelOut& o) {

@@ -44,8 +44,9 @@ struct LevelAcc {
   }
 };
 
-// Block-wide tree reduction of the per-thread sums into partials[blockIdx.x].
-__device__ __forceinline__ void block_reduce_store(const LevelAcc& acc, double* __restrict__ partials) {
+// Block-wide tree reduction of the per-thread sums into partials[bid].
+__device__ __forceinline__ void block_reduce_store(const LevelAcc& acc, double* __restrict__ partials,
+                                                   uint32_t bid) {
   __shared__ double red[kSums][kLevelBlock];
 #pragma unroll
   for (int j = 0; j < kSums; ++j) red[j][threadIdx.x] = acc.k[j];
@@ -57,8 +58,31 @@ __device__ __forceinline__ void block_reduce_store(const LevelAcc& acc, double* 
     }
     __syncthreads();
   }
-  if (threadIdx.x < kSums) partials[size_t(blockIdx.x) * kSums + threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x < kSums) partials[size_t(bid) * kSums + threadIdx.x] = red[threadIdx.x][0];
 }
+
+__device__ __forceinline__ void block_reduce_store(const LevelAcc& acc, double* __restrict__ partials) {
+  block_reduce_store(acc, partials, blockIdx.x);
+}
+
+// Level-batched calls (one launch for many (level, kind) jobs of one
+// estimator): at most kMaxJobs jobs; job j owns the work-groups
+// [start[j], start[j+1]) of the launch, as many as its own level call would
+// launch, and its partials sit at the same offsets of the batch's partials.
+constexpr int kMaxJobs = 24;
+
+struct JobSpans {
+  uint32_t start[kMaxJobs + 1];
+  double n_paths[kMaxJobs];
+  uint32_t n_jobs;
+};
+
+// The final pass of a batch: one work-group per job, each the single-call
+// final pass over its own partials (the same summation order, so each job's
+// sums are bit-identical to its level call's); out: n_jobs x kSumsOut.
+// counters: one fallback counter per job (or NULL), read and cleared.
+aicdf_status reduce_batch(const double* partials, const JobSpans& spans, unsigned long long* counters, double* out,
+                          hipStream_t s);
 
 // Host side: one workspace per (device, stream) a level call has used
 // (created on first use, kept until the process ends), so that calls on
@@ -70,6 +94,8 @@ __device__ __forceinline__ void block_reduce_store(const LevelAcc& acc, double* 
 // zeroed at creation, read and cleared by the final pass of each call.
 struct Workspace {
   double* partials = nullptr;  // kMaxLevelBlocks * kSums doubles
+  double* batch_partials = nullptr;            // kMaxJobs * kMaxLevelBlocks * kSums doubles (first batch call)
+  unsigned long long* batch_counters = nullptr;  // kMaxJobs fallback counters, zero between calls
   double* host_result = nullptr;  // kSumsOut doubles of pinned host memory, written by the final pass
   unsigned long long* counter = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -91,6 +117,9 @@ struct LevelOut {
 aicdf_status check_level_out(const LevelOut& o);
 
 aicdf_status get_workspace(hipStream_t s, Workspace** ws);
+
+// The workspace's batch buffers, allocated on its first batched call.
+aicdf_status get_batch_buffers(Workspace* ws);
 
 // Records the start event of a synchronous call (no-op for a stream-ordered one).
 aicdf_status begin_level(Workspace* ws, hipStream_t s, const LevelOut& o);

@@ -14,14 +14,17 @@
 // from the FP64 exact normal minus the FP32 approximate one.
 //
 // Calls with few paths of many steps (the high levels of an MLMC allocation,
-// whose time is the serial time of one path) run one path per wavefront
-// instead: every scheme step maps the state linearly,
+// whose time is the serial time of one path) run one path per group of
+// G = min(64, 2^l / 2) lanes instead: every scheme step maps the state
+// linearly,
 //   X' = g X  (EXACT, APPROX),   (X~, e)' = [[g~, 0], [dg, g^]] (X~, e),
-// so each lane forms the product of the step maps of its 2^l/64 consecutive
+// so each lane forms the product of the step maps of its 2^l/G consecutive
 // steps (draws and normals included) and an ordered tree of shuffles
-// multiplies the 64 lane products; lane 0 applies the result to (S0, 0).
+// multiplies the G lane products; the group's first lane applies the result
+// to (S0, 0).
 #include <cmath>
 #include <mutex>
+#include <string>
 
 #include "mlmc_common.hpp"
 
@@ -50,13 +53,16 @@ struct GbmArgs {
   uint32_t rows;
   float inv_log2r;     // geometric: 1 / log2(r)
   int table_in_lds;
-  uint32_t sparse;     // 1: one path per wavefront (2^l >= 128)
+  uint32_t sparse;     // 1: one path per group of `group` lanes
+  uint32_t group;      // lanes per path when sparse: min(64, 2^l / 2)
 };
 
-// One path per wavefront for calls of at most this many paths with 2^l >= 128
-// steps (two or more steps per lane, so coarse steps stay within a lane):
-// 64 lanes per path then still fill the GPU's 256 x 2048 lanes.
-constexpr uint64_t kGbmSparseMaxPaths = 8192;
+// A level of 2^l >= 4 steps runs one path per group of G = min(64, 2^l / 2)
+// lanes (two or more steps per lane, so coarse steps stay within a lane) when
+// its paths times G fit the lanes the GPU keeps resident (256 CUs x 2048):
+// its time is then the serial time of 2^l / G steps instead of 2^l.  This
+// includes one path per wavefront for up to 8192 paths at 2^l >= 128.
+constexpr uint64_t kGbmGroupLanes = uint64_t(1) << 19;
 
 // [[a, 0], [c, b]]: X' = a X, e' = c X + b e.
 struct Lt2 {
@@ -68,11 +74,13 @@ __device__ __forceinline__ Lt2 lt2_mul(const Lt2& y, const Lt2& x) {
   return Lt2{y.a * x.a, fmaf(y.c, x.a, y.b * x.c), y.b * x.b};
 }
 
-// Ordered product over the wave, M_63 ... M_0, delivered to lane 0.
-__device__ __forceinline__ Lt2 lt2_wave_product(Lt2 m, int lane) {
-  for (int d = 1; d < 64; d <<= 1) {
+// Ordered product over a group of G lanes (G a power of two, groups aligned
+// within the wave), M_(G-1) ... M_0, delivered to the group's lane g = 0; a
+// lane reads only lanes of its own group.
+__device__ __forceinline__ Lt2 lt2_group_product(Lt2 m, int g, int G) {
+  for (int d = 1; d < G; d <<= 1) {
     const Lt2 o{__shfl_down(m.a, d), __shfl_down(m.c, d), __shfl_down(m.b, d)};
-    if ((lane & (2 * d - 1)) == 0) m = lt2_mul(o, m);
+    if ((g & (2 * d - 1)) == 0) m = lt2_mul(o, m);
   }
   return m;
 }
@@ -196,35 +204,42 @@ __device__ __forceinline__ void gbm_chunk(const GbmArgs& a, const float* tab, ui
   }
 }
 
-template <int KIND, int SCHEME, int PAYOFF, int TAB, bool SPARSE>
-__global__ __launch_bounds__(kLevelBlock) void gbm_level_kernel(GbmArgs a, double* __restrict__ partials,
-                                                               double* __restrict__ path_out) {
+// The approximation's table staged in LDS (when it fits), else read from
+// global memory.
+template <int TAB>
+__device__ __forceinline__ const float* stage_table(const GbmArgs& a) {
   extern __shared__ f32x4 lds4[];
-  const float* tab = a.table;
-  if (KIND != AICDF_KIND_EXACT && a.table_in_lds) {
-    float* l = reinterpret_cast<float*>(lds4);
-    const uint32_t nf = TAB == 0 ? 64u * 4u : TAB == 2 ? 64u * 6u : a.rows;
-    for (uint32_t i = threadIdx.x; i < nf; i += kLevelBlock) l[i] = a.table[i];
-    __syncthreads();
-    tab = l;
-  }
+  if (!a.table_in_lds) return a.table;
+  float* l = reinterpret_cast<float*>(lds4);
+  const uint32_t nf = TAB == 0 ? 64u * 4u : TAB == 2 ? 64u * 6u : a.rows;
+  for (uint32_t i = threadIdx.x; i < nf; i += kLevelBlock) l[i] = a.table[i];
+  __syncthreads();
+  return l;
+}
+
+// Work-group `bid` of the `nblk` work-groups of one level: its paths (a
+// grid-stride loop over nblk work-groups), their sums into partials[bid].
+template <int KIND, int SCHEME, int PAYOFF, int TAB, bool SPARSE>
+__device__ __forceinline__ void gbm_level_block(const GbmArgs& a, const float* tab, double* __restrict__ partials,
+                                                double* __restrict__ path_out, uint32_t bid, uint32_t nblk) {
   LevelAcc acc;
   const uint32_t nf = a.nsteps;
   if constexpr (SPARSE) {
-    // one path per wavefront; lane l takes steps [l m, l m + m), m = 2^l / 64
-    const int lane = int(threadIdx.x % 64);
-    const uint32_t m = nf / 64;
-    const uint64_t per_block = kLevelBlock / 64;
-    for (uint64_t base = uint64_t(blockIdx.x) * per_block; base < a.n_paths;
-         base += uint64_t(gridDim.x) * per_block) {
-      const uint64_t i = base + threadIdx.x / 64;
-      if (i >= a.n_paths) continue;  // wave-uniform
+    // one path per group of G lanes; lane g of a group takes steps
+    // [g m, g m + m), m = 2^l / G (even)
+    const int G = int(a.group);
+    const int g = int(threadIdx.x) & (G - 1);
+    const uint32_t m = nf / uint32_t(G);
+    const uint64_t per_block = kLevelBlock / G;
+    for (uint64_t base = uint64_t(bid) * per_block; base < a.n_paths; base += uint64_t(nblk) * per_block) {
+      const uint64_t i = base + threadIdx.x / G;
+      if (i >= a.n_paths) continue;  // uniform over each group
       const uint64_t P = a.path_offset + i;
       Lt2 f, c;
-      gbm_chunk<KIND, SCHEME, TAB>(a, tab, uint32_t(P), uint32_t(P >> 32), lane * m, lane * m + m, f, c);
-      f = lt2_wave_product(f, lane);
-      c = lt2_wave_product(c, lane);
-      if (lane == 0) {
+      gbm_chunk<KIND, SCHEME, TAB>(a, tab, uint32_t(P), uint32_t(P >> 32), g * m, g * m + m, f, c);
+      f = lt2_group_product(f, g, G);
+      c = lt2_group_product(c, g, G);
+      if (g == 0) {
         float Y, Pf, Pc;
         const float Xf = a.S0 * f.a, Xc = a.S0 * c.a;
         if constexpr (KIND == AICDF_KIND_CORRECTION) {
@@ -247,11 +262,11 @@ __global__ __launch_bounds__(kLevelBlock) void gbm_level_kernel(GbmArgs a, doubl
         }
       }
     }
-    block_reduce_store(acc, partials);
+    block_reduce_store(acc, partials, bid);
     return;
   }
-  const uint64_t stride = uint64_t(gridDim.x) * kLevelBlock;
-  for (uint64_t i = uint64_t(blockIdx.x) * kLevelBlock + threadIdx.x; i < a.n_paths; i += stride) {
+  const uint64_t stride = uint64_t(nblk) * kLevelBlock;
+  for (uint64_t i = uint64_t(bid) * kLevelBlock + threadIdx.x; i < a.n_paths; i += stride) {
     const uint64_t P = a.path_offset + i;
     const uint32_t plo = uint32_t(P), phi = uint32_t(P >> 32);
     float Y, Pf, Pc;
@@ -336,7 +351,80 @@ __global__ __launch_bounds__(kLevelBlock) void gbm_level_kernel(GbmArgs a, doubl
       path_out[3 * i + 2] = double(Pc);
     }
   }
-  block_reduce_store(acc, partials);
+  block_reduce_store(acc, partials, bid);
+}
+
+template <int KIND, int SCHEME, int PAYOFF, int TAB, bool SPARSE>
+__global__ __launch_bounds__(kLevelBlock) void gbm_level_kernel(GbmArgs a, double* __restrict__ partials,
+                                                               double* __restrict__ path_out) {
+  const float* tab = KIND != AICDF_KIND_EXACT ? stage_table<TAB>(a) : a.table;
+  gbm_level_block<KIND, SCHEME, PAYOFF, TAB, SPARSE>(a, tab, partials, path_out, blockIdx.x, gridDim.x);
+}
+
+// The level jobs of one batched call: the arguments of each job's level call
+// and the work-group spans (job j owns [start[j], start[j+1])).
+struct GbmBatch {
+  GbmArgs job[kMaxJobs];
+  uint32_t start[kMaxJobs + 1];
+  uint32_t n_jobs;
+};
+
+// KSET 0: EXACT jobs only; 1: APPROX jobs only; 2: any kinds.  Each
+// work-group finds its job (a wave-uniform scan of at most kMaxJobs spans)
+// and runs that job's level code on its share of the job's paths.
+template <int KSET, int SCHEME, int PAYOFF, int TAB>
+__global__ __launch_bounds__(kLevelBlock) void gbm_levels_kernel(GbmBatch b, double* __restrict__ partials) {
+  uint32_t j = 0;
+  while (j + 1 < b.n_jobs && blockIdx.x >= b.start[j + 1]) ++j;
+  const GbmArgs a = b.job[j];
+  const uint32_t bid = blockIdx.x - b.start[j], nblk = b.start[j + 1] - b.start[j];
+  double* part = partials + size_t(b.start[j]) * kSums;
+  const int kind = int(a.tag >> 8);
+  if constexpr (KSET == 0) {
+    if (a.sparse)
+      gbm_level_block<AICDF_KIND_EXACT, SCHEME, PAYOFF, TAB, true>(a, a.table, part, nullptr, bid, nblk);
+    else
+      gbm_level_block<AICDF_KIND_EXACT, SCHEME, PAYOFF, TAB, false>(a, a.table, part, nullptr, bid, nblk);
+  } else {
+    const float* tab = kind != AICDF_KIND_EXACT ? stage_table<TAB>(a) : a.table;
+    if (KSET == 1 || kind == AICDF_KIND_APPROX) {
+      if (a.sparse)
+        gbm_level_block<AICDF_KIND_APPROX, SCHEME, PAYOFF, TAB, true>(a, tab, part, nullptr, bid, nblk);
+      else
+        gbm_level_block<AICDF_KIND_APPROX, SCHEME, PAYOFF, TAB, false>(a, tab, part, nullptr, bid, nblk);
+    } else if constexpr (KSET == 2) {
+      if (kind == AICDF_KIND_CORRECTION) {
+        if (a.sparse)
+          gbm_level_block<AICDF_KIND_CORRECTION, SCHEME, PAYOFF, TAB, true>(a, tab, part, nullptr, bid, nblk);
+        else
+          gbm_level_block<AICDF_KIND_CORRECTION, SCHEME, PAYOFF, TAB, false>(a, tab, part, nullptr, bid, nblk);
+      } else {
+        if (a.sparse)
+          gbm_level_block<AICDF_KIND_EXACT, SCHEME, PAYOFF, TAB, true>(a, tab, part, nullptr, bid, nblk);
+        else
+          gbm_level_block<AICDF_KIND_EXACT, SCHEME, PAYOFF, TAB, false>(a, tab, part, nullptr, bid, nblk);
+      }
+    }
+  }
+}
+
+template <int KSET, int SCHEME, int PAYOFF>
+void launch_batch_tab(int tab, const GbmBatch& b, unsigned grid, size_t lds, hipStream_t s, double* p) {
+  if (tab == 0 || KSET == 0)
+    hipLaunchKernelGGL((gbm_levels_kernel<KSET, SCHEME, PAYOFF, 0>), dim3(grid), dim3(kLevelBlock), lds, s, b, p);
+  else if (tab == 2)
+    hipLaunchKernelGGL((gbm_levels_kernel<KSET, SCHEME, PAYOFF, 2>), dim3(grid), dim3(kLevelBlock), lds, s, b, p);
+  else
+    hipLaunchKernelGGL((gbm_levels_kernel<KSET, SCHEME, PAYOFF, 1>), dim3(grid), dim3(kLevelBlock), lds, s, b, p);
+}
+
+template <int KSET>
+void launch_batch(int scheme, int payoff, int tab, const GbmBatch& b, unsigned grid, size_t lds, hipStream_t s,
+                  double* p) {
+  if (scheme == 0 && payoff == 0) launch_batch_tab<KSET, 0, 0>(tab, b, grid, lds, s, p);
+  if (scheme == 0 && payoff == 1) launch_batch_tab<KSET, 0, 1>(tab, b, grid, lds, s, p);
+  if (scheme == 1 && payoff == 0) launch_batch_tab<KSET, 1, 0>(tab, b, grid, lds, s, p);
+  if (scheme == 1 && payoff == 1) launch_batch_tab<KSET, 1, 1>(tab, b, grid, lds, s, p);
 }
 
 template <int KIND, int SCHEME, int PAYOFF, int TAB>
@@ -391,31 +479,22 @@ aicdf_status scratch_address(int dev, double** out) {
 // scratch_partials: when non-NULL the level's partials go there and the sums
 // to out.dev with no workspace (nothing allocated, no lock); else the
 // per-stream workspace is used.
-aicdf_status gbm_level(const aicdf_gbm_params* prm, uint32_t level, uint64_t n_paths, int32_t kind,
-                       const aicdf_table* approx, uint64_t seed, uint64_t path_offset, const LevelOut& out,
-                       double* path_out, void* stream, bool no_alloc = false) {
-  if (!prm) return fail(AICDF_EINVAL, "params must be non-NULL");
-  aicdf_status st = check_level_out(out);
-  if (st != AICDF_OK) return st;
+// Checks one level's arguments and fills its kernel arguments, table kind,
+// LDS bytes and work-group count (the launch shape of its level call).
+aicdf_status setup_gbm(const aicdf_gbm_params* prm, uint32_t level, uint64_t n_paths, int32_t kind,
+                       const aicdf_table* approx, uint64_t seed, uint64_t path_offset, int dev, GbmArgs& a,
+                       int& tab, size_t& lds, unsigned& grid) {
   if (level > 20) return fail(AICDF_ERANGE, "level %u > 20", level);
   if (kind < 0 || kind > 2) return fail(AICDF_EINVAL, "kind must be 0, 1 or 2");
-  if (prm->scheme < 0 || prm->scheme > 1 || prm->payoff < 0 || prm->payoff > 1)
-    return fail(AICDF_EINVAL, "scheme and payoff must be 0 or 1");
-  if (!(prm->T > 0.0) || !(prm->sigma >= 0.0) || !std::isfinite(prm->S0) || !std::isfinite(prm->r))
-    return fail(AICDF_EINVAL, "need T > 0, sigma >= 0, finite S0 and r");
   if (kind != AICDF_KIND_EXACT && !approx) return fail(AICDF_EINVAL, "the approximate kinds need a table");
-  if (n_paths == 0) return no_alloc ? reduce_partials_to(nullptr, 0, 0.0, out.dev, static_cast<hipStream_t>(stream))
-                                    : empty_level(static_cast<hipStream_t>(stream), out);
   if (n_paths > (uint64_t(1) << 40)) return fail(AICDF_ERANGE, "n_paths > 2^40");
   if (path_offset + n_paths < path_offset) return fail(AICDF_ERANGE, "path_offset + n_paths overflows");
-  int dev = 0;
-  AICDF_HIP(hipGetDevice(&dev));
   if (approx && kind != AICDF_KIND_EXACT && approx->device != dev)
     return fail(AICDF_EINVAL, "table lives on device %d, current device is %d", approx->device, dev);
 
   const uint32_t nf = 1u << level;
   const double dt = prm->T / nf;
-  GbmArgs a{};
+  a = GbmArgs{};
   a.S0 = float(prm->S0);
   a.r_dt = float(prm->r * dt);
   a.r_2dt = float(prm->r * 2.0 * dt);
@@ -433,8 +512,8 @@ aicdf_status gbm_level(const aicdf_gbm_params* prm, uint32_t level, uint64_t n_p
   a.k0 = uint32_t(seed);
   a.k1 = uint32_t(seed >> 32);
   a.tag = level | (uint32_t(kind) << 8);
-  int tab = 0;
-  size_t lds = 0;
+  tab = 0;
+  lds = 0;
   if (kind != AICDF_KIND_EXACT) {
     tab = approx->kind == 1 ? 0 : approx->kind == 2 ? 2 : 1;
     if (tab == 2) a.inv_log2r = float(1.0 / std::log2(approx->r));
@@ -446,10 +525,43 @@ aicdf_status gbm_level(const aicdf_gbm_params* prm, uint32_t level, uint64_t n_p
     a.table_in_lds = bytes <= 64 * 1024;
     lds = a.table_in_lds ? bytes : 0;
   }
-  a.sparse = (nf >= 128 && n_paths <= kGbmSparseMaxPaths) ? 1u : 0u;
-  const uint64_t per_block = a.sparse ? kLevelBlock / 64 : kLevelBlock;
+  a.group = nf >= 4 ? (nf / 2 < 64 ? nf / 2 : 64) : 0u;
+  a.sparse = (a.group && n_paths * a.group <= kGbmGroupLanes) ? 1u : 0u;
+  const uint64_t per_block = a.sparse ? kLevelBlock / a.group : kLevelBlock;
   const uint64_t need = (n_paths + per_block - 1) / per_block;
-  const unsigned grid = unsigned(need < uint64_t(kMaxLevelBlocks) ? need : kMaxLevelBlocks);
+  grid = unsigned(need < uint64_t(kMaxLevelBlocks) ? need : kMaxLevelBlocks);
+  return AICDF_OK;
+}
+
+aicdf_status check_gbm_params(const aicdf_gbm_params* prm) {
+  if (!prm) return fail(AICDF_EINVAL, "params must be non-NULL");
+  if (prm->scheme < 0 || prm->scheme > 1 || prm->payoff < 0 || prm->payoff > 1)
+    return fail(AICDF_EINVAL, "scheme and payoff must be 0 or 1");
+  if (!(prm->T > 0.0) || !(prm->sigma >= 0.0) || !std::isfinite(prm->S0) || !std::isfinite(prm->r))
+    return fail(AICDF_EINVAL, "need T > 0, sigma >= 0, finite S0 and r");
+  return AICDF_OK;
+}
+
+aicdf_status gbm_level(const aicdf_gbm_params* prm, uint32_t level, uint64_t n_paths, int32_t kind,
+                       const aicdf_table* approx, uint64_t seed, uint64_t path_offset, const LevelOut& out,
+                       double* path_out, void* stream, bool no_alloc = false) {
+  aicdf_status st = check_gbm_params(prm);
+  if (st != AICDF_OK) return st;
+  st = check_level_out(out);
+  if (st != AICDF_OK) return st;
+  if (level > 20) return fail(AICDF_ERANGE, "level %u > 20", level);
+  if (kind < 0 || kind > 2) return fail(AICDF_EINVAL, "kind must be 0, 1 or 2");
+  if (kind != AICDF_KIND_EXACT && !approx) return fail(AICDF_EINVAL, "the approximate kinds need a table");
+  if (n_paths == 0) return no_alloc ? reduce_partials_to(nullptr, 0, 0.0, out.dev, static_cast<hipStream_t>(stream))
+                                    : empty_level(static_cast<hipStream_t>(stream), out);
+  int dev = 0;
+  AICDF_HIP(hipGetDevice(&dev));
+  GbmArgs a;
+  int tab = 0;
+  size_t lds = 0;
+  unsigned grid = 0;
+  st = setup_gbm(prm, level, n_paths, kind, approx, seed, path_offset, dev, a, tab, lds, grid);
+  if (st != AICDF_OK) return st;
 
   auto s = static_cast<hipStream_t>(stream);
   if (no_alloc) {
@@ -508,4 +620,63 @@ extern "C" aicdf_status mlmc_level_gbm_noalloc(const aicdf_gbm_params* prm, uint
   if (!sums_dev) return fail(AICDF_EINVAL, "sums_dev must be non-NULL");
   return gbm_level(prm, level, n_paths, kind, approx, seed, path_offset, LevelOut{nullptr, sums_dev}, path_out,
                    stream, true);
+}
+
+extern "C" aicdf_status mlmc_levels_gbm(const aicdf_gbm_params* prm, const aicdf_level_job* jobs, uint32_t n_jobs,
+                                        const aicdf_table* approx, uint64_t seed, double* sums_dev, void* stream) {
+  aicdf_status st = check_gbm_params(prm);
+  if (st != AICDF_OK) return st;
+  if (n_jobs == 0) return ok();
+  if (!jobs || !sums_dev) return fail(AICDF_EINVAL, "jobs and sums_dev must be non-NULL");
+  if (n_jobs > uint32_t(kMaxJobs)) return fail(AICDF_ERANGE, "%u jobs > %d", n_jobs, kMaxJobs);
+  if (reinterpret_cast<uintptr_t>(sums_dev) & 7u) return fail(AICDF_EINVAL, "sums_dev must be 8-byte aligned");
+  int dev = 0;
+  AICDF_HIP(hipGetDevice(&dev));
+  GbmBatch b{};
+  JobSpans sp{};
+  b.n_jobs = sp.n_jobs = n_jobs;
+  bool any_exact = false, any_approx = false, any_corr = false;
+  int tab = -1;
+  size_t lds = 0;
+  uint32_t total = 0;
+  for (uint32_t j = 0; j < n_jobs; ++j) {
+    const aicdf_level_job& jb = jobs[j];
+    int t = 0;
+    size_t l = 0;
+    unsigned g = 0;
+    st = setup_gbm(prm, jb.level, jb.n_paths, jb.kind, approx, seed, jb.path_offset, dev, b.job[j], t, l, g);
+    if (st != AICDF_OK) {
+      const std::string msg = aicdf_last_error();
+      return fail(st, "job %u: %s", j, msg.c_str());
+    }
+    if (jb.n_paths == 0) g = 0;
+    if (jb.kind != AICDF_KIND_EXACT) {
+      tab = t;
+      lds = l;
+    }
+    any_exact |= jb.kind == AICDF_KIND_EXACT;
+    any_approx |= jb.kind == AICDF_KIND_APPROX;
+    any_corr |= jb.kind == AICDF_KIND_CORRECTION;
+    sp.start[j] = b.start[j] = total;
+    sp.n_paths[j] = double(jb.n_paths);
+    total += g;
+  }
+  sp.start[n_jobs] = b.start[n_jobs] = total;
+  auto s = static_cast<hipStream_t>(stream);
+  Workspace* ws = nullptr;
+  st = get_workspace(s, &ws);
+  if (st != AICDF_OK) return st;
+  std::lock_guard<std::mutex> lock(ws->mu);
+  st = get_batch_buffers(ws);
+  if (st != AICDF_OK) return st;
+  if (total > 0) {
+    if (!any_approx && !any_corr)
+      launch_batch<0>(prm->scheme, prm->payoff, 0, b, total, 0, s, ws->batch_partials);
+    else if (!any_exact && !any_corr)
+      launch_batch<1>(prm->scheme, prm->payoff, tab, b, total, lds, s, ws->batch_partials);
+    else
+      launch_batch<2>(prm->scheme, prm->payoff, tab, b, total, lds, s, ws->batch_partials);
+    AICDF_HIP(hipGetLastError());
+  }
+  return reduce_batch(ws->batch_partials, sp, nullptr, sums_dev, s);
 }

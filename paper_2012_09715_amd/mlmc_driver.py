@@ -62,6 +62,19 @@ def level_call_async(model, params, level, n, kind, approx, seed, offset, sums):
     return A.mlmc_level_cir_async(params, level, n, kind, approx, seed, offset, sums)
 
 
+def batch_supported(model, approx):
+    return model == "gbm"
+
+
+def level_batch(model, params, jobs, approx, seed, sums):
+    """All (level, kind, n_paths, path_offset) jobs of one estimator in one
+    launch of the level kernel and one final pass (stream-ordered, current
+    stream); row j of `sums` receives job j's 8 sums."""
+    if model == "gbm":
+        return A.mlmc_levels_gbm(params, jobs, approx, seed, sums)
+    raise NotImplementedError("level-batched calls for this model")
+
+
 class Acc:
     """Running totals of one (level, kind) over several calls."""
 
@@ -269,6 +282,36 @@ def run_estimators(model, params, L, eps, approx, seed, accs, alloc, lats=None, 
             ref = calls[lk][2]
             same = (same and r["n"] == ref["n"] and r["sum"] == ref["sum"] and r["sum_pf"] == ref["sum_pf"]
                     and r["sum_pc"] == ref["sum_pc"] and r["fallbacks"] == ref["fallbacks"])
+    # the same calls once more, each estimator as ONE batched call (one level
+    # launch and one final pass), timed by events on the stream
+    if batch_supported(model, approx):
+        stream = torch.cuda.current_stream()
+        bsums = torch.zeros((A.MAX_JOBS, 8), dtype=torch.float64, device="cuda")
+        level_batch(model, params, [(0, A.KIND_EXACT, 2, 0)], approx, seed, bsums)  # warm: workspace buffers
+        torch.cuda.synchronize()
+        dev_ms = {}
+        bsame = True
+        for name, kinds in (("hat", (A.KIND_EXACT,)), ("tilde", (A.KIND_APPROX, A.KIND_CORRECTION))):
+            keys = [(l, k) for l in range(L + 1) for k in kinds]
+            est = {lk: max(calls[lk][0] * cost[lk[1]][lk[0]], lats[lk[0]][lk[1]] if lats else 0.0) for lk in keys}
+            keys.sort(key=lambda lk: -est[lk])
+            jobs = [(lk[0], lk[1], calls[lk][0], calls[lk][1]) for lk in keys]
+            times = []
+            for rep in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                level_batch(model, params, jobs, approx, seed, bsums)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+            dev_ms[name] = min(times)
+            host = bsums.cpu()
+            for j, lk in enumerate(keys):
+                r, ref = A.sums_dict(host[j]), calls[lk][2]
+                bsame = (bsame and r["n"] == ref["n"] and r["sum"] == ref["sum"] and r["sum_pf"] == ref["sum_pf"]
+                         and r["sum_pc"] == ref["sum_pc"])
+        out.update(device_ms_hat_batched=dev_ms["hat"], device_ms_tilde_batched=dev_ms["tilde"],
+                   measured_speedup_batched=dev_ms["hat"] / dev_ms["tilde"], batched_sums_identical=bool(bsame))
     theta_hat = sum(runs[l][A.KIND_EXACT].mean for l in range(L + 1))
     var_hat = sum(runs[l][A.KIND_EXACT].var / runs[l][A.KIND_EXACT].n for l in range(L + 1))
     theta_tilde = sum(runs[l][A.KIND_APPROX].mean + runs[l][A.KIND_CORRECTION].mean for l in range(L + 1))
@@ -374,8 +417,85 @@ def variance_study(params=FIG4B_PARAMS, levels=range(0, 9), n=1 << 16, seed=4242
     return out
 
 
+GBM_X = dict(S0=1.0, r=0.05, sigma=0.2, T=1.0, K=1.0, scheme=0, payoff=0)
+
+
+def fig3_tables():
+    """The approximations of Section 4.1's variance study (Figure 3, Table 3):
+    Rademacher variables, the 1024-interval constant table, and the 16-row
+    linear and cubic dyadic tables (FP32 coefficients)."""
+    return {"rademacher": A.Table.rademacher(), "const1024": A.Table.const(1024, 0),
+            "linear16": A.Table.dyadic(16, 1), "cubic16": A.Table.dyadic(16, 3)}
+
+
+def fig3_study(levels=range(0, 11), n=1 << 20, seed=3030):
+    """Figure 3 on the device: GBM with P = X_T, Euler-Maruyama and Milstein;
+    per level the two-way variance v^_l = Var(P^_l - P^_(l-1)) (exact
+    normals) and the four-way variance V~_l = Var(D_l) of the correction
+    kind for each approximation, n paths per level and kind.  Returns log2 of
+    both, and the Table 3 drop log2(V~_l / v^_l) averaged over the levels
+    l >= 1."""
+    tabs = fig3_tables()
+    out = {"paths": n, "levels": list(levels), "params": GBM_X}
+    for scheme, sname in ((0, "em"), (1, "milstein")):
+        p = dict(GBM_X, scheme=scheme)
+        var = lambda s: max(s["sum"][1] / s["n"] - (s["sum"][0] / s["n"]) ** 2, 1e-300)
+        vh = [var(A.mlmc_level_gbm(p, l, n, A.KIND_EXACT, None, seed + 17 * l)) for l in levels]
+        r = {"log2_v_hat": [math.log2(v) for v in vh], "log2_V4": {}, "drop": {}}
+        for j, (name, tab) in enumerate(tabs.items()):
+            v4 = [var(A.mlmc_level_gbm(p, l, n, A.KIND_CORRECTION, tab, seed + 1000 * (j + 1) + 17 * l))
+                  for l in levels]
+            r["log2_V4"][name] = [math.log2(v) for v in v4]
+            d = [math.log2(a / b) for a, b, l in zip(v4, vh, levels) if l >= 1]
+            r["drop"][name] = sum(d) / len(d)
+        out[sname] = r
+    return out
+
+
+def _sig(x, n=3):
+    if isinstance(x, float) and x != 0.0 and math.isfinite(x):
+        return float(f"{x:.{n}g}")
+    return x
+
+
+def compact(full):
+    """The benchmark's MLMC results in a compact form for the one-line JSON
+    record: per estimator the speed-ups, device times, estimates and, per
+    level, log2 of the variances v^_l, v~_l, V~_l, the costs c^_l, c~_l,
+    C~_l (ns per path) and the allocated path counts m^_l, m~_l, M~_l."""
+    out = {}
+    for key, r in full.items():
+        if key in ("surrogate", "fig4b", "fig4b_time_average"):
+            if key == "surrogate":
+                out[key] = {k: _sig(v) for k, v in r.items()}
+            else:
+                out[key] = {"log2_ratio": {k: [round(x, 2) for x in v] for k, v in r["log2_ratio"].items()}}
+            continue
+        if key == "fig3":
+            out[key] = {s: {"log2_v_hat": [round(x, 2) for x in r[s]["log2_v_hat"]],
+                            "log2_V4": {t: [round(x, 2) for x in v] for t, v in r[s]["log2_V4"].items()},
+                            "drop": {t: round(v, 2) for t, v in r[s]["drop"].items()}}
+                        for s in ("em", "milstein")}
+            out[key]["paths"] = r["paths"]
+            continue
+        c = {k: _sig(v) for k, v in _short(r).items()}
+        pl = r.get("per_level", [])
+        lg = lambda v: round(math.log2(v), 2) if v and v > 1e-299 else None
+        c["per_level"] = {
+            "log2_v_hat": [lg(p["v_hat"]) for p in pl], "log2_v2": [lg(p["v2"]) for p in pl],
+            "log2_v4": [lg(p["v4"]) for p in pl],
+            "c_hat_ns": [_sig(p["c_hat_ns"]) for p in pl], "c2_ns": [_sig(p["c2_ns"]) for p in pl],
+            "c4_ns": [_sig(p["c4_ns"]) for p in pl],
+            "m_hat": [math.ceil(p["m_hat"]) for p in pl], "m_tilde": [math.ceil(p["m_tilde"]) for p in pl],
+            "M_tilde": [math.ceil(p["M_tilde"]) for p in pl]}
+        out[key] = c
+    return out
+
+
 def _short(r):
-    keys = ("eps", "levels", "formula_speedup", "measured_speedup", "measured_speedup_concurrent", "T_hat_s",
+    keys = ("eps", "levels", "formula_speedup", "measured_speedup", "measured_speedup_concurrent",
+            "measured_speedup_batched", "device_ms_hat_batched", "device_ms_tilde_batched",
+            "batched_sums_identical", "T_hat_s",
             "T_tilde_s", "device_ms_hat", "device_ms_tilde", "wall_ms_hat_concurrent", "wall_ms_tilde_concurrent",
             "concurrent_sums_identical", "paths_hat", "paths_tilde", "theta_hat", "se_hat", "theta_tilde",
             "se_tilde", "fallbacks")
@@ -404,6 +524,13 @@ def bench_summary(log=print, seed=20201217, large_paths=1e8):
       cir_poly1_1e8 (levels 0..10, linear chi-squared table)."""
     res = {}
     lin16 = A.Table.dyadic(16, 1)
+    log("variance study (Figure 3, Table 3): GBM, P = X_T, Euler-Maruyama and Milstein, levels 0..10")
+    res["fig3"] = fig3_study()
+    for sch in ("em", "milstein"):
+        log(f"  {sch}: log2 v^_l " + " ".join(f"{x:6.2f}" for x in res["fig3"][sch]["log2_v_hat"]))
+        for k, v in res["fig3"][sch]["log2_V4"].items():
+            log(f"  {sch}: {k:10s} log2 V~_l " + " ".join(f"{x:6.2f}" for x in v)
+                + f"   drop {res['fig3'][sch]['drop'][k]:.2f}")
     log("mlmc: GBM Euler-Maruyama, levels 0..8")
     res["gbm_em"] = nested_mlmc("gbm", GBM_CALL, 8, 1e-3, lin16, seed)
     log(f"  formula speedup {res['gbm_em']['formula_speedup']:.3f}")

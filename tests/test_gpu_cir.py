@@ -165,6 +165,21 @@ def test_time_average_mean():
         s = A.mlmc_level_cir(p, level, n, 0, None, 40 + level)
         m = s["sum_pf"] / n
         assert abs(m - cir.mean_time_average(p, level)) < 5 * 0.05 / np.sqrt(n)
+    # v0 = 0.09 != theta: E v_t varies along the path, and the mean of the
+    # device's time average is the trapezoidal rule on E v_t (the oracle's
+    # closed form), 20 standard errors away from the plain mean over the nodes
+    p = dict(CIR, functional=1, v0=0.09)
+    n = 1 << 23
+    for level in (1, 2):
+        s = A.mlmc_level_cir(p, level, n, 0, None, 50 + level)
+        m = s["sum_pf"] / n
+        # sum_pf only: the standard error from the fine functional's spread
+        # (Y's second moment is that of P_f - P_c), bounded by 0.05 / sqrt(n)
+        se = 0.05 / np.sqrt(n)
+        trap = cir.mean_time_average(p, level)
+        plain = float(np.mean(cir.mean_v(p, np.linspace(0.0, 1.0, (1 << level) + 1))))
+        assert abs(m - trap) < 5 * se, (level, m, trap)
+        assert abs(m - plain) > 5 * se, (level, m, plain)
 
 
 def test_errors(damped):
@@ -243,3 +258,26 @@ def test_exact_kind_parity_long_paths():
     for got in (few, dense[pick]):
         for j in range(3):
             assert np.all(np.abs(got[:, j] - ref[j]) <= 1e-9 * scale), j
+
+
+def test_level10_paths_against_oracle(damped):
+    # the finest level of the large fused run: 1024 exact transitions per path,
+    # one path per wavefront, against the oracle's replay stored by
+    # tests/golden/make_level10_paths.py (exact kind, and the correction kind
+    # with this module's damped surrogate)
+    from tests.conftest import read_golden
+    s, _ = damped
+    p = dict(CIR, functional=1)
+    for case, seed, path, Y, Pf, Pc in read_golden("level10_paths.txt"):
+        kind = 0 if case == "exact" else 2
+        _, got = run(p, 10, 1, kind, None if kind == 0 else s, int(seed), int(path))
+        ref = np.array([float(Y), float(Pf), float(Pc)])
+        scale = max(abs(ref[1]), abs(ref[2]))
+        # P_f, P_c: the exact path, FP64 on both sides
+        assert np.all(np.abs(got[0, 1:] - ref[1:]) <= 1e-9 * scale), (case, got[0], ref)
+        # Y: exact for EXACT; CORRECTION subtracts the FP32 surrogate path's
+        # fine-minus-coarse difference, whose FP32 state errs by at most
+        # N eps32 of the path scale after N = 1024 steps, counted twice (the
+        # trapezoid weights of each functional sum to 1); 5e-10 measured
+        tolY = 1e-9 * scale if kind == 0 else 2 * 1024 * 2.0 ** -24 * scale
+        assert abs(got[0, 0] - ref[0]) <= tolY, (case, got[0], ref)

@@ -239,3 +239,30 @@ def test_config_size_sampled(lin16, scheme):
         ref = gbm.level_replay(p, level, kind, seed, pick, table=lin16[1])
         check_paths(got[pick], ref, kind, level)
         assert s["n"] == n
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_level10_milstein_wave_shape(lin16, kind):
+    # the finest level of the large fused run (1024 Milstein steps), a few
+    # paths in the one-path-per-wavefront shape, against the oracle's replay
+    p = dict(GBM, scheme=1, payoff=1)
+    level, seed, off = 10, 1010 + kind, 5_000_000
+    _, got = run_paths(p, level, 6, kind, lin16[0], seed, off)
+    ref = gbm.level_replay(p, level, kind, seed, off + np.arange(6), table=lin16[1])
+    check_paths(got, ref, kind, level)
+
+
+@pytest.mark.parametrize("level", [2, 3, 5, 7])
+def test_group_shapes(lin16, level):
+    # calls with paths x G <= 2^19 run one path per group of G = min(64, 2^l/2)
+    # lanes: against the oracle, and against one path per thread (a call too
+    # large for groups) to FP32 rounding
+    p = dict(GBM, scheme=1, payoff=1)
+    G = min(64, (1 << level) // 2)
+    for kind in (0, 1, 2):
+        seed = 300 + 10 * level + kind
+        _, few = run_paths(p, level, 100, kind, lin16[0], seed, 0)
+        ref = gbm.level_replay(p, level, kind, seed, np.arange(100), table=lin16[1])
+        check_paths(few, ref, kind, level)
+        _, dense = run_paths(p, level, (1 << 19) // G + 1, kind, lin16[0], seed, 0)
+        check_paths(dense[:100], ref, kind, level)
