@@ -419,6 +419,24 @@ typedef struct {
  * Errors: EINVAL, ERANGE, EDTYPE, EHIP, ENOMEM (an error in job j names it). */
 aicdf_status mlmc_levels_gbm(const aicdf_gbm_params* params, const aicdf_level_job* jobs, uint32_t n_jobs,
                              const aicdf_table* approx, uint64_t seed, double* sums_dev, void* stream);
+
+/* The approximate transition of a batched CIR call (approx argument). */
+#define AICDF_CIR_SURROGATE 0 /* const aicdf_surrogate*   (as mlmc_level_cir)          */
+#define AICDF_CIR_TABLE 1     /* const aicdf_chi2_table*  (as mlmc_level_cir_table)    */
+#define AICDF_CIR_EM 2        /* NULL                     (as mlmc_level_cir_em)       */
+#define AICDF_CIR_SANKARAN 3  /* NULL                     (as mlmc_level_cir_sankaran) */
+
+/* mlmc_levels_gbm for the CIR process (Section 5.2): every job of one
+ * estimator in ONE launch of the level kernel plus one final pass; each job
+ * runs on exactly the work-groups, launch shape and paths of its own
+ * stream-ordered level call with the chosen approximation, so its 8 sums
+ * (fallback count included) are bit-identical to that call's.  Kinds EXACT,
+ * APPROX and CORRECTION (the two-way kind is not batched).  Arguments,
+ * ordering advice, workspace and errors as for mlmc_levels_gbm; the
+ * approximation is checked against params as in the level calls. */
+aicdf_status mlmc_levels_cir(const aicdf_cir_params* params, const aicdf_level_job* jobs, uint32_t n_jobs,
+                             int32_t approx_type, const void* approx, uint64_t seed, double* sums_dev,
+                             void* stream);
 aicdf_status mlmc_level_cir_async(const aicdf_cir_params* params, uint32_t level, uint64_t n_paths,
                                   int32_t kind, const aicdf_surrogate* approx, uint64_t seed,
                                   uint64_t path_offset, double* sums_dev, double* path_out,

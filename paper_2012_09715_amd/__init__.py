@@ -301,6 +301,30 @@ def mlmc_levels_gbm(params, jobs, table, seed, sums, stream=None):
                               _batch_sums(sums, n), _stream(stream)))
 
 
+CIR_SURROGATE, CIR_TABLE, CIR_EM, CIR_SANKARAN = 0, 1, 2, 3
+
+
+def mlmc_levels_cir(params, jobs, approx, seed, sums, stream=None):
+    """Several CIR levels in one launch (stream-ordered): jobs as for
+    mlmc_levels_gbm; approx is a Surrogate, a Chi2Table, "em", "sankaran" or
+    None (EXACT jobs only)."""
+    p = _cir_params(params)
+    arr, n = _jobs(jobs)
+    if isinstance(approx, Surrogate):
+        t, h = CIR_SURROGATE, approx.handle
+    elif isinstance(approx, Chi2Table):
+        t, h = CIR_TABLE, approx.handle
+    elif approx == "em":
+        t, h = CIR_EM, None
+    elif approx == "sankaran":
+        t, h = CIR_SANKARAN, None
+    elif approx is None:
+        t, h = CIR_SURROGATE, None
+    else:
+        raise AicdfError(-1, f"unknown approximation {approx!r}")
+    check(lib.mlmc_levels_cir(C.byref(p), arr, n, t, h, seed, _batch_sums(sums, n), _stream(stream)))
+
+
 def mlmc_level_gbm_noalloc(params, level, n_paths, kind, table, seed, path_offset, sums, path_out=None,
                            stream=None):
     """mlmc_level_gbm_async without any allocation: the level's partial sums

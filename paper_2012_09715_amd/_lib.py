@@ -74,6 +74,7 @@ _PROTOS = {
     "mlmc_level_cir_sankaran": (status, [C.POINTER(CirParams), u32, u64, i32, u64, u64, C.POINTER(LevelSums), vp,
                                          vp]),
     "mlmc_level_gbm_async": (status, [C.POINTER(GbmParams), u32, u64, i32, vp, u64, u64, vp, vp, vp]),
+    "mlmc_levels_cir": (status, [C.POINTER(CirParams), C.POINTER(LevelJob), u32, i32, vp, u64, vp, vp]),
     "mlmc_levels_gbm": (status, [C.POINTER(GbmParams), C.POINTER(LevelJob), u32, vp, u64, vp, vp]),
     "mlmc_level_gbm_noalloc": (status, [C.POINTER(GbmParams), u32, u64, i32, vp, u64, u64, vp, vp, vp]),
     "mlmc_level_cir_async": (status, [C.POINTER(CirParams), u32, u64, i32, vp, u64, u64, vp, vp, vp]),

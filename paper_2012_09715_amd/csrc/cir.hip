@@ -38,6 +38,7 @@
 #include <cmath>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 
 #include "chi2_device.hpp"
@@ -162,13 +163,29 @@ __device__ __forceinline__ double exact_inverse(double u, double nu, double lam,
   return SPARSE ? ncx2_icdf_wave(u, nu, lam, x0) : ncx2_icdf(u, nu, lam, nullptr, x0);
 }
 
-template <int KIND, int FUNC, int APX, bool SPARSE>
-__global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const float* __restrict__ params,
-                                                               const uint16_t* __restrict__ w2b,
-                                                               const f32x4* __restrict__ wtab,
-                                                               double* __restrict__ partials,
-                                                               double* __restrict__ path_out,
-                                                               unsigned long long* __restrict__ fallbacks) {
+// Static LDS of a level work-group: the surrogate's staged parameters, the
+// per-wave exchange of the one-sample network call, W2 (one path per
+// wavefront only: W2 = true), the 16-row cubic table of the network's input
+// feature, and the block's fallback counts.
+template <bool W2>
+struct CirLds {
+  MlpLds L;
+  MlpXchg xch[kLevelBlock / 64];
+  __align__(16) uint16_t w2s[W2 ? kHidden * kW2Stride : 8];
+  f32x4 tab[16];
+  unsigned long long fbs[kLevelBlock];
+};
+
+// Work-group `bid` of the `nblk` work-groups of one level: its paths (a
+// grid-stride loop over nblk work-groups), their sums into partials[bid],
+// its fallbacks added to *fallbacks.  ctab: the dynamic LDS of the
+// chi-squared table (APX_POLY*).
+template <int KIND, int FUNC, int APX, bool SPARSE, bool W2>
+__device__ __forceinline__ void cir_level_block(const CirArgs& a, const float* __restrict__ params,
+                                                const uint16_t* __restrict__ w2b, const f32x4* __restrict__ wtab,
+                                                double* __restrict__ partials, double* __restrict__ path_out,
+                                                unsigned long long* __restrict__ fallbacks, uint32_t bid,
+                                                uint32_t nblk, CirLds<W2>& S, f32x4* __restrict__ ctab) {
   constexpr bool kExact = KIND != AICDF_KIND_APPROX;
   constexpr bool kApx = KIND != AICDF_KIND_EXACT;
   constexpr bool kSurr = kApx && APX == APX_SURROGATE;
@@ -176,11 +193,11 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
   constexpr bool kEm = kApx && APX == APX_EM;
   constexpr bool kSank = kApx && APX == APX_SANKARAN;
   constexpr bool kCall = !SPARSE && (kSurr || kEm || kSank);
-  __shared__ MlpLds L;
-  __shared__ MlpXchg xch[kLevelBlock / 64];  // SPARSE surrogate: one per wave
-  __shared__ __align__(16) uint16_t w2s[SPARSE && kSurr ? kHidden * kW2Stride : 8];  // SPARSE surrogate: W2
-  __shared__ f32x4 tab[16];
-  extern __shared__ f32x4 ctab[];  // APX_POLY*: the chi-squared table (dynamic LDS)
+  static_assert(!(SPARSE && kSurr) || W2, "one path per wavefront with the surrogate needs W2 in LDS");
+  MlpLds& L = S.L;
+  MlpXchg* xch = S.xch;
+  uint16_t* w2s = S.w2s;
+  f32x4* tab = S.tab;
   bf16x8 A[2][4];
   if (kSurr) {
     mlp_stage_params(L, params, threadIdx.x, kLevelBlock);
@@ -201,8 +218,7 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
   const uint32_t per_block = SPARSE ? kLevelBlock / 64 : kLevelBlock;
   const uint32_t slot = SPARSE ? threadIdx.x / 64 : threadIdx.x;
   const bool lead = SPARSE ? (threadIdx.x % 64) == 0 : true;
-  for (uint64_t base = uint64_t(blockIdx.x) * per_block; base < a.n_paths;
-       base += uint64_t(gridDim.x) * per_block) {
+  for (uint64_t base = uint64_t(bid) * per_block; base < a.n_paths; base += uint64_t(nblk) * per_block) {
     const uint64_t i = base + slot;
     const bool act = lead && i < a.n_paths;   // lanes that keep the sums
     const bool work = SPARSE ? i < a.n_paths : true;  // wave-uniform when SPARSE
@@ -306,28 +322,39 @@ __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const
       }
     }
   }
-  block_reduce_store(acc, partials);
+  block_reduce_store(acc, partials, bid);
   if (kSurr) {
-    __shared__ unsigned long long fbs[kLevelBlock];
-    fbs[threadIdx.x] = fb;
+    S.fbs[threadIdx.x] = fb;
     __syncthreads();
     if (threadIdx.x == 0) {
       unsigned long long t = 0;
-      for (int k = 0; k < kLevelBlock; ++k) t += fbs[k];
+      for (int k = 0; k < kLevelBlock; ++k) t += S.fbs[k];
       if (t) atomicAdd(fallbacks, t);
     }
   }
 }
 
+template <int KIND, int FUNC, int APX, bool SPARSE>
+__global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const float* __restrict__ params,
+                                                               const uint16_t* __restrict__ w2b,
+                                                               const f32x4* __restrict__ wtab,
+                                                               double* __restrict__ partials,
+                                                               double* __restrict__ path_out,
+                                                               unsigned long long* __restrict__ fallbacks) {
+  constexpr bool kW2 = SPARSE && KIND != AICDF_KIND_EXACT && APX == APX_SURROGATE;
+  __shared__ CirLds<kW2> S;
+  extern __shared__ f32x4 ctab[];  // APX_POLY*: the chi-squared table (dynamic LDS)
+  cir_level_block<KIND, FUNC, APX, SPARSE, kW2>(a, params, w2b, wtab, partials, path_out, fallbacks, blockIdx.x,
+                                                gridDim.x, S, ctab);
+}
+
 using LevelKernel = void (*)(CirArgs, const float*, const uint16_t*, const f32x4*, double*, double*,
                             unsigned long long*);
 
-// Chooses the launch shape (above), sets a.sparse and the grid, launches.
+// The launch shape (above) of a level: sets a.sparse and the work-group count.
 template <int KIND, int APX>
-aicdf_status launch_func(int func, CirArgs a, size_t lds, hipStream_t s, const float* p, const uint16_t* w2,
-                         const f32x4* wt, double* part, double* po, unsigned long long* fb, unsigned* grid) {
+aicdf_status choose_shape(int func, CirArgs& a, size_t lds, unsigned* grid) {
   const LevelKernel ks = func == 0 ? cir_level_kernel<KIND, 0, APX, true> : cir_level_kernel<KIND, 1, APX, true>;
-  const LevelKernel kd = func == 0 ? cir_level_kernel<KIND, 0, APX, false> : cir_level_kernel<KIND, 1, APX, false>;
   bool sparse = false;
   if (KIND != AICDF_KIND_APPROX && a.n_paths < kDenseAlways) {
     sparse = a.n_paths <= kSparseAlways;
@@ -343,8 +370,132 @@ aicdf_status launch_func(int func, CirArgs a, size_t lds, hipStream_t s, const f
   const uint64_t per_block = sparse ? kLevelBlock / 64 : kLevelBlock;
   const uint64_t need = (a.n_paths + per_block - 1) / per_block;
   *grid = unsigned(need < uint64_t(kMaxLevelBlocks) ? need : kMaxLevelBlocks);
-  hipLaunchKernelGGL(sparse ? ks : kd, dim3(*grid), dim3(kLevelBlock), lds, s, a, p, w2, wt, part, po, fb);
   return AICDF_OK;
+}
+
+// Chooses the launch shape, sets a.sparse and the grid, launches.
+template <int KIND, int APX>
+aicdf_status launch_func(int func, CirArgs a, size_t lds, hipStream_t s, const float* p, const uint16_t* w2,
+                         const f32x4* wt, double* part, double* po, unsigned long long* fb, unsigned* grid) {
+  const LevelKernel ks = func == 0 ? cir_level_kernel<KIND, 0, APX, true> : cir_level_kernel<KIND, 1, APX, true>;
+  const LevelKernel kd = func == 0 ? cir_level_kernel<KIND, 0, APX, false> : cir_level_kernel<KIND, 1, APX, false>;
+  aicdf_status st = choose_shape<KIND, APX>(func, a, lds, grid);
+  if (st != AICDF_OK) return st;
+  hipLaunchKernelGGL(a.sparse ? ks : kd, dim3(*grid), dim3(kLevelBlock), lds, s, a, p, w2, wt, part, po, fb);
+  return AICDF_OK;
+}
+
+// The shape of a level of any kind (the exact kind's kernel does not depend
+// on the approximation: it is the APX_SURROGATE instance).
+template <int APX>
+aicdf_status choose_shape_kind(int kind, int func, CirArgs& a, size_t lds, unsigned* grid) {
+  if (kind == AICDF_KIND_EXACT) return choose_shape<AICDF_KIND_EXACT, APX_SURROGATE>(func, a, 0, grid);
+  if (kind == AICDF_KIND_APPROX) return choose_shape<AICDF_KIND_APPROX, APX>(func, a, lds, grid);
+  return choose_shape<AICDF_KIND_CORRECTION, APX>(func, a, lds, grid);
+}
+
+// The per-level arguments of one job of a batched call; the rest of CirArgs
+// is common to the batch.
+struct CirJob {
+  double c, decay;
+  float cf, decayf, kdt, xi_sqdt;
+  uint32_t level, nsteps, tag, sparse;
+  uint64_t n_paths, path_offset;
+};
+
+struct CirBatch {
+  CirArgs base;
+  CirJob job[kMaxJobs];
+  uint32_t start[kMaxJobs + 1];
+  uint32_t n_jobs;
+};
+// kernel arguments are limited to 4 KiB (with the pointers that follow)
+static_assert(sizeof(CirBatch) + 64 <= 4096, "batched CIR arguments exceed the kernel argument limit");
+
+// KSET 0: EXACT jobs only; 1: APPROX jobs only; 2: EXACT, APPROX and
+// CORRECTION jobs.  Each work-group finds its job and runs that job's level
+// code on its share of the job's paths; fallbacks: one counter per job.
+template <int KSET, int FUNC, int APX>
+__global__ __launch_bounds__(kLevelBlock) void cir_levels_kernel(CirBatch b, const float* __restrict__ params,
+                                                                const uint16_t* __restrict__ w2b,
+                                                                const f32x4* __restrict__ wtab,
+                                                                double* __restrict__ partials,
+                                                                unsigned long long* __restrict__ fallbacks) {
+  constexpr bool kW2 = KSET != 0 && APX == APX_SURROGATE;
+  __shared__ CirLds<kW2> S;
+  extern __shared__ f32x4 ctab[];
+  uint32_t j = 0;
+  while (j + 1 < b.n_jobs && blockIdx.x >= b.start[j + 1]) ++j;
+  CirArgs a = b.base;
+  const CirJob& jb = b.job[j];
+  a.c = jb.c;
+  a.decay = jb.decay;
+  a.cf = jb.cf;
+  a.decayf = jb.decayf;
+  a.kdt = jb.kdt;
+  a.xi_sqdt = jb.xi_sqdt;
+  a.level = jb.level;
+  a.nsteps = jb.nsteps;
+  a.tag = jb.tag;
+  a.sparse = jb.sparse;
+  a.n_paths = jb.n_paths;
+  a.path_offset = jb.path_offset;
+  const uint32_t bid = blockIdx.x - b.start[j], nblk = b.start[j + 1] - b.start[j];
+  double* part = partials + size_t(b.start[j]) * kSums;
+  unsigned long long* fb = fallbacks + j;
+  const int kind = int(a.tag >> 8) - 4;
+  if constexpr (KSET == 0) {
+    if (a.sparse)
+      cir_level_block<AICDF_KIND_EXACT, FUNC, APX, true, kW2>(a, params, w2b, wtab, part, nullptr, fb, bid, nblk, S,
+                                                              ctab);
+    else
+      cir_level_block<AICDF_KIND_EXACT, FUNC, APX, false, kW2>(a, params, w2b, wtab, part, nullptr, fb, bid, nblk,
+                                                               S, ctab);
+  } else {
+    if (KSET == 1 || kind == AICDF_KIND_APPROX) {
+      // the approximate kind always runs one path per thread
+      cir_level_block<AICDF_KIND_APPROX, FUNC, APX, false, kW2>(a, params, w2b, wtab, part, nullptr, fb, bid, nblk,
+                                                                S, ctab);
+    } else if constexpr (KSET == 2) {
+      if (kind == AICDF_KIND_CORRECTION) {
+        if (a.sparse)
+          cir_level_block<AICDF_KIND_CORRECTION, FUNC, APX, true, kW2>(a, params, w2b, wtab, part, nullptr, fb, bid,
+                                                                       nblk, S, ctab);
+        else
+          cir_level_block<AICDF_KIND_CORRECTION, FUNC, APX, false, kW2>(a, params, w2b, wtab, part, nullptr, fb, bid,
+                                                                        nblk, S, ctab);
+      } else {
+        if (a.sparse)
+          cir_level_block<AICDF_KIND_EXACT, FUNC, APX, true, kW2>(a, params, w2b, wtab, part, nullptr, fb, bid, nblk,
+                                                                  S, ctab);
+        else
+          cir_level_block<AICDF_KIND_EXACT, FUNC, APX, false, kW2>(a, params, w2b, wtab, part, nullptr, fb, bid,
+                                                                   nblk, S, ctab);
+      }
+    }
+  }
+}
+
+template <int KSET, int APX>
+void launch_cir_batch(int func, const CirBatch& b, unsigned grid, size_t lds, hipStream_t s, const float* p,
+                      const uint16_t* w2, const f32x4* wt, double* part, unsigned long long* fb) {
+  if (func == 0)
+    hipLaunchKernelGGL((cir_levels_kernel<KSET, 0, APX>), dim3(grid), dim3(kLevelBlock), lds, s, b, p, w2, wt, part,
+                       fb);
+  else
+    hipLaunchKernelGGL((cir_levels_kernel<KSET, 1, APX>), dim3(grid), dim3(kLevelBlock), lds, s, b, p, w2, wt, part,
+                       fb);
+}
+
+template <int APX>
+void launch_cir_batch_kset(int kset, int func, const CirBatch& b, unsigned grid, size_t lds, hipStream_t s,
+                           const float* p, const uint16_t* w2, const f32x4* wt, double* part, unsigned long long* fb) {
+  if (kset == 0)
+    launch_cir_batch<0, APX_SURROGATE>(func, b, grid, 0, s, p, w2, wt, part, fb);
+  else if (kset == 1)
+    launch_cir_batch<1, APX>(func, b, grid, lds, s, p, w2, wt, part, fb);
+  else
+    launch_cir_batch<2, APX>(func, b, grid, lds, s, p, w2, wt, part, fb);
 }
 
 template <int APX>
@@ -528,7 +679,138 @@ aicdf_status cir_level_sankaran(const aicdf_cir_params* prm, uint32_t level, uin
   return finish_level(ws, grid, s, double(n_paths), out);
 }
 
+template <int APX>
+aicdf_status cir_batch_apx(const aicdf_cir_params* prm, const aicdf_level_job* jobs, uint32_t n_jobs,
+                           const CirArgs& common, size_t lds, uint64_t seed, double* sums_dev, hipStream_t s,
+                           const float* p, const uint16_t* w2, const f32x4* wt) {
+  CirBatch b{};
+  JobSpans sp{};
+  b.n_jobs = sp.n_jobs = n_jobs;
+  bool any_exact = false, any_approx = false, any_corr = false;
+  uint32_t total = 0;
+  for (uint32_t j = 0; j < n_jobs; ++j) {
+    const aicdf_level_job& jb = jobs[j];
+    CirArgs a;
+    aicdf_status st = cir_setup(prm, jb.level, jb.n_paths, jb.kind, seed, jb.path_offset,
+                                LevelOut{nullptr, sums_dev}, a);
+    if (st == AICDF_OK && jb.kind == KIND_TWOWAY) st = fail(AICDF_EINVAL, "the two-way kind is not batched");
+    unsigned g = 0;
+    if (st == AICDF_OK && jb.n_paths > 0) {
+      a.lo = common.lo;
+      a.hi = common.hi;
+      a.inv_span2 = common.inv_span2;
+      a.geo = common.geo;
+      a.table_rows = common.table_rows;
+      st = choose_shape_kind<APX>(jb.kind, prm->functional, a, lds, &g);
+    }
+    if (st != AICDF_OK) {
+      const std::string msg = aicdf_last_error();
+      return fail(st, "job %u: %s", j, msg.c_str());
+    }
+    if (j == 0) {
+      b.base = a;
+      b.base.lo = common.lo;
+      b.base.hi = common.hi;
+      b.base.inv_span2 = common.inv_span2;
+      b.base.geo = common.geo;
+      b.base.table_rows = common.table_rows;
+    }
+    b.job[j] = CirJob{a.c, a.decay, a.cf, a.decayf, a.kdt, a.xi_sqdt, a.level, a.nsteps, a.tag, a.sparse,
+                      a.n_paths, a.path_offset};
+    any_exact |= jb.kind == AICDF_KIND_EXACT;
+    any_approx |= jb.kind == AICDF_KIND_APPROX;
+    any_corr |= jb.kind == AICDF_KIND_CORRECTION;
+    sp.start[j] = b.start[j] = total;
+    sp.n_paths[j] = double(jb.n_paths);
+    total += g;
+  }
+  sp.start[n_jobs] = b.start[n_jobs] = total;
+  Workspace* ws = nullptr;
+  aicdf_status st = get_workspace(s, &ws);
+  if (st != AICDF_OK) return st;
+  std::lock_guard<std::mutex> lock(ws->mu);
+  st = get_batch_buffers(ws);
+  if (st != AICDF_OK) return st;
+  if (total > 0) {
+    const int kset = (!any_approx && !any_corr) ? 0 : (!any_exact && !any_corr) ? 1 : 2;
+    launch_cir_batch_kset<APX>(kset, prm->functional, b, total, lds, s, p, w2, wt, ws->batch_partials,
+                               ws->batch_counters);
+    AICDF_HIP(hipGetLastError());
+  }
+  return reduce_batch(ws->batch_partials, sp, ws->batch_counters, sums_dev, s);
+}
+
+aicdf_status cir_batch(const aicdf_cir_params* prm, const aicdf_level_job* jobs, uint32_t n_jobs, int32_t apx,
+                       const void* approx, uint64_t seed, double* sums_dev, void* stream) {
+  if (!prm) return fail(AICDF_EINVAL, "params must be non-NULL");
+  if (n_jobs == 0) return ok();
+  if (!jobs || !sums_dev) return fail(AICDF_EINVAL, "jobs and sums_dev must be non-NULL");
+  if (n_jobs > uint32_t(kMaxJobs)) return fail(AICDF_ERANGE, "%u jobs > %d", n_jobs, kMaxJobs);
+  if (reinterpret_cast<uintptr_t>(sums_dev) & 7u) return fail(AICDF_EINVAL, "sums_dev must be 8-byte aligned");
+  if (apx < AICDF_CIR_SURROGATE || apx > AICDF_CIR_SANKARAN) return fail(AICDF_EINVAL, "unknown approximation %d", apx);
+  bool any_apx = false;
+  for (uint32_t j = 0; j < n_jobs; ++j) any_apx |= jobs[j].kind != AICDF_KIND_EXACT;
+  if (any_apx && !approx && (apx == AICDF_CIR_SURROGATE || apx == AICDF_CIR_TABLE))
+    return fail(AICDF_EINVAL, "the approximate kinds need a surrogate or table");
+  int dev = 0;
+  AICDF_HIP(hipGetDevice(&dev));
+  const double nu = 4.0 * prm->kappa * prm->theta / (prm->xi * prm->xi);
+  auto s = static_cast<hipStream_t>(stream);
+  CirArgs common{};
+  if (apx == AICDF_CIR_SURROGATE) {
+    const auto* sur = static_cast<const aicdf_surrogate*>(approx);
+    double snu = nu, lo = 0.0, hi = 0.0;
+    int sdev = dev;
+    if (sur) {
+      surrogate_range(sur, &snu, &lo, &hi, &sdev);
+      if (any_apx && sdev != dev)
+        return fail(AICDF_EINVAL, "surrogate lives on device %d, current device is %d", sdev, dev);
+      if (any_apx && std::fabs(snu - nu) > 1e-12 * nu)
+        return fail(AICDF_EINVAL, "surrogate was built for nu = %.17g, the process has nu = %.17g", snu, nu);
+    }
+    common.lo = float(lo);
+    common.hi = float(hi);
+    common.inv_span2 = sur ? float(2.0 / (hi - lo)) : 0.0f;
+    const float* p = sur ? surrogate_params(sur) : nullptr;
+    const uint16_t* w2 = sur ? surrogate_w2b(sur) : nullptr;
+    const f32x4* wt = sur ? reinterpret_cast<const f32x4*>(surrogate_wtab(sur)) : nullptr;
+    return cir_batch_apx<APX_SURROGATE>(prm, jobs, n_jobs, common, 0, seed, sums_dev, s, p, w2, wt);
+  }
+  if (apx == AICDF_CIR_TABLE) {
+    const auto* tab = static_cast<const aicdf_chi2_table*>(approx);
+    Chi2Info ti{};
+    size_t lds = 0;
+    if (tab) {
+      ti = chi2_info(tab);
+      if (any_apx && ti.device != dev)
+        return fail(AICDF_EINVAL, "table lives on device %d, current device is %d", ti.device, dev);
+      if (any_apx && std::fabs(ti.nu - nu) > 1e-12 * nu)
+        return fail(AICDF_EINVAL, "table was built for nu = %.17g, the process has nu = %.17g", ti.nu, nu);
+      common.geo = Chi2Geom{float(ti.nu), float(std::sqrt(ti.nu)), float(ti.n_knots - 1), ti.n_knots - 2,
+                            ti.n_intervals};
+      common.table_rows = ti.n_knots * 2 * ti.n_intervals;
+      if (common.table_rows > kMaxLdsRows)
+        return fail(AICDF_EINVAL, "table has %u rows; the CIR level stages at most %u in LDS", common.table_rows,
+                    kMaxLdsRows);
+      lds = size_t(common.table_rows) * sizeof(f32x4);
+    }
+    const auto* wt = static_cast<const f32x4*>(ti.dev_rows);
+    if (!tab || ti.degree == 1)
+      return cir_batch_apx<APX_POLY1>(prm, jobs, n_jobs, common, lds, seed, sums_dev, s, nullptr, nullptr, wt);
+    return cir_batch_apx<APX_POLY3>(prm, jobs, n_jobs, common, lds, seed, sums_dev, s, nullptr, nullptr, wt);
+  }
+  if (apx == AICDF_CIR_EM)
+    return cir_batch_apx<APX_EM>(prm, jobs, n_jobs, common, 0, seed, sums_dev, s, nullptr, nullptr, nullptr);
+  return cir_batch_apx<APX_SANKARAN>(prm, jobs, n_jobs, common, 0, seed, sums_dev, s, nullptr, nullptr, nullptr);
+}
+
 }  // namespace
+
+extern "C" aicdf_status mlmc_levels_cir(const aicdf_cir_params* prm, const aicdf_level_job* jobs, uint32_t n_jobs,
+                                        int32_t approx_type, const void* approx, uint64_t seed, double* sums_dev,
+                                        void* stream) {
+  return cir_batch(prm, jobs, n_jobs, approx_type, approx, seed, sums_dev, stream);
+}
 
 extern "C" aicdf_status mlmc_level_cir(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths, int32_t kind,
                                        const aicdf_surrogate* sur, uint64_t seed, uint64_t path_offset,

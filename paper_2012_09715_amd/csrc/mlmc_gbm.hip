@@ -368,6 +368,8 @@ struct GbmBatch {
   uint32_t start[kMaxJobs + 1];
   uint32_t n_jobs;
 };
+// kernel arguments are limited to 4 KiB (with the pointer that follows)
+static_assert(sizeof(GbmBatch) + 64 <= 4096, "batched GBM arguments exceed the kernel argument limit");
 
 // KSET 0: EXACT jobs only; 1: APPROX jobs only; 2: any kinds.  Each
 // work-group finds its job (a wave-uniform scan of at most kMaxJobs spans)

@@ -63,7 +63,7 @@ def level_call_async(model, params, level, n, kind, approx, seed, offset, sums):
 
 
 def batch_supported(model, approx):
-    return model == "gbm"
+    return True
 
 
 def level_batch(model, params, jobs, approx, seed, sums):
@@ -72,7 +72,7 @@ def level_batch(model, params, jobs, approx, seed, sums):
     stream); row j of `sums` receives job j's 8 sums."""
     if model == "gbm":
         return A.mlmc_levels_gbm(params, jobs, approx, seed, sums)
-    raise NotImplementedError("level-batched calls for this model")
+    return A.mlmc_levels_cir(params, jobs, approx, seed, sums)
 
 
 class Acc:
@@ -245,7 +245,7 @@ def run_async(jobs, costs, n_streams=4):
     return [A.sums_dict(host[i]) for i in range(len(jobs))], wall
 
 
-def run_estimators(model, params, L, eps, approx, seed, accs, alloc, lats=None, n_streams=4):
+def run_estimators(model, params, L, eps, approx, seed, accs, alloc, lats=None, n_streams=4, split_kinds=None):
     """Runs the allocated path counts on fresh paths of every stream (the
     pilot paths are not reused, so the estimate is independent of the
     allocation) and returns the two estimators, their standard errors and
@@ -296,21 +296,41 @@ def run_estimators(model, params, L, eps, approx, seed, accs, alloc, lats=None, 
             est = {lk: max(calls[lk][0] * cost[lk[1]][lk[0]], lats[lk[0]][lk[1]] if lats else 0.0) for lk in keys}
             keys.sort(key=lambda lk: -est[lk])
             jobs = [(lk[0], lk[1], calls[lk][0], calls[lk][1]) for lk in keys]
+            # the nested estimator's APPROX jobs (light kernels, high occupancy)
+            # and CORRECTION jobs (exact inverses, many registers) either share
+            # one launch or take one each (split_kinds)
+            groups = [jobs]
+            split = split_kinds
+            if split is None:
+                # one launch per kind once the estimator's work (at full
+                # throughput) exceeds the launch floor of ~50 us; below it one
+                # launch for both kinds
+                split = sum(calls[lk][0] * cost[lk[1]][lk[0]] for lk in keys) > 5e-5
+            if split and len(kinds) > 1:
+                groups = [[j for j in jobs if j[1] == k] for k in kinds]
             times = []
             for rep in range(3):
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
-                level_batch(model, params, jobs, approx, seed, bsums)
+                row = 0
+                for g in groups:
+                    level_batch(model, params, g, approx, seed, bsums[row:row + len(g)])
+                    row += len(g)
                 e1.record(stream)
                 torch.cuda.synchronize()
                 times.append(e0.elapsed_time(e1))
+            jobs = [j for g in groups for j in g]
+            keys = [(j[0], j[1]) for j in jobs]
+            if name == "tilde":
+                n_launch_tilde = len(groups)
             dev_ms[name] = min(times)
             host = bsums.cpu()
             for j, lk in enumerate(keys):
                 r, ref = A.sums_dict(host[j]), calls[lk][2]
                 bsame = (bsame and r["n"] == ref["n"] and r["sum"] == ref["sum"] and r["sum_pf"] == ref["sum_pf"]
                          and r["sum_pc"] == ref["sum_pc"])
-        out.update(device_ms_hat_batched=dev_ms["hat"], device_ms_tilde_batched=dev_ms["tilde"],
+        out.update(batched_launches={"hat": 1, "tilde": n_launch_tilde},
+                   device_ms_hat_batched=dev_ms["hat"], device_ms_tilde_batched=dev_ms["tilde"],
                    measured_speedup_batched=dev_ms["hat"] / dev_ms["tilde"], batched_sums_identical=bool(bsame))
     theta_hat = sum(runs[l][A.KIND_EXACT].mean for l in range(L + 1))
     var_hat = sum(runs[l][A.KIND_EXACT].var / runs[l][A.KIND_EXACT].n for l in range(L + 1))
@@ -332,7 +352,8 @@ def run_estimators(model, params, L, eps, approx, seed, accs, alloc, lats=None, 
     return out
 
 
-def nested_mlmc(model, params, L, eps, approx, seed, n_pilot=1 << 16, steps_budget=1 << 26, target_paths=None):
+def nested_mlmc(model, params, L, eps, approx, seed, n_pilot=1 << 16, steps_budget=1 << 26, target_paths=None,
+                split_kinds=None):
     """Pilot, allocate and run both estimators.  With target_paths, eps is
     lowered so that the regular estimator allocates about that many paths in
     total (the allocation scales as eps^-2)."""
@@ -341,7 +362,7 @@ def nested_mlmc(model, params, L, eps, approx, seed, n_pilot=1 << 16, steps_budg
     if target_paths:
         eps = eps * math.sqrt(sum(alloc["m_hat"]) / target_paths)
         alloc = allocate(eps, accs, costs)
-    est = run_estimators(model, params, L, eps, approx, seed, accs, alloc, lats)
+    est = run_estimators(model, params, L, eps, approx, seed, accs, alloc, lats, split_kinds=split_kinds)
     per_level = []
     for l in range(L + 1):
         per_level.append({
@@ -495,7 +516,7 @@ def compact(full):
 def _short(r):
     keys = ("eps", "levels", "formula_speedup", "measured_speedup", "measured_speedup_concurrent",
             "measured_speedup_batched", "device_ms_hat_batched", "device_ms_tilde_batched",
-            "batched_sums_identical", "T_hat_s",
+            "batched_sums_identical", "batched_launches", "T_hat_s",
             "T_tilde_s", "device_ms_hat", "device_ms_tilde", "wall_ms_hat_concurrent", "wall_ms_tilde_concurrent",
             "concurrent_sums_identical", "paths_hat", "paths_tilde", "theta_hat", "se_hat", "theta_tilde",
             "se_tilde", "fallbacks")

@@ -74,3 +74,62 @@ def test_batch_errors():
         A.mlmc_levels_gbm(D.GBM_CALL, [(1, AP, 10, 0)], None, 1, out)
     with pytest.raises(A.AicdfError):
         A.mlmc_levels_gbm(D.GBM_CALL, [(1, E, 10, 0)] * 3, tab, 1, out[:2].reshape(-1)[:16].contiguous())
+
+
+# ------------------------------------------------------------------ CIR
+CIRP = dict(v0=0.04, kappa=0.5, theta=0.04, xi=0.3, T=1.0, functional=1)
+NU = 4 * 0.5 * 0.04 / 0.3 ** 2
+
+CIR_JOBS = {
+    "exact": [(6, E, 200, 0), (2, E, 3000, 5), (0, E, 150_000, 0), (4, E, 0, 0), (8, E, 2, 77)],
+    "approx": [(6, AP, 20_000, 0), (0, AP, 300_000, 3), (3, AP, 1, 0)],
+    "mixed": [(8, C, 2, 0), (6, C, 300, 0), (6, AP, 5000, 0), (0, C, 140_000, 9), (0, AP, 400_000, 0),
+              (3, E, 1000, 0), (2, C, 0, 0)],
+}
+
+
+def cir_level_async(params, level, n, kind, approx, seed, off, sums):
+    if isinstance(approx, A.Chi2Table):
+        return A.mlmc_level_cir_table_async(params, level, n, kind, approx, seed, off, sums)
+    if approx == "em":
+        return A.mlmc_level_cir_em_async(params, level, n, kind, seed, off, sums)
+    if approx == "sankaran":
+        return A.mlmc_level_cir_sankaran_async(params, level, n, kind, seed, off, sums)
+    return A.mlmc_level_cir_async(params, level, n, kind, approx, seed, off, sums)
+
+
+@pytest.fixture(scope="module")
+def cir_approxes():
+    return {"surrogate": A.Surrogate.create(NU, -8.0, 10.0, seed=3), "poly1": A.Chi2Table.create(NU, 1),
+            "poly3": A.Chi2Table.create(NU, 3), "em": "em", "sankaran": "sankaran"}
+
+
+@pytest.mark.parametrize("name", list(CIR_JOBS))
+@pytest.mark.parametrize("apx", ["surrogate", "poly1", "poly3", "em", "sankaran"])
+@pytest.mark.parametrize("functional", [0, 1])
+def test_cir_batch_equals_level_calls(cir_approxes, name, apx, functional):
+    if name == "exact" and apx != "surrogate":
+        pytest.skip("the exact kind does not depend on the approximation")
+    p = dict(CIRP, functional=functional)
+    approx = cir_approxes[apx]
+    jobs = CIR_JOBS[name]
+    ref = torch.zeros((len(jobs), 8), dtype=torch.float64, device="cuda")
+    for j, (level, kind, n, off) in enumerate(jobs):
+        cir_level_async(p, level, n, kind, approx, 555, off, ref[j])
+    got = torch.full((len(jobs), 8), -7.0, dtype=torch.float64, device="cuda")
+    A.mlmc_levels_cir(p, jobs, None if name == "exact" else approx, 555, got)
+    torch.cuda.synchronize()
+    assert torch.equal(got.cpu(), ref.cpu()), (got.cpu() - ref.cpu()).abs().max()
+
+
+def test_cir_batch_errors(cir_approxes):
+    out = torch.zeros((30, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(A.AicdfError, match="two-way"):
+        A.mlmc_levels_cir(CIRP, [(1, 3, 10, 0)], cir_approxes["poly1"], 1, out)
+    with pytest.raises(A.AicdfError, match="EINVAL"):
+        A.mlmc_levels_cir(CIRP, [(1, AP, 10, 0)], None, 1, out)
+    with pytest.raises(A.AicdfError, match="job 1"):
+        A.mlmc_levels_cir(CIRP, [(1, E, 10, 0), (13, E, 10, 0)], None, 1, out)
+    other = A.Chi2Table.create(2.0, 1)
+    with pytest.raises(A.AicdfError, match="nu"):
+        A.mlmc_levels_cir(CIRP, [(1, AP, 10, 0)], other, 1, out)
