@@ -246,7 +246,9 @@ typedef struct {
                          CORRECTION, approximate path for APPROX)            */
   double sum_pc;      /* sum of the coarse functional (0 at level 0)         */
   double kernel_ms;   /* device time of the level kernel, HIP events         */
-  uint64_t fallbacks; /* CIR surrogate steps routed to the exact inverse     */
+  uint64_t fallbacks; /* CIR surrogate steps outside the trained log-lambda
+                         range: above it routed to the exact inverse, below
+                         it (lambda = 0 included) evaluated at its lower end */
   uint64_t reserved;
 } aicdf_level_sums;
 
@@ -296,7 +298,9 @@ typedef struct aicdf_surrogate aicdf_surrogate;
  *               network is evaluated at the range's lower end (P depends on
  *               lambda only through O(lambda) terms there); steps whose
  *               log(lambda) lies above the range use the exact inverse on
- *               the same u24 (counted in out->fallbacks)
+ *               the same u24; both kinds of out-of-range step are counted in
+ *               out->fallbacks (the correction level removes the bias of
+ *               either)
  *   CORRECTION  both on two-word draws (surrogate on the u24 of the high word)
  *   TWOWAY      both on the draws of CORRECTION, fine paths only:
  *               Y = P^_f - P~_f, sum_pf over P^_f, sum_pc over P~_f

@@ -11,8 +11,8 @@
 //                  evaluated at the range's lower end: P depends on lambda
 //                  only through O(lambda) terms there, far below the
 //                  network's own error.  A lane whose log lambda lies above
-//                  the range takes the exact inverse on the same u24 instead
-//                  (counted).
+//                  the range takes the exact inverse on the same u24 instead.
+//                  Both are counted as fallbacks.
 //   APX_POLY1/3    Section 5.1's piecewise-polynomial approximation (two
 //                  dyadic half tables per knot, linear interpolation in
 //                  sqrt(y)), clamped at 0; the table is staged in LDS.
@@ -259,6 +259,7 @@ __device__ __forceinline__ void cir_level_block(const CirArgs& a, const float* _
         if (inr) {
           const float s = lam + a.nuf;
           x = fmaxf(fmaf(2.0f * sqrtf(s), Pt, s), 0.0f);
+          fb += (act && ll < a.lo) ? 1 : 0;  // below the range: counted, evaluated at its end
         } else {
           // (rare: behind a call in every shape)
           x = work ? float(exact_inverse<SPARSE, kCall>(double(u24), a.nu, double(lam), 0.0)) : 0.0f;

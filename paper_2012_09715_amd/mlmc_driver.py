@@ -486,7 +486,9 @@ def compact(full):
     C~_l (ns per path) and the allocated path counts m^_l, m~_l, M~_l."""
     out = {}
     for key, r in full.items():
-        if key in ("surrogate", "fig4b", "fig4b_time_average"):
+        if key == "fig4b_time_average":
+            continue  # in the detail file only
+        if key in ("surrogate", "fig4b"):
             if key == "surrogate":
                 out[key] = {k: _sig(v) for k, v in r.items()}
             else:
@@ -499,7 +501,10 @@ def compact(full):
                         for s in ("em", "milstein")}
             out[key]["paths"] = r["paths"]
             continue
-        c = {k: _sig(v) for k, v in _short(r).items()}
+        c = {k: _sig(v, 4 if k.startswith("theta") else 3) for k, v in _short(r).items() if k != "levels"}
+        if key not in ("gbm_em", "gbm_milstein_1e8", "cir", "cir_1e8"):
+            out[key] = c  # per-level figures for the configurations' estimators only
+            continue
         pl = r.get("per_level", [])
         lg = lambda v: round(math.log2(v), 2) if v and v > 1e-299 else None
         c["per_level"] = {
@@ -515,11 +520,9 @@ def compact(full):
 
 def _short(r):
     keys = ("eps", "levels", "formula_speedup", "measured_speedup", "measured_speedup_concurrent",
-            "measured_speedup_batched", "device_ms_hat_batched", "device_ms_tilde_batched",
-            "batched_sums_identical", "batched_launches", "T_hat_s",
-            "T_tilde_s", "device_ms_hat", "device_ms_tilde", "wall_ms_hat_concurrent", "wall_ms_tilde_concurrent",
-            "concurrent_sums_identical", "paths_hat", "paths_tilde", "theta_hat", "se_hat", "theta_tilde",
-            "se_tilde", "fallbacks")
+            "measured_speedup_batched", "device_ms_hat_batched", "device_ms_tilde_batched", "batched_launches",
+            "batched_sums_identical", "T_hat_s", "T_tilde_s", "paths_hat", "paths_tilde", "theta_hat", "se_hat",
+            "theta_tilde", "se_tilde", "fallbacks")
     return {k: r[k] for k in keys if k in r}
 
 

@@ -134,14 +134,41 @@ def test_split_determinism_and_fallbacks(damped):
     assert np.array_equal(c2, c[500:1500])
     st2 = A.mlmc_level_cir(p, 2, n1 + n2, 2, s, 5)
     assert st["sum"] == st2["sum"] and st["fallbacks"] == st2["fallbacks"]
-    # a surrogate whose range lies below every lambda falls back on every
-    # step; one whose range lies above every lambda never does (the network
-    # is evaluated at its lower end)
+    # a surrogate whose range lies below every lambda falls back to the
+    # exact inverse on every step; one whose range lies above every lambda
+    # evaluates the network at its lower end on every step: both counted
     low = A.Surrogate.create(NU, -60.0, -59.0, seed=2)
     sn = A.mlmc_level_cir(p, 2, 1000, 1, low, 5)
     assert sn["fallbacks"] == 1000 * 4
     high = A.Surrogate.create(NU, 50.0, 51.0, seed=2)
-    assert A.mlmc_level_cir(p, 2, 1000, 1, high, 5)["fallbacks"] == 0
+    assert A.mlmc_level_cir(p, 2, 1000, 1, high, 5)["fallbacks"] == 1000 * 4
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+def test_lambda_zero_paths(damped, kind):
+    # v0 = 0: the first step has lambda = 0, below the surrogate's range,
+    # where the network is evaluated at the range's lower end; such steps
+    # are counted.  Paths against the oracle's replay (which applies the same
+    # rule), and the count against the oracle's own count of surrogate
+    # steps with lambda < e^lo on the approximate path
+    s, q = damped
+    p = dict(CIR, v0=0.0, functional=1)
+    n, level, seed = 300, 2, 808 + kind
+    st, got = run(p, level, n, kind, s, seed)
+    f = oracle_surrogate_x(q)
+    count = [0]
+
+    def counting(u, lam):
+        count[0] += int(np.count_nonzero(np.asarray(lam, float) < np.exp(LO)))
+        return f(u, lam)
+
+    ref = cir.level_replay(p, level, kind, seed, np.arange(n), surrogate_x=counting)
+    scale = np.maximum(np.abs(ref[1]), 1e-3)
+    N = 1 << level
+    tol = 2e-4 * N * scale
+    for j in range(3):
+        assert np.all(np.abs(got[:, j] - ref[j]) <= tol), (j, np.max(np.abs(got[:, j] - ref[j]) / scale))
+    assert st["fallbacks"] == count[0] and count[0] >= n
 
 
 def test_exact_mean_and_variance():
@@ -216,14 +243,17 @@ def test_one_path_per_wavefront_surrogate_is_bit_exact(damped):
     # TWOWAY returns P_c = P~_f, the surrogate path alone: its network calls
     # spread one sample over a wavefront when the call runs one path per
     # wavefront, with the per-sample arithmetic of the 64-sample call, so
-    # the two launch shapes give the same bits (no fallbacks at these lambda)
+    # the two launch shapes give the same bits (lambda stays far below the
+    # range's upper end e^10 here, so no step takes the exact inverse; the
+    # steps counted as fallbacks lie below the range, lambda = 0 after a
+    # clamped step of this untrained network, and are evaluated by the
+    # network at its lower end in both shapes)
     s, _ = damped
     for functional, level in ((1, 2), (0, 3)):
         p = dict(CIR, functional=functional)
         n = (1 << 17) + 5
         st, dense = run(p, level, n, 3, s, 71)
         _, sparse = run(p, level, 300, 3, s, 71, 5000)
-        assert st["fallbacks"] == 0
         assert np.array_equal(sparse[:, 2], dense[5000:5300, 2])
         ok, worst = same_paths(sparse, dense[5000:5300])
         assert ok, worst
