@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-mlmc", action="store_true", help="skip the nested MLMC measurements")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
                     help="write the headline kernel's HBM traffic from two rocprofv3 --pmc counter files (no GPU)")
+    ap.add_argument("--profile-transforms", action="store_true",
+                    help="only one call each of four streaming transforms (for counters)")
     ap.add_argument("--profile-levels", action="store_true",
                     help="only one GPU-filling call of each fused level kernel and of the surrogate (for counters)")
     ap.add_argument("--detail", default=None, help="write the full per-level MLMC results to this JSON file")
@@ -404,6 +406,26 @@ def stored_traffic():
     return t.get("traffic_bytes_per_launch")
 
 
+def profile_transforms(A, torch):
+    """--profile-transforms: one call each (after one untimed call) of the
+    streaming transforms on 2^30 FP32 uniforms, for hardware counters: the
+    headline 16-row linear table to FP32, the same to FP16, the 32-row cubic
+    table to FP16 and the 1024-interval constant table to FP32."""
+    u = torch.empty(N_MAIN, dtype=torch.float32, device="cuda")
+    A.uniform_fill(u, SEED, 3, 0)
+    z = torch.empty(N_MAIN, dtype=torch.float32, device="cuda")
+    z16 = torch.empty(N_MAIN, dtype=torch.float16, device="cuda")
+    calls = [("dyadic16 d1 f32", lambda: A.approx_icdf_linear(A.Table.dyadic(16, 1), u, z=z)),
+             ("dyadic16 d1 f16", lambda: A.approx_icdf_linear(A.Table.dyadic(16, 1, torch.float16), u, z=z16)),
+             ("dyadic32 d3 f16", lambda: A.approx_icdf_linear(A.Table.dyadic(32, 3, torch.float16), u, z=z16)),
+             ("const1024 f32", lambda: A.approx_icdf_const(A.Table.const(1024), u, z=z))]
+    out = {}
+    for name, fn in calls:
+        out[name] = time_kernel(fn, 1, torch.cuda.current_stream())
+        log(f"{name}: {out[name]:.4f} ms")
+    return out
+
+
 def main():
     args = parse()
     if args.traffic_from:
@@ -422,6 +444,9 @@ def main():
     log(f"device: {torch.cuda.get_device_name(dev)}")
     if args.profile_levels:
         print(json.dumps({"profile_levels_ms": profile_levels(A, torch)}), flush=True)
+        return 0
+    if args.profile_transforms:
+        print(json.dumps({"profile_transforms_ms": profile_transforms(A, torch)}), flush=True)
         return 0
 
     # ---------------------------------------------------------- main workload
@@ -485,12 +510,23 @@ def main():
 
     # ---------------------------------------------------------- sweep
     sweep = []
-    reps = 5
+    reps = 10
+    # one 16-bit output buffer for every 16-bit variant (a fresh 2 GiB
+    # allocation per variant made the first variant timed on it slower)
+    z16 = torch.empty(N_MAIN, dtype=torch.float16, device=dev)
+    # the 16-bit-output transforms reach their steady rate only after some
+    # 20-30 ms of such launches (measured: the first 16-bit variant timed ran
+    # at 65-75 % of peak, the same kernel later at ~84 %), so they are warmed
+    # up before the sweep
+    warm16 = A.Table.dyadic(16, 1, torch.float16)
+    for _ in range(40):
+        A.approx_icdf_linear(warm16, u, z=z16)
+    torch.cuda.synchronize()
     for T in (8, 16, 32):
         for d in (1, 3):
             for cdt, name in ((torch.float32, "f32"), (torch.float16, "f16"), (torch.bfloat16, "bf16")):
                 t = A.Table.dyadic(T, d, cdt)
-                zo = torch.empty(N_MAIN, dtype=cdt, device=dev)
+                zo = z if cdt == torch.float32 else z16.view(cdt)
                 ms = time_kernel(lambda: A.approx_icdf_linear(t, u, z=zo), reps, stream)
                 nb = N_MAIN * (4 + zo.element_size())
                 rmse, mx = exact_error_on_grid(A, torch, t, cdt, "dyadic")
@@ -499,7 +535,6 @@ def main():
                               "hbm_frac": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "ms": ms,
                               "rmse_vs_fp64": rmse, "max_err_vs_fp64": mx})
                 log(f"sweep {sweep[-1]}")
-                del zo
     # geometric intervals with decay rate r (Theorem 2.5): 64 rows, FP32
     for rr in (0.5, 0.6, 0.7, 0.8, 0.9):
         for d in (1, 3):
@@ -529,7 +564,7 @@ def main():
     result["sweep"] = {"columns": cols, "rows": [[sig(r.get(c), 3) for c in cols] for r in sweep if "degree" in r]}
     result["sweep_other"] = [compact_row(r) for r in sweep if "degree" not in r]
     result["sweep_error_reference"] = "library exact_icdf (AS 241; oracle-pinned 4e-15) on the whole u24 grid"
-    del u, z
+    del u, z, z16
     torch.cuda.empty_cache()
 
     # ---------------------------------------------------------- C1
