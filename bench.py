@@ -299,7 +299,7 @@ def profile_levels(A, torch):
     exact, approximate (16-row linear dyadic table) and correction kinds; CIR
     time average, level 6: approximate kind with the linear chi-squared table
     (2^20 paths), the surrogate (2^20 paths), and the exact kind (2^17 paths);
-    surrogate: one training epoch over 2^20 exact targets (batch 4096) and one
+    surrogate: one training epoch over 2^20 exact targets (batch 65536) and one
     forward pass over 2^22 inputs.  Prints one line per call with its kernel
     time from the library's events."""
     from paper_2012_09715_amd import mlmc_driver as D
@@ -324,7 +324,7 @@ def profile_levels(A, torch):
     for rep in range(2):
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record()
-        sur.train(u, ll, t, epochs=1, batch=4096, lr=1e-3, seed=rep)
+        sur.train(u, ll, t, epochs=1, batch=65536, lr=1e-2, seed=rep)
         ev1.record()
         torch.cuda.synchronize()
         out["surrogate training epoch (2^20 samples)"] = ev0.elapsed_time(ev1)

@@ -247,8 +247,8 @@ typedef struct {
   double sum_pc;      /* sum of the coarse functional (0 at level 0)         */
   double kernel_ms;   /* device time of the level kernel, HIP events         */
   uint64_t fallbacks; /* CIR surrogate steps outside the trained log-lambda
-                         range: above it routed to the exact inverse, below
-                         it (lambda = 0 included) evaluated at its lower end */
+                         range (lambda = 0 included), where the network is
+                         evaluated at the range's nearer end                 */
   uint64_t reserved;
 } aicdf_level_sums;
 
@@ -293,14 +293,13 @@ typedef struct aicdf_surrogate aicdf_surrogate;
  * lambda_n = v_n e^(-kappa delta) / c,  v_(n+1) = c C_nu^-1(U_n; lambda_n).
  * The coarse path is the fine path observed at even steps.  kind:
  *   EXACT       exact inverse (FP64), two-word u53 draws
- *   APPROX      the surrogate network (required), one-word u24 draws; below
- *               the surrogate's log(lambda) range (lambda = 0 included) the
- *               network is evaluated at the range's lower end (P depends on
- *               lambda only through O(lambda) terms there); steps whose
- *               log(lambda) lies above the range use the exact inverse on
- *               the same u24; both kinds of out-of-range step are counted in
- *               out->fallbacks (the correction level removes the bias of
- *               either)
+ *   APPROX      the surrogate network (required), one-word u24 draws;
+ *               outside the surrogate's log(lambda) range (lambda = 0
+ *               included) the network is evaluated at the range's nearer
+ *               end (below it P depends on lambda only through O(lambda)
+ *               terms, above it P is close to its Gaussian limit); such
+ *               steps are counted in out->fallbacks (the correction level
+ *               removes the bias)
  *   CORRECTION  both on two-word draws (surrogate on the u24 of the high word)
  *   TWOWAY      both on the draws of CORRECTION, fine paths only:
  *               Y = P^_f - P~_f, sum_pf over P^_f, sum_pc over P~_f
@@ -550,10 +549,10 @@ aicdf_status approx_ncx2_sankaran(double nu, size_t n, const float* u, const flo
  * at a fixed nu for log(lambda) in [loglam_lo, loglam_hi]:
  *   w  = D(U): the 16-row cubic dyadic approximation of Phi^-1 (FP32)
  *   g  = 2 (log lambda - loglam_lo) / (loglam_hi - loglam_lo) - 1
- *   h1 = silu(W1 [w, g] + b1)                 W1 64x2, FP32
- *   h2 = silu(W2 bf16(h1) + b2)               W2 64x64 in BF16, FP32 sums (MFMA)
+ *   h1 = relu(W1 [w, g] + b1)                 W1 64x2, FP32
+ *   h2 = relu(W2 bf16(h1) + b2)               W2 64x64 in BF16, FP32 sums (MFMA)
  *   P~ = w + W3 . h2 + b3                     W3 64, FP32
- * silu(t) = t / (1 + e^-t).  Parameters are a flat FP32 vector of
+ * relu(t) = max(t, 0).  Parameters are a flat FP32 vector of
  * AICDF_SURROGATE_NPARAMS values in the order W1 (row-major 64x2), b1, W2
  * (row-major 64x64, out x in), b2, W3, b3. */
 #define AICDF_SURROGATE_HIDDEN 64
@@ -592,7 +591,7 @@ aicdf_status aicdf_surrogate_make_data(const aicdf_surrogate* s, uint64_t seed, 
                                        float* u, float* loglam, float* target, void* stream);
 
 /* Adam training (FP32 master weights) on device data for `epochs` passes of
- * mini-batches of `batch` samples (a multiple of 256, at most 65536) in a
+ * mini-batches of `batch` samples (a multiple of 256, at most 262144) in a
  * seeded shuffled order; cosine learning-rate decay from lr.  host_loss
  * (optional) receives the mean loss of the last epoch.  Synchronises.
  * Errors: EINVAL, ENOMEM, EHIP. */

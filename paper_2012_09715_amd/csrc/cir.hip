@@ -6,13 +6,15 @@
 //   APX_SURROGATE  P~ = MLP(D(U), g(log lambda)), x = lambda + nu +
 //                  2 sqrt(lambda+nu) P~, clamped at 0.  The network call is a
 //                  wave-wide matrix-core routine, so all 64 lanes step
-//                  together.  Below the trained log-lambda range (lambda = 0
-//                  included, after a step clamped at 0) the network is
-//                  evaluated at the range's lower end: P depends on lambda
-//                  only through O(lambda) terms there, far below the
-//                  network's own error.  A lane whose log lambda lies above
-//                  the range takes the exact inverse on the same u24 instead.
-//                  Both are counted as fallbacks.
+//                  together.  Outside the trained log-lambda range the
+//                  network is evaluated at the range's nearer end (counted
+//                  as fallbacks): below it (lambda = 0 included, after a step
+//                  clamped at 0) P depends on lambda only through O(lambda)
+//                  terms, above it (e^10 = 22026 for the benchmark's
+//                  network) P is within O(lambda^-1/2) of its Gaussian
+//                  limit; the correction level removes the bias either way.
+//                  No exact inverse in the approximate kind: its registers
+//                  would halve the waves the level keeps per SIMD.
 //   APX_POLY1/3    Section 5.1's piecewise-polynomial approximation (two
 //                  dyadic half tables per knot, linear interpolation in
 //                  sqrt(y)), clamped at 0; the table is staged in LDS.
@@ -57,7 +59,9 @@ constexpr uint32_t kMaxLdsRows = 2048;  // 32 KiB of chi-squared table rows
 
 struct CirArgs {
   double nu, c, decay, v0;
-  float nuf, cf, decayf, v0f, lo, hi, inv_span2;
+  float nuf, cf, decayf, v0f;
+  float lamf;      // decay / c: lambda of the next step is lamf times the variance
+  float g_a, g_b;  // surrogate feature before clamping: g = g_a log2(lambda) + g_b
   uint32_t level, nsteps;
   uint64_t n_paths, path_offset;
   uint32_t k0, k1, tag;
@@ -248,35 +252,31 @@ __device__ __forceinline__ void cir_level_block(const CirArgs& a, const float* _
       // path's lambda, starts the exact inverse's root iteration
       double x0 = 0.0;
       if (kSurr) {
-        const float lam = vs * a.decayf / a.cf;
-        const float ll = lam > 0.0f ? __logf(lam) : -1e30f;
-        const bool inr = ll <= a.hi;
-        const float g = inr ? mlp_g(fmaxf(ll, a.lo), a.lo, a.inv_span2) : 0.0f;
+        const float lam = vs * a.lamf;
+        // g in [-1, 1] on the trained log-lambda range; outside it the
+        // network is evaluated at the range's nearer end (counted; lambda = 0
+        // gives -inf).  Hardware log2 and square root (about 1 ulp): the
+        // correctly rounded library forms cost ~20 more instructions a step.
+        const float gr = fmaf(__builtin_amdgcn_logf(lam), a.g_a, a.g_b);
+        const float g = __builtin_amdgcn_fmed3f(gr, -1.0f, 1.0f);
         // all lanes; one path per wavefront: one sample spread over the wave
         const float Pt = SPARSE ? mlp_wave_forward_one(L, xch[threadIdx.x / 64], w2s, dyadic_w16(u24, tab), g)
                                 : mlp_wave_forward(L, A, dyadic_w16(u24, tab), g);
-        float x;
-        if (inr) {
-          const float s = lam + a.nuf;
-          x = fmaxf(fmaf(2.0f * sqrtf(s), Pt, s), 0.0f);
-          fb += (act && ll < a.lo) ? 1 : 0;  // below the range: counted, evaluated at its end
-        } else {
-          // (rare: behind a call in every shape)
-          x = work ? float(exact_inverse<SPARSE, kCall>(double(u24), a.nu, double(lam), 0.0)) : 0.0f;
-          fb += act ? 1 : 0;
-        }
+        const float s = lam + a.nuf;
+        const float x = fmaxf(fmaf(2.0f * __builtin_amdgcn_sqrtf(s), Pt, s), 0.0f);
+        fb += (act && !(gr >= -1.0f && gr <= 1.0f)) ? 1 : 0;
         if (kExact) x0 = double(x) + (ve * a.decay / a.c - double(lam));
         vs = a.cf * x;
         if (FUNC == 1) fs.node(n + 1, N, double(vs));
       }
       if (kPoly) {
-        const float lam = vs * a.decayf / a.cf;
+        const float lam = vs * a.lamf;
         vs = a.cf * fmaxf(chi2_approx_x<APX>(u24, lam, ctab, a.geo), 0.0f);
         if (kExact) x0 = double(chi2_approx_x<APX>(u24, float(ve * a.decay / a.c), ctab, a.geo));
         if (FUNC == 1) fs.node(n + 1, N, double(vs));
       }
       if (kSank) {
-        const float lam = vs * a.decayf / a.cf;
+        const float lam = vs * a.lamf;
         vs = a.cf * sankaran_x(u24, lam, a.nuf);
         if (kExact) x0 = double(sankaran_x(u24, float(ve * a.decay / a.c), a.nuf));
         if (FUNC == 1) fs.node(n + 1, N, double(vs));
@@ -335,6 +335,23 @@ __device__ __forceinline__ void cir_level_block(const CirArgs& a, const float* _
   }
 }
 
+// The surrogate's approximate kind one path per thread, held to three waves
+// per SIMD (168 registers: the W2 fragments stay in registers across the
+// path loop; reading them from LDS at every call frees 32, not enough for a
+// fourth wave without spills in the step loop, measured 3x slower).
+template <int FUNC>
+__global__ __launch_bounds__(kLevelBlock, 3) void cir_level_kernel_surr(CirArgs a, const float* __restrict__ params,
+                                                                       const uint16_t* __restrict__ w2b,
+                                                                       const f32x4* __restrict__ wtab,
+                                                                       double* __restrict__ partials,
+                                                                       double* __restrict__ path_out,
+                                                                       unsigned long long* __restrict__ fallbacks) {
+  __shared__ CirLds<false> S;
+  extern __shared__ f32x4 ctab[];
+  cir_level_block<AICDF_KIND_APPROX, FUNC, APX_SURROGATE, false, false>(a, params, w2b, wtab, partials, path_out,
+                                                                        fallbacks, blockIdx.x, gridDim.x, S, ctab);
+}
+
 template <int KIND, int FUNC, int APX, bool SPARSE>
 __global__ __launch_bounds__(kLevelBlock) void cir_level_kernel(CirArgs a, const float* __restrict__ params,
                                                                const uint16_t* __restrict__ w2b,
@@ -379,7 +396,9 @@ template <int KIND, int APX>
 aicdf_status launch_func(int func, CirArgs a, size_t lds, hipStream_t s, const float* p, const uint16_t* w2,
                          const f32x4* wt, double* part, double* po, unsigned long long* fb, unsigned* grid) {
   const LevelKernel ks = func == 0 ? cir_level_kernel<KIND, 0, APX, true> : cir_level_kernel<KIND, 1, APX, true>;
-  const LevelKernel kd = func == 0 ? cir_level_kernel<KIND, 0, APX, false> : cir_level_kernel<KIND, 1, APX, false>;
+  LevelKernel kd = func == 0 ? cir_level_kernel<KIND, 0, APX, false> : cir_level_kernel<KIND, 1, APX, false>;
+  if (KIND == AICDF_KIND_APPROX && APX == APX_SURROGATE)
+    kd = func == 0 ? cir_level_kernel_surr<0> : cir_level_kernel_surr<1>;
   aicdf_status st = choose_shape<KIND, APX>(func, a, lds, grid);
   if (st != AICDF_OK) return st;
   hipLaunchKernelGGL(a.sparse ? ks : kd, dim3(*grid), dim3(kLevelBlock), lds, s, a, p, w2, wt, part, po, fb);
@@ -399,7 +418,7 @@ aicdf_status choose_shape_kind(int kind, int func, CirArgs& a, size_t lds, unsig
 // is common to the batch.
 struct CirJob {
   double c, decay;
-  float cf, decayf, kdt, xi_sqdt;
+  float cf, decayf, lamf, kdt, xi_sqdt;
   uint32_t level, nsteps, tag, sparse;
   uint64_t n_paths, path_offset;
 };
@@ -416,15 +435,12 @@ static_assert(sizeof(CirBatch) + 64 <= 4096, "batched CIR arguments exceed the k
 // KSET 0: EXACT jobs only; 1: APPROX jobs only; 2: EXACT, APPROX and
 // CORRECTION jobs.  Each work-group finds its job and runs that job's level
 // code on its share of the job's paths; fallbacks: one counter per job.
-template <int KSET, int FUNC, int APX>
-__global__ __launch_bounds__(kLevelBlock) void cir_levels_kernel(CirBatch b, const float* __restrict__ params,
-                                                                const uint16_t* __restrict__ w2b,
-                                                                const f32x4* __restrict__ wtab,
-                                                                double* __restrict__ partials,
-                                                                unsigned long long* __restrict__ fallbacks) {
-  constexpr bool kW2 = KSET != 0 && APX == APX_SURROGATE;
-  __shared__ CirLds<kW2> S;
-  extern __shared__ f32x4 ctab[];
+template <int KSET, int FUNC, int APX, bool kW2>
+__device__ __forceinline__ void cir_levels_body(const CirBatch& b, const float* __restrict__ params,
+                                                const uint16_t* __restrict__ w2b, const f32x4* __restrict__ wtab,
+                                                double* __restrict__ partials,
+                                                unsigned long long* __restrict__ fallbacks, CirLds<kW2>& S,
+                                                f32x4* __restrict__ ctab) {
   uint32_t j = 0;
   while (j + 1 < b.n_jobs && blockIdx.x >= b.start[j + 1]) ++j;
   CirArgs a = b.base;
@@ -433,6 +449,7 @@ __global__ __launch_bounds__(kLevelBlock) void cir_levels_kernel(CirBatch b, con
   a.decay = jb.decay;
   a.cf = jb.cf;
   a.decayf = jb.decayf;
+  a.lamf = jb.lamf;
   a.kdt = jb.kdt;
   a.xi_sqdt = jb.xi_sqdt;
   a.level = jb.level;
@@ -477,9 +494,41 @@ __global__ __launch_bounds__(kLevelBlock) void cir_levels_kernel(CirBatch b, con
   }
 }
 
+template <int KSET, int FUNC, int APX>
+__global__ __launch_bounds__(kLevelBlock) void cir_levels_kernel(CirBatch b, const float* __restrict__ params,
+                                                                const uint16_t* __restrict__ w2b,
+                                                                const f32x4* __restrict__ wtab,
+                                                                double* __restrict__ partials,
+                                                                unsigned long long* __restrict__ fallbacks) {
+  constexpr bool kW2 = KSET != 0 && APX == APX_SURROGATE;
+  __shared__ CirLds<kW2> S;
+  extern __shared__ f32x4 ctab[];
+  cir_levels_body<KSET, FUNC, APX, kW2>(b, params, w2b, wtab, partials, fallbacks, S, ctab);
+}
+
+// APPROX-only batches with the surrogate: three waves per SIMD, as
+// cir_level_kernel_surr.
+template <int FUNC>
+__global__ __launch_bounds__(kLevelBlock, 3) void cir_levels_kernel_surr(CirBatch b, const float* __restrict__ params,
+                                                                        const uint16_t* __restrict__ w2b,
+                                                                        const f32x4* __restrict__ wtab,
+                                                                        double* __restrict__ partials,
+                                                                        unsigned long long* __restrict__ fallbacks) {
+  __shared__ CirLds<false> S;
+  extern __shared__ f32x4 ctab[];
+  cir_levels_body<1, FUNC, APX_SURROGATE, false>(b, params, w2b, wtab, partials, fallbacks, S, ctab);
+}
+
 template <int KSET, int APX>
 void launch_cir_batch(int func, const CirBatch& b, unsigned grid, size_t lds, hipStream_t s, const float* p,
                       const uint16_t* w2, const f32x4* wt, double* part, unsigned long long* fb) {
+  if (KSET == 1 && APX == APX_SURROGATE) {
+    if (func == 0)
+      hipLaunchKernelGGL(cir_levels_kernel_surr<0>, dim3(grid), dim3(kLevelBlock), lds, s, b, p, w2, wt, part, fb);
+    else
+      hipLaunchKernelGGL(cir_levels_kernel_surr<1>, dim3(grid), dim3(kLevelBlock), lds, s, b, p, w2, wt, part, fb);
+    return;
+  }
   if (func == 0)
     hipLaunchKernelGGL((cir_levels_kernel<KSET, 0, APX>), dim3(grid), dim3(kLevelBlock), lds, s, b, p, w2, wt, part,
                        fb);
@@ -537,6 +586,7 @@ aicdf_status cir_setup(const aicdf_cir_params* prm, uint32_t level, uint64_t n_p
   a.nuf = float(nu);
   a.cf = float(a.c);
   a.decayf = float(a.decay);
+  a.lamf = float(a.decay / a.c);
   a.v0f = float(prm->v0);
   a.level = level;
   a.nsteps = N;
@@ -549,6 +599,12 @@ aicdf_status cir_setup(const aicdf_cir_params* prm, uint32_t level, uint64_t n_p
   a.theta = float(prm->theta);
   a.xi_sqdt = float(prm->xi * std::sqrt(dt));
   return AICDF_OK;
+}
+
+// g = 2 (log lambda - lo) / (hi - lo) - 1 as g_a log2(lambda) + g_b.
+void surrogate_feature(bool have, double lo, double hi, CirArgs& a) {
+  a.g_a = have ? float(2.0 * std::log(2.0) / (hi - lo)) : 0.0f;
+  a.g_b = have ? float(-2.0 * lo / (hi - lo) - 1.0) : 0.0f;
 }
 
 aicdf_status cir_level_surrogate(const aicdf_cir_params* prm, uint32_t level, uint64_t n_paths, int32_t kind,
@@ -571,9 +627,7 @@ aicdf_status cir_level_surrogate(const aicdf_cir_params* prm, uint32_t level, ui
         return fail(AICDF_EINVAL, "surrogate was built for nu = %.17g, the process has nu = %.17g", snu, a.nu);
     }
   }
-  a.lo = float(lo);
-  a.hi = float(hi);
-  a.inv_span2 = sur ? float(2.0 / (hi - lo)) : 0.0f;
+  surrogate_feature(sur != nullptr, lo, hi, a);
 
   auto s = static_cast<hipStream_t>(stream);
   Workspace* ws = nullptr;
@@ -697,9 +751,8 @@ aicdf_status cir_batch_apx(const aicdf_cir_params* prm, const aicdf_level_job* j
     if (st == AICDF_OK && jb.kind == KIND_TWOWAY) st = fail(AICDF_EINVAL, "the two-way kind is not batched");
     unsigned g = 0;
     if (st == AICDF_OK && jb.n_paths > 0) {
-      a.lo = common.lo;
-      a.hi = common.hi;
-      a.inv_span2 = common.inv_span2;
+      a.g_a = common.g_a;
+      a.g_b = common.g_b;
       a.geo = common.geo;
       a.table_rows = common.table_rows;
       st = choose_shape_kind<APX>(jb.kind, prm->functional, a, lds, &g);
@@ -710,13 +763,12 @@ aicdf_status cir_batch_apx(const aicdf_cir_params* prm, const aicdf_level_job* j
     }
     if (j == 0) {
       b.base = a;
-      b.base.lo = common.lo;
-      b.base.hi = common.hi;
-      b.base.inv_span2 = common.inv_span2;
+      b.base.g_a = common.g_a;
+      b.base.g_b = common.g_b;
       b.base.geo = common.geo;
       b.base.table_rows = common.table_rows;
     }
-    b.job[j] = CirJob{a.c, a.decay, a.cf, a.decayf, a.kdt, a.xi_sqdt, a.level, a.nsteps, a.tag, a.sparse,
+    b.job[j] = CirJob{a.c, a.decay, a.cf, a.decayf, a.lamf, a.kdt, a.xi_sqdt, a.level, a.nsteps, a.tag, a.sparse,
                       a.n_paths, a.path_offset};
     any_exact |= jb.kind == AICDF_KIND_EXACT;
     any_approx |= jb.kind == AICDF_KIND_APPROX;
@@ -769,9 +821,7 @@ aicdf_status cir_batch(const aicdf_cir_params* prm, const aicdf_level_job* jobs,
       if (any_apx && std::fabs(snu - nu) > 1e-12 * nu)
         return fail(AICDF_EINVAL, "surrogate was built for nu = %.17g, the process has nu = %.17g", snu, nu);
     }
-    common.lo = float(lo);
-    common.hi = float(hi);
-    common.inv_span2 = sur ? float(2.0 / (hi - lo)) : 0.0f;
+    surrogate_feature(sur != nullptr, lo, hi, common);
     const float* p = sur ? surrogate_params(sur) : nullptr;
     const uint16_t* w2 = sur ? surrogate_w2b(sur) : nullptr;
     const f32x4* wt = sur ? reinterpret_cast<const f32x4*>(surrogate_wtab(sur)) : nullptr;

@@ -7,15 +7,16 @@
 //   forward   as mlp_wave_forward (mlp_device.hpp), keeping bf16(h1), a2;
 //   output    r = P~ - P, dP = 2 r / batch (mean squared error);
 //   layer 3   dW3[m] = sum_s dP_s h2[s][m], db3 = sum_s dP_s;
-//   layer 2   da2 = dP W3 silu'(a2); db2 = sum_s da2;
+//   layer 2   da2 = dP W3 relu'(a2); db2 = sum_s da2;
 //             dW2 = da2^T bf16(h1)      on MFMA (M = out, N = in, K = sample)
 //             dH1^T = bf16(W2)^T da2^T  on MFMA (M = in, N = sample, K = out)
 //             (da2 enters both products rounded to BF16; the rounding of h1
 //             and W2 is passed straight through)
-//   layer 1   da1 = dH1 silu'(a1), dW1 = sum_s da1 [w, g], db1 = sum_s da1.
+//   layer 1   da1 = dH1 relu'(a1), dW1 = sum_s da1 [w, g], db1 = sum_s da1.
 // Operands are transposed through LDS.  Every work-group writes its partial
-// gradient (4417 floats); one pass sums the partials in a fixed order and
-// applies Adam, so training is deterministic for a given seed.
+// gradient (4417 floats); two passes sum the partials in a fixed order
+// (slices of blocks, then the slices) and apply Adam, so training is
+// deterministic for a given seed.
 #include <cmath>
 #include <cstring>
 #include <fstream>
@@ -31,12 +32,14 @@ struct aicdf_surrogate {
   int device;
   float* params;     // device, kNParams FP32 master
   uint16_t* w2b;     // device, 64 x 64 BF16 copy of W2
+  uint16_t* w2bt;    // device, its transpose in the training kernel's K-slot order
   float* adam_m;     // device
   float* adam_v;     // device
   float* wtab;       // device, 64 rows x 4 floats: cubic dyadic table for w
   float* partials;   // device, max_blocks x kNParams
   float* loss_part;  // device, max_blocks
   double* scratch;   // device, kNParams + 1 doubles (reduced gradient, loss)
+  double* stage;     // device, kMaxSlices x (kNParams + 1): sums of block slices
   size_t max_blocks;
   uint64_t step;
 };
@@ -44,7 +47,12 @@ struct aicdf_surrogate {
 namespace {
 
 constexpr int kTrainWave = 64;
-constexpr size_t kMaxTrainBlocks = 1024;  // 65536 samples per call of the train kernel
+// version 2: relu activations (version 1 files hold weights of another network)
+constexpr uint32_t kFileVersion = 2;
+constexpr size_t kMaxTrainBlocks = 4096;  // 262144 samples per call of the train kernel
+// the per-block partial gradients are summed in two fixed-order stages: up to
+// kMaxSlices slices of at least kSliceRows blocks each, then the slices
+constexpr unsigned kMaxSlices = 32, kSliceRows = 32;
 
 // w = D(u): the 16-row cubic dyadic approximation in FP32 (Algorithm 1), rows
 // zero-padded to four coefficients.
@@ -84,14 +92,24 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const float* __restric
 }
 
 // ---------------------------------------------------------------- training
+// K slot k of the dH1 product holds output unit swap23(k) (bits 2 and 3 of k
+// exchanged): slot 16 kt + 8 h + i is then unit mlp_unit(kt / 2, 8 (kt % 2) +
+// i, h), the unit that a lane of half h holds in its layer-2 result slot
+// j = 8 (kt % 2) + i of tile kt / 2, so that each lane's own bf16(da2)
+// values are its B fragments and need no transpose.
+__host__ __device__ constexpr int swap23(int k) { return (k & ~12) | ((k & 4) << 1) | ((k & 8) >> 1); }
+
 struct TrainLds {
   MlpLds P;
+  bf16x8 a1n[2][64];  // layer-1 A fragments with rows in natural unit order (zero in lanes 32..63)
   f32x4 tab[16];
-  uint16_t w2t[kHidden * kHidden];     // bf16(W2)^T  [in][out]
-  uint16_t h1t[kHidden * kHidden];     // bf16(h1)    [in][sample]
-  uint16_t da2_sm[kHidden * kHidden];  // bf16(da2)   [sample][out]
-  uint16_t da2_ms[kHidden * kHidden];  // bf16(da2)   [out][sample]
-  float red[64][33];
+  union {
+    struct {
+      uint16_t h1t[kHidden * kHidden];     // bf16(h1)  [in][sample]
+      uint16_t da2_ms[kHidden * kHidden];  // bf16(da2) [out][sample]
+    } t;
+    float red[64][33];  // per-unit sums over samples (after the dW2 product)
+  } u;
 };
 
 __device__ __forceinline__ uint16_t bits(__bf16 x) { return __builtin_bit_cast(uint16_t, x); }
@@ -102,11 +120,11 @@ __device__ __forceinline__ float half_sum(TrainLds& S, const float (&v)[32]) {
   const int l = threadIdx.x;
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < 32; ++i) S.red[l][i] = v[i];
+  for (int i = 0; i < 32; ++i) S.u.red[l][i] = v[i];
   __syncthreads();
   const int idx = l & 31, h = l >> 5;
   float s = 0.0f;
-  for (int rr = 0; rr < 32; ++rr) s += S.red[h * 32 + rr][idx];
+  for (int rr = 0; rr < 32; ++rr) s += S.u.red[h * 32 + rr][idx];
   return s;
 }
 
@@ -116,16 +134,29 @@ __device__ __forceinline__ float wave_sum(float x) {
   return x;
 }
 
-__global__ __launch_bounds__(kTrainWave) void mlp_train_kernel(
-    const float* __restrict__ params, const uint16_t* __restrict__ w2b, const f32x4* __restrict__ wtab,
-    const float* __restrict__ u, const float* __restrict__ loglam, const float* __restrict__ target, size_t n_data,
-    uint64_t perm_a, uint64_t perm_b, size_t first, size_t count, float inv_batch, float lo, float inv_span2,
-    float* __restrict__ partials, float* __restrict__ loss_part) {
+// One work-group of one wave: 64 samples.  w2bt: bf16(W2)^T with its
+// columns in K-slot order, w2bt[in][k] = bf16(W2[swap23(k)][in]).  Held to
+// 256 registers (two waves per SIMD; the compiler's own choice, 251 + 80
+// accumulation registers, leaves one).
+__global__ __launch_bounds__(kTrainWave) __attribute__((amdgpu_waves_per_eu(2))) void mlp_train_kernel(
+    const float* __restrict__ params, const uint16_t* __restrict__ w2b, const uint16_t* __restrict__ w2bt,
+    const f32x4* __restrict__ wtab, const float* __restrict__ u, const float* __restrict__ loglam,
+    const float* __restrict__ target, size_t n_data, uint64_t perm_a, uint64_t perm_b, size_t first, size_t count,
+    float inv_batch, float lo, float inv_span2, float* __restrict__ partials, float* __restrict__ loss_part) {
   __shared__ TrainLds S;
   const int l = threadIdx.x, r = l & 31, half = l >> 5;
   mlp_stage_params(S.P, params, l, kTrainWave);
+  {
+    // natural-order rows: row k is hidden unit k
+    __bf16 wh, wl, gh, gl, bh, bl;
+    split_bf16(params[kOffW1 + 2 * l], wh, wl);
+    split_bf16(params[kOffW1 + 2 * l + 1], gh, gl);
+    split_bf16(params[kOffB1 + l], bh, bl);
+    const __bf16 zero = to_bf16(0.0f);
+    S.a1n[l >> 5][l & 31] = bf16x8{wh, wl, wh, gh, gl, gh, bh, bl};
+    S.a1n[l >> 5][32 + (l & 31)] = bf16x8{zero, zero, zero, zero, zero, zero, zero, zero};
+  }
   if (l < 16) S.tab[l] = wtab[l];
-  for (int i = 0; i < kHidden; ++i) S.w2t[l * kHidden + i] = w2b[i * kHidden + l];
   __syncthreads();
 
   // ---- sample of this lane (permuted index; lanes past the batch are masked)
@@ -141,34 +172,38 @@ __global__ __launch_bounds__(kTrainWave) void mlp_train_kernel(
   const float w = dyadic_w(ui, S.tab);
   if (!act) ti = w;
 
-  // ---- forward
+  // ---- forward: the arithmetic of mlp_wave_forward, keeping bf16(h1), a2
   bf16x8 A[2][4];
   mlp_load_w2(w2b, A);
   const float wo = __shfl_xor(w, 32), go = __shfl_xor(gi, 32);
-  const float ws[2] = {half ? wo : w, half ? w : wo};
+  const float ws[2] = {half ? wo : w, half ? w : wo};  // inputs of samples r, r + 32
   const float gs[2] = {half ? go : gi, half ? gi : go};
+  const bf16x8 X[2] = {mlp_input_frag(w, gi), mlp_input_frag(wo, go)};
   bf16x8 B[2][4];
-  mlp_layer1(S.P, ws, gs, B);
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt) mlp_layer1_mfma(mlp_w1_frag(S.P, 0), mlp_w1_frag(S.P, 1), X[nt], B[nt]);
 #pragma unroll
   for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
     for (int kt = 0; kt < 4; ++kt)
 #pragma unroll
-      for (int i = 0; i < 8; ++i) S.h1t[(16 * kt + 8 * half + i) * kHidden + 32 * nt + r] = bits(B[nt][kt][i]);
-  f32x16 acc[2][2];
-  mlp_layer2(A, B, acc);
-  float part[2] = {0.0f, 0.0f};
+      for (int i = 0; i < 8; ++i) S.u.t.h1t[(16 * kt + 8 * half + i) * kHidden + 32 * nt + r] = bits(B[nt][kt][i]);
+  f32x16 acc[2][2];  // a2 = W2 bf16(h1) + b2, [mt][nt]
+  float part[2];
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
+  for (int nt = 0; nt < 2; ++nt) {
+    float p = 0.0f;
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
+    for (int mt = 0; mt < 2; ++mt) {
+      f32x16 c = mlp_b2_acc(S.P, mt, half);
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const f32x2 p = S.P.u2[mlp_unit(mt, j, half)];
-        part[nt] = fmaf(p[1], mlp_silu(acc[mt][nt][j] + p[0]), part[nt]);
-      }
-  part[0] += __shfl_xor(part[0], 32);
-  part[1] += __shfl_xor(part[1], 32);
+      for (int kt = 0; kt < 4; ++kt) c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[mt][kt], B[nt][kt], c, 0, 0, 0);
+      acc[mt][nt] = c;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) p = fmaf(S.P.w3s[mt][half][j], mlp_act(c[j]), p);
+    }
+    part[nt] = p + __shfl_xor(p, 32);
+  }
   const float P = w + (half ? part[1] : part[0]) + S.P.b3;
 
   // ---- output gradient
@@ -177,27 +212,26 @@ __global__ __launch_bounds__(kTrainWave) void mlp_train_kernel(
   const float dPo = __shfl_xor(dP, 32);
   const float dPs[2] = {half ? dPo : dP, half ? dP : dPo};
 
-  // ---- layers 3 and 2 (elementwise part)
+  // ---- layers 3 and 2 (elementwise part); bf16(da2) as the dH1 B
+  // fragments (K slot order swap23) and, transposed, for dW2
   float gW3[32], gb2[32];
+  bf16x8 Bd[2][4];
 #pragma unroll
   for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int m = mlp_unit(mt, j, half);
-      const f32x2 p = S.P.u2[m];
+      const float w3 = S.P.w3s[mt][half][j];
       float s3 = 0.0f, s2 = 0.0f;
 #pragma unroll
       for (int nt = 0; nt < 2; ++nt) {
-        const float a2 = acc[mt][nt][j] + p[0];
-        const float sg = mlp_sigmoid(a2);
-        const float h2 = a2 * sg;
-        const float da2 = dPs[nt] * p[1] * sg * fmaf(a2, 1.0f - sg, 1.0f);
-        s3 = fmaf(dPs[nt], h2, s3);
+        const float a2 = acc[mt][nt][j];
+        const float da2 = dPs[nt] * w3 * mlp_act_grad(a2);
+        s3 = fmaf(dPs[nt], mlp_act(a2), s3);
         s2 += da2;
-        const uint16_t db = f32_to_bf16_bits(da2);
-        const int s = 32 * nt + r;
-        S.da2_sm[s * kHidden + m] = db;
-        S.da2_ms[m * kHidden + s] = db;
+        const __bf16 db = to_bf16(da2);
+        Bd[nt][2 * mt + (j >> 3)][j & 7] = db;
+        S.u.t.da2_ms[m * kHidden + 32 * nt + r] = bits(db);
       }
       gW3[mt * 16 + j] = s3;
       gb2[mt * 16 + j] = s2;
@@ -212,8 +246,8 @@ __global__ __launch_bounds__(kTrainWave) void mlp_train_kernel(
     for (int t = 0; t < 2; ++t)
 #pragma unroll
       for (int kt = 0; kt < 4; ++kt) {
-        Aa[t][kt] = *reinterpret_cast<const bf16x8*>(&S.da2_ms[(32 * t + r) * kHidden + 16 * kt + 8 * half]);
-        Bb[t][kt] = *reinterpret_cast<const bf16x8*>(&S.h1t[(32 * t + r) * kHidden + 16 * kt + 8 * half]);
+        Aa[t][kt] = *reinterpret_cast<const bf16x8*>(&S.u.t.da2_ms[(32 * t + r) * kHidden + 16 * kt + 8 * half]);
+        Bb[t][kt] = *reinterpret_cast<const bf16x8*>(&S.u.t.h1t[(32 * t + r) * kHidden + 16 * kt + 8 * half]);
       }
     f32x16 g2[2][2];
     mlp_layer2(Aa, Bb, g2);
@@ -225,46 +259,52 @@ __global__ __launch_bounds__(kTrainWave) void mlp_train_kernel(
         for (int j = 0; j < 16; ++j)
           out[kOffW2 + mlp_unit(mt, j, half) * kHidden + 32 * nt + r] = g2[mt][nt][j];
   }
-  // ---- dH1^T = bf16(W2)^T da2^T: M = in, N = sample, K = out; then layer 1
-  float gw0[32], gw1[32], gb1[32];
-  {
-    bf16x8 Aa[2][4], Bb[2][4];
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-      for (int kt = 0; kt < 4; ++kt) {
-        Aa[t][kt] = *reinterpret_cast<const bf16x8*>(&S.w2t[(32 * t + r) * kHidden + 16 * kt + 8 * half]);
-        Bb[t][kt] = *reinterpret_cast<const bf16x8*>(&S.da2_sm[(32 * t + r) * kHidden + 16 * kt + 8 * half]);
-      }
-    f32x16 dh[2][2];
-    mlp_layer2(Aa, Bb, dh);
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const f32x4 c = S.P.u1[mlp_unit(mt, j, half)];
-        float s0 = 0.0f, s1 = 0.0f, sb = 0.0f;
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
-          const float a1 = fmaf(c[0], ws[nt], fmaf(c[1], gs[nt], c[2]));
-          const float sg = mlp_sigmoid(a1);
-          const float da1 = dh[mt][nt][j] * sg * fmaf(a1, 1.0f - sg, 1.0f);
-          s0 = fmaf(da1, ws[nt], s0);
-          s1 = fmaf(da1, gs[nt], s1);
-          sb += da1;
-        }
-        gw0[mt * 16 + j] = s0;
-        gw1[mt * 16 + j] = s1;
-        gb1[mt * 16 + j] = sb;
-      }
-  }
-  // ---- reductions over samples of the per-unit vectors
+  // ---- reductions over samples of the per-unit vectors of layers 3 and 2
+  // (LDS of the transposes is free from here on)
   const int unit = mlp_unit((l & 31) >> 4, l & 15, half);
   float v;
   v = half_sum(S, gW3);
   out[kOffW3 + unit] = v;
   v = half_sum(S, gb2);
   out[kOffB2 + unit] = v;
+  // ---- dH1^T = bf16(W2)^T da2^T: M = in, N = sample, K = out (slot order
+  // swap23); then layer 1, with relu'(a1) from the layer-1 product with rows
+  // in natural order (the result layout of dH1^T)
+  float gw0[32], gw1[32], gb1[32];
+  {
+    bf16x8 Aw[2][4];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int kt = 0; kt < 4; ++kt)
+        Aw[t][kt] = *reinterpret_cast<const bf16x8*>(w2bt + (32 * t + r) * kHidden + 16 * kt + 8 * half);
+    f32x16 dh[2][2];
+    mlp_layer2(Aw, Bd, dh);
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      float s0[16], s1[16], sb[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) s0[j] = s1[j] = sb[j] = 0.0f;
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) {
+        const f32x16 a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(S.a1n[mt][l], X[nt], f32x16{}, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const float da1 = dh[mt][nt][j] * mlp_act_grad(a1[j]);
+          s0[j] = fmaf(da1, ws[nt], s0[j]);
+          s1[j] = fmaf(da1, gs[nt], s1[j]);
+          sb[j] += da1;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        gw0[mt * 16 + j] = s0[j];
+        gw1[mt * 16 + j] = s1[j];
+        gb1[mt * 16 + j] = sb[j];
+      }
+    }
+  }
+  // ---- and of layer 1
   v = half_sum(S, gw0);
   out[kOffW1 + 2 * unit] = v;
   v = half_sum(S, gw1);
@@ -279,26 +319,42 @@ __global__ __launch_bounds__(kTrainWave) void mlp_train_kernel(
   }
 }
 
-// Sum of the per-block partials (fixed order, FP64) and, for mode 1, one
-// Adam step on the FP32 master weights with a refresh of the BF16 W2 copy.
-__global__ __launch_bounds__(256) void mlp_reduce_kernel(const float* __restrict__ partials,
-                                                         const float* __restrict__ loss_part, unsigned nblocks,
+// First stage: slice blockIdx.y of the per-block partials (blocks
+// [y rows, min((y + 1) rows, nblocks))), summed in order in FP64; entry
+// kNParams is the loss.
+__global__ __launch_bounds__(256) void mlp_slice_sum_kernel(const float* __restrict__ partials,
+                                                            const float* __restrict__ loss_part, unsigned nblocks,
+                                                            unsigned rows, double* __restrict__ stage) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p > kNParams) return;
+  const unsigned b0 = blockIdx.y * rows, b1 = min(b0 + rows, nblocks);
+  double g = 0.0;
+  if (p == kNParams) {
+    for (unsigned b = b0; b < b1; ++b) g += loss_part[b];
+  } else {
+    // unrolled so that the loads are in flight together; the sum keeps its order
+#pragma unroll 16
+    for (unsigned b = b0; b < b1; ++b) g += partials[size_t(b) * kNParams + p];
+  }
+  stage[size_t(blockIdx.y) * (kNParams + 1) + p] = g;
+}
+
+// Second stage: the sum of the slices (in order) and, for mode 1, one Adam
+// step on the FP32 master weights with a refresh of the BF16 W2 copy.
+__global__ __launch_bounds__(256) void mlp_reduce_kernel(const double* __restrict__ stage, unsigned slices,
                                                          double* __restrict__ grad_out, float* __restrict__ params,
                                                          float* __restrict__ am, float* __restrict__ av,
-                                                         uint16_t* __restrict__ w2b, int adam, float lr, float bc1,
-                                                         float bc2) {
+                                                         uint16_t* __restrict__ w2b, uint16_t* __restrict__ w2bt,
+                                                         int adam, float lr, float bc1, float bc2) {
   const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p == kNParams) {
-    double s = 0.0;
-#pragma unroll 16
-    for (unsigned b = 0; b < nblocks; ++b) s += loss_part[b];
-    grad_out[kNParams] += s;  // running loss sum
-  }
-  if (p >= kNParams) return;
+  if (p > kNParams) return;
   double g = 0.0;
-  // unrolled so that the loads are in flight together; the sum keeps its order
 #pragma unroll 16
-  for (unsigned b = 0; b < nblocks; ++b) g += partials[size_t(b) * kNParams + p];
+  for (unsigned y = 0; y < slices; ++y) g += stage[size_t(y) * (kNParams + 1) + p];
+  if (p == kNParams) {
+    grad_out[kNParams] += g;  // running loss sum
+    return;
+  }
   if (!adam) {
     grad_out[p] = g;
     return;
@@ -311,12 +367,17 @@ __global__ __launch_bounds__(256) void mlp_reduce_kernel(const float* __restrict
   const float mh = m / bc1, vh = v / bc2;
   const float np = params[p] - lr * mh / (sqrtf(vh) + 1e-8f);
   params[p] = np;
-  if (p >= kOffW2 && p < kOffW2 + kHidden * kHidden) w2b[p - kOffW2] = f32_to_bf16_bits(np);
+  if (p >= kOffW2 && p < kOffW2 + kHidden * kHidden) {
+    const int q = p - kOffW2, o = q / kHidden, i = q % kHidden;
+    w2b[q] = w2bt[i * kHidden + swap23(o)] = f32_to_bf16_bits(np);
+  }
 }
 
-__global__ __launch_bounds__(256) void w2_refresh_kernel(const float* __restrict__ params, uint16_t* __restrict__ w2b) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < kHidden * kHidden) w2b[i] = f32_to_bf16_bits(params[kOffW2 + i]);
+__global__ __launch_bounds__(256) void w2_refresh_kernel(const float* __restrict__ params, uint16_t* __restrict__ w2b,
+                                                         uint16_t* __restrict__ w2bt) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q < kHidden * kHidden)
+    w2b[q] = w2bt[(q % kHidden) * kHidden + swap23(q / kHidden)] = f32_to_bf16_bits(params[kOffW2 + q]);
 }
 
 // ---------------------------------------------------------------- training data
@@ -373,8 +434,8 @@ aicdf_status check_dev(const aicdf_surrogate* s) {
 
 void free_surrogate(aicdf_surrogate* s) {
   if (!s) return;
-  for (void* p : {(void*)s->params, (void*)s->w2b, (void*)s->adam_m, (void*)s->adam_v, (void*)s->wtab,
-                  (void*)s->partials, (void*)s->loss_part, (void*)s->scratch})
+  for (void* p : {(void*)s->params, (void*)s->w2b, (void*)s->w2bt, (void*)s->adam_m, (void*)s->adam_v, (void*)s->wtab,
+                  (void*)s->partials, (void*)s->loss_part, (void*)s->scratch, (void*)s->stage})
     if (p) (void)hipFree(p);
   delete s;
 }
@@ -389,11 +450,13 @@ aicdf_status alloc_surrogate(double nu, double lo, double hi, aicdf_surrogate** 
   s->max_blocks = kMaxTrainBlocks;
   if (hipGetDevice(&s->device) != hipSuccess ||
       hipMalloc(&s->params, kNParams * 4) != hipSuccess || hipMalloc(&s->w2b, kHidden * kHidden * 2) != hipSuccess ||
+      hipMalloc(&s->w2bt, kHidden * kHidden * 2) != hipSuccess ||
       hipMalloc(&s->adam_m, kNParams * 4) != hipSuccess || hipMalloc(&s->adam_v, kNParams * 4) != hipSuccess ||
       hipMalloc(&s->wtab, 64 * 16) != hipSuccess ||
       hipMalloc(&s->partials, s->max_blocks * kNParams * 4) != hipSuccess ||
       hipMalloc(&s->loss_part, s->max_blocks * 4) != hipSuccess ||
-      hipMalloc(&s->scratch, (kNParams + 1) * 8) != hipSuccess) {
+      hipMalloc(&s->scratch, (kNParams + 1) * 8) != hipSuccess ||
+      hipMalloc(&s->stage, size_t(kMaxSlices) * (kNParams + 1) * 8) != hipSuccess) {
     free_surrogate(s);
     return fail(AICDF_ENOMEM, "device allocation for the surrogate failed");
   }
@@ -413,7 +476,7 @@ aicdf_status alloc_surrogate(double nu, double lo, double hi, aicdf_surrogate** 
 
 aicdf_status upload_params(aicdf_surrogate* s, const float* host) {
   AICDF_HIP(hipMemcpy(s->params, host, kNParams * 4, hipMemcpyHostToDevice));
-  hipLaunchKernelGGL(w2_refresh_kernel, dim3(16), dim3(256), 0, 0, s->params, s->w2b);
+  hipLaunchKernelGGL(w2_refresh_kernel, dim3(16), dim3(256), 0, 0, s->params, s->w2b, s->w2bt);
   AICDF_HIP(hipGetLastError());
   AICDF_HIP(hipMemset(s->adam_m, 0, kNParams * 4));
   AICDF_HIP(hipMemset(s->adam_v, 0, kNParams * 4));
@@ -517,7 +580,7 @@ aicdf_status grad_pass(aicdf_surrogate* s, const float* u, const float* ll, cons
   const unsigned nb = unsigned((count + kTrainWave - 1) / kTrainWave);
   if (nb > s->max_blocks) return fail(AICDF_ERANGE, "batch too large");
   const float inv_span2 = float(2.0 / (s->hi - s->lo));
-  hipLaunchKernelGGL(mlp_train_kernel, dim3(nb), dim3(kTrainWave), 0, st, s->params, s->w2b,
+  hipLaunchKernelGGL(mlp_train_kernel, dim3(nb), dim3(kTrainWave), 0, st, s->params, s->w2b, s->w2bt,
                      reinterpret_cast<const f32x4*>(s->wtab), u, ll, t, n_data, pa, pb, first, count, inv_batch,
                      float(s->lo), inv_span2, s->partials, s->loss_part);
   float bc1 = 1.0f, bc2 = 1.0f;
@@ -526,8 +589,12 @@ aicdf_status grad_pass(aicdf_surrogate* s, const float* u, const float* ll, cons
     bc1 = float(1.0 - std::pow(0.9, double(s->step)));
     bc2 = float(1.0 - std::pow(0.999, double(s->step)));
   }
-  hipLaunchKernelGGL(mlp_reduce_kernel, dim3((kNParams + 1 + 255) / 256), dim3(256), 0, st, s->partials,
-                     s->loss_part, nb, s->scratch, s->params, s->adam_m, s->adam_v, s->w2b, adam, lr, bc1, bc2);
+  const unsigned slices = std::min(kMaxSlices, (nb + kSliceRows - 1) / kSliceRows);
+  const unsigned rows = (nb + slices - 1) / slices;
+  hipLaunchKernelGGL(mlp_slice_sum_kernel, dim3((kNParams + 1 + 255) / 256, slices), dim3(256), 0, st, s->partials,
+                     s->loss_part, nb, rows, s->stage);
+  hipLaunchKernelGGL(mlp_reduce_kernel, dim3((kNParams + 1 + 255) / 256), dim3(256), 0, st, s->stage, slices,
+                     s->scratch, s->params, s->adam_m, s->adam_v, s->w2b, s->w2bt, adam, lr, bc1, bc2);
   AICDF_HIP(hipGetLastError());
   return AICDF_OK;
 }
@@ -577,7 +644,8 @@ extern "C" aicdf_status aicdf_surrogate_train(aicdf_surrogate* s, size_t n, cons
                                               uint64_t seed, double* host_loss, void* stream) {
   if (!s || !u || !loglam || !target) return fail(AICDF_EINVAL, "NULL argument");
   if (n == 0 || epochs == 0) return fail(AICDF_EINVAL, "need n > 0 and epochs > 0");
-  if (batch == 0 || batch % 256 || batch > 65536) return fail(AICDF_EINVAL, "batch must be a multiple of 256 <= 65536");
+  if (batch == 0 || batch % 256 || batch > kMaxTrainBlocks * kTrainWave)
+    return fail(AICDF_EINVAL, "batch must be a multiple of 256 <= %zu", kMaxTrainBlocks * kTrainWave);
   if (!(lr > 0.0f)) return fail(AICDF_EINVAL, "lr must be > 0");
   aicdf_status st = check_dev(s);
   if (st != AICDF_OK) return st;
@@ -622,7 +690,7 @@ extern "C" aicdf_status aicdf_surrogate_save(const aicdf_surrogate* s, const cha
   std::ofstream f(path, std::ios::binary);
   if (!f) return fail(AICDF_EIO, "cannot open %s", path);
   const char magic[8] = {'A', 'I', 'C', 'D', 'F', 'S', 'U', 'R'};
-  const uint32_t version = 1, np = kNParams;
+  const uint32_t version = kFileVersion, np = kNParams;
   f.write(magic, 8);
   f.write(reinterpret_cast<const char*>(&version), 4);
   f.write(reinterpret_cast<const char*>(&np), 4);
@@ -648,7 +716,7 @@ extern "C" aicdf_status aicdf_surrogate_load(const char* path, aicdf_surrogate**
   f.read(reinterpret_cast<char*>(&nu), 8);
   f.read(reinterpret_cast<char*>(&lo), 8);
   f.read(reinterpret_cast<char*>(&hi), 8);
-  if (!f || std::memcmp(magic, "AICDFSUR", 8) != 0 || version != 1 || np != uint32_t(kNParams))
+  if (!f || std::memcmp(magic, "AICDFSUR", 8) != 0 || version != kFileVersion || np != uint32_t(kNParams))
     return fail(AICDF_EIO, "%s is not a surrogate file of this version", path);
   std::vector<float> p(kNParams);
   f.read(reinterpret_cast<char*>(p.data()), kNParams * 4);

@@ -384,7 +384,7 @@ NU_CIR = 4 * CIR_PARAMS["kappa"] * CIR_PARAMS["theta"] / CIR_PARAMS["xi"] ** 2
 SURROGATE_RANGE = (-8.0, 10.0)
 
 
-def train_surrogate(n_train=10_000_000, epochs=8, batch=4096, lr=3e-3, seed=20201217, n_eval=1 << 18, log=print):
+def train_surrogate(n_train=10_000_000, epochs=64, batch=65536, lr=1e-2, seed=20201217, n_eval=1 << 18, log=print):
     """Builds and trains the CIR surrogate on n_train exact FP64 targets;
     returns (surrogate, report) with the held-out RMSE against exact targets."""
     s = A.Surrogate.create(NU_CIR, *SURROGATE_RANGE, seed=seed)

@@ -22,7 +22,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-from oracle import cir, mlp, ncx2, tables  # noqa: E402
+from oracle import cir, mlp, tables  # noqa: E402
 from oracle.dtypes import round_f32  # noqa: E402
 from oracle.transform import dyadic_transform_f32  # noqa: E402
 
@@ -45,15 +45,11 @@ def surrogate_x(q):
         u, lam = np.asarray(u, float), np.asarray(lam, float)
         with np.errstate(divide="ignore"):
             ll = np.where(lam > 0, np.log(np.where(lam > 0, lam, 1.0)), -np.inf)
-        inr = ll <= HI
-        llc = np.where(inr, np.maximum(ll, LO), 0.0)
+        llc = np.clip(ll, LO, HI)  # outside the range: the network at the nearer end
         w = dyadic_transform_f32(cubic, u.astype(np.float32))[0].astype(np.float64)
-        P = mlp.forward(q, w, np.where(inr, mlp.g_feature(llc, LO, HI), 0.0), bf16=True)
+        P = mlp.forward(q, w, mlp.g_feature(llc, LO, HI), bf16=True)
         s = lam + NU
-        x = np.maximum(s + 2 * np.sqrt(s) * P, 0.0)
-        if (~inr).any():
-            x[~inr] = ncx2.icdf(u[~inr], NU, lam[~inr])
-        return x
+        return np.maximum(s + 2 * np.sqrt(s) * P, 0.0)
     return f
 
 

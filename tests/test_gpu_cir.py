@@ -12,7 +12,7 @@ import pytest
 import torch
 
 import paper_2012_09715_amd as A
-from oracle import cir, mlp, ncx2, tables
+from oracle import cir, mlp, tables
 from oracle.dtypes import round_f32
 from oracle.transform import dyadic_transform_f32
 
@@ -51,18 +51,12 @@ def oracle_surrogate_x(q):
         lam = np.asarray(lam, float)
         with np.errstate(divide="ignore"):
             ll = np.where(lam > 0, np.log(np.where(lam > 0, lam, 1.0)), -np.inf)
-        # below the range (lambda = 0 included) the network at the lower end;
-        # above it the exact inverse
-        inr = ll <= HI
-        llc = np.where(inr, np.maximum(ll, LO), 0.0)
+        # outside the range (lambda = 0 included) the network at the nearer end
+        llc = np.clip(ll, LO, HI)
         w = dyadic_transform_f32(CUBIC, u.astype(np.float32))[0].astype(np.float64)
-        P = mlp.forward(q, w, np.where(inr, mlp.g_feature(llc, LO, HI), 0.0), bf16=True)
+        P = mlp.forward(q, w, mlp.g_feature(llc, LO, HI), bf16=True)
         s = lam + NU
-        x = np.maximum(s + 2 * np.sqrt(s) * P, 0.0)
-        out = x.copy()
-        if (~inr).any():
-            out[~inr] = ncx2.icdf(u[~inr], NU, lam[~inr])
-        return out
+        return np.maximum(s + 2 * np.sqrt(s) * P, 0.0)
     return f
 
 
@@ -134,9 +128,8 @@ def test_split_determinism_and_fallbacks(damped):
     assert np.array_equal(c2, c[500:1500])
     st2 = A.mlmc_level_cir(p, 2, n1 + n2, 2, s, 5)
     assert st["sum"] == st2["sum"] and st["fallbacks"] == st2["fallbacks"]
-    # a surrogate whose range lies below every lambda falls back to the
-    # exact inverse on every step; one whose range lies above every lambda
-    # evaluates the network at its lower end on every step: both counted
+    # a surrogate whose range lies below every lambda, or above every lambda,
+    # evaluates the network at the range's nearer end on every step: counted
     low = A.Surrogate.create(NU, -60.0, -59.0, seed=2)
     sn = A.mlmc_level_cir(p, 2, 1000, 1, low, 5)
     assert sn["fallbacks"] == 1000 * 4
@@ -243,11 +236,10 @@ def test_one_path_per_wavefront_surrogate_is_bit_exact(damped):
     # TWOWAY returns P_c = P~_f, the surrogate path alone: its network calls
     # spread one sample over a wavefront when the call runs one path per
     # wavefront, with the per-sample arithmetic of the 64-sample call, so
-    # the two launch shapes give the same bits (lambda stays far below the
-    # range's upper end e^10 here, so no step takes the exact inverse; the
-    # steps counted as fallbacks lie below the range, lambda = 0 after a
-    # clamped step of this untrained network, and are evaluated by the
-    # network at its lower end in both shapes)
+    # the two launch shapes give the same bits (the steps counted as
+    # fallbacks lie below the range, lambda = 0 after a clamped step of this
+    # untrained network, and are evaluated by the network at its lower end
+    # in both shapes)
     s, _ = damped
     for functional, level in ((1, 2), (0, 3)):
         p = dict(CIR, functional=functional)

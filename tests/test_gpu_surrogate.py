@@ -3,7 +3,7 @@ targets) against the oracle's FP64 forward/backward.
 
 Tolerances
   forward    |dP| <= 2e-4 max(1, |P|): the oracle rounds h1 and W2 to BF16
-             like the kernels, but its FP64 silu may place an h1 value on the
+             like the kernels, but its FP64 layer-1 sums may place an h1 value on the
              other side of a BF16 rounding boundary (one BF16 ulp of h1, about
              4e-3 relative, reaching P through W2 and W3)
   gradient   relative norm error <= 2e-2 per parameter block (the kernels

@@ -177,13 +177,21 @@ def test_mlp_finite_differences():
 
 
 def test_mlp_hand_case():
+    # unit 0 of layer 1 passes w through relu; unit 3 of layer 2 adds it to
+    # its bias 2; unit 5 of layer 2 has a negative input (-3) that relu
+    # removes, whatever its output weight:
+    #   w = 1.5:  h1[0] = 1.5, a2[3] = 3.5, P = 1.5 + 0.5 * 3.5 + 0.25 = 3.5
+    #   w = -2:   h1[0] = 0,   a2[3] = 2,   P = -2 + 0.5 * 2 + 0.25 = -0.75
     p = {k: np.zeros(s) for k, s in mlp.PARAM_SHAPES.items()}
-    p["b3"] = np.array(0.25)
+    p["W1"][0, 0] = 1.0
+    p["W2"][3, 0] = 1.0
     p["b2"][3] = 2.0
     p["W3"][3] = 0.5
+    p["b2"][5] = -3.0
+    p["W3"][5] = 7.0
+    p["b3"] = np.array(0.25)
     P = mlp.forward(p, np.array([1.5, -2.0]), np.array([0.0, 0.3]))
-    s = 2.0 / (1.0 + np.exp(-2.0))  # silu(2)
-    assert np.allclose(P, np.array([1.5, -2.0]) + 0.25 + 0.5 * s, rtol=1e-15)
+    assert np.array_equal(P, np.array([3.5, -0.75]))
 
 
 def test_truncated_em_step_closed_form():
@@ -214,3 +222,23 @@ def test_twoway_replay_is_fine_difference():
     assert np.allclose(Y, Pf - Pt, rtol=0, atol=0)
     Yc, Pfc, _ = cir.level_replay(p, 2, cir.CORRECTION, 5, np.arange(6), surrogate_x=em)
     assert not np.allclose(Pf, Pfc)  # another stream (kind 7 vs 6)
+
+
+def test_mlp_split_layer1():
+    # the split-BF16 layer 1 of the inference kernels: exact when every
+    # value is a BF16 number, and within ~2^-16 relative of the exact a1
+    # otherwise (the dropped lo x lo products and the second-level residues)
+    rng = np.random.default_rng(11)
+    p = mlp.init_params(3)
+    p = {k: np.asarray(v, float).astype(np.float32).astype(np.float64) for k, v in p.items()}
+    w = rng.normal(size=500).astype(np.float32).astype(np.float64)
+    g = rng.uniform(-1, 1, 500).astype(np.float32).astype(np.float64)
+    exact = np.stack([w, g], axis=-1) @ p["W1"].T + p["b1"]
+    split = mlp.layer1_split(p, w, g)
+    scale = np.abs(w)[:, None] * np.abs(p["W1"][:, 0]) + np.abs(g)[:, None] * np.abs(p["W1"][:, 1]) + np.abs(p["b1"])
+    assert np.all(np.abs(split - exact) <= 2.0 ** -15 * scale)
+    assert np.any(split != exact)
+    from oracle.dtypes import round_bf16
+    q = {k: round_bf16(v) for k, v in p.items()}
+    wq, gq = round_bf16(w), round_bf16(g)
+    assert np.array_equal(mlp.layer1_split(q, wq, gq), np.stack([wq, gq], axis=-1) @ q["W1"].T + q["b1"])
