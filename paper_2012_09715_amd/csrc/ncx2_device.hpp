@@ -159,11 +159,39 @@ __host__ __device__ inline __noinline__ Ncx2Val ncx2_cdf(double x, double nu, do
   const double lD = (y < A + 1.0) ? lc + log(P) : lw + log(fmax(1.0 - Q * exp(lt), 1e-300));
   const double L = fmax(lD, lc);
   double D = exp(lD - L), c = exp(lc - L), w = 1.0;
+  // the stopping bound below, log w + lw - L - 600 k log 2 + log(r/(1-r))
+  // <= log(1e-17 C), without logarithms: w r <= T (1 - r) cdf with
+  // T = 1e-17 e^(L - lw) 2^(600 k) (0 or inf where that leaves the FP64
+  // range: never or always met)
+  double T = ncx2_scale(1e-17, L - lw);
   // mu = 0 ends the sweep at j = 0 before inv_mu is used
   const double inv_mu = 1.0 / mu, inv_y = 1.0 / y;
   double cdf = 0.0, pa = 0.0, pb = 0.0;  // pa = sum c_j (a+j), pb = sum c_j (a+j)(a+j-1)
   int k = 0;
-  for (int j = int(je);; --j) {
+  // the terms j >= max(jb + 2, 1) cannot end the sweep (the tests below
+  // start at j - 1 < jb + 1): without the tests, the same arithmetic
+  double dj = je;
+  const double jm = fmax(jb + 2.0, 1.0);
+  for (; dj >= jm; dj -= 1.0) {
+    const double Aj = a + dj;
+    cdf += D;
+    pa = fma(c, Aj, pa);
+    pb = fma(c, Aj * (Aj - 1.0), pb);
+    const double rw = dj * inv_mu;
+    c = c * rw * (Aj * inv_y);
+    w = w * rw;
+    D = fma(D, rw, c);
+    if (D > kNcx2Big || c > kNcx2Big) {
+      D *= kNcx2Small;
+      c *= kNcx2Small;
+      cdf *= kNcx2Small;
+      pa *= kNcx2Small;
+      pb *= kNcx2Small;
+      T *= kNcx2Big;
+      ++k;
+    }
+  }
+  for (int j = int(dj);; --j) {
     const double Aj = a + j;
     cdf += D;
     pa = fma(c, Aj, pa);
@@ -180,21 +208,21 @@ __host__ __device__ inline __noinline__ Ncx2Val ncx2_cdf(double x, double nu, do
       cdf *= kNcx2Small;
       pa *= kNcx2Small;
       pb *= kNcx2Small;
+      T *= kNcx2Big;
       ++k;
     }
     if (j - 1 < mu && j - 1 < jb + 1.0) {
       // remaining head: sum_(k<j-1) w_k P_k <= w_(j-1) r/(1-r), r = (j-1)/mu;
-      // sum of the remaining c_k <= c_(j-1) rc/(1-rc)
+      // sum of the remaining c_k <= c_(j-1) rc/(1-rc).  Lanes reach this
+      // test at different terms, so it is kept to a few multiplications.
       const double r = (j - 1) * inv_mu;
       const double rc = r * ((a + j - 1) * inv_y);
-      if (r < 1.0 && rc < 1.0) {
-        const double log_head = log(w) + lw - L - k * 415.88830833596718 + log(r / (1.0 - r));
-        if (log_head <= log(1e-17 * cdf) && D <= 1e-17 * cdf && c * rc / (1.0 - rc) <= 0.5e-17 * pa) {
-          cdf += D;
-          pa = fma(c, a + j - 1, pa);
-          pb = fma(c, (a + j - 1) * (a + j - 2), pb);
-          break;
-        }
+      if (r < 1.0 && rc < 1.0 && w * r <= T * (1.0 - r) * cdf && D <= 1e-17 * cdf &&
+          c * rc <= 0.5e-17 * pa * (1.0 - rc)) {
+        cdf += D;
+        pa = fma(c, a + j - 1, pa);
+        pb = fma(c, (a + j - 1) * (a + j - 2), pb);
+        break;
       }
     }
   }
@@ -219,10 +247,36 @@ __host__ __device__ inline __noinline__ Ncx2Val ncx2_sf(double x, double nu, dou
   const double lG = (y < A + 1.0) ? lw + log(fmax(1.0 - P * exp(lt), 1e-300)) : lc + log(Q);
   const double L = fmax(lG, lc);
   double G = exp(lG - L), c = exp(lc - L), w = 1.0;
+  double T = ncx2_scale(1e-17, L - lw);  // the stopping bound's factor, as in ncx2_cdf
   const double muy = mu * y;
   double sf = 0.0, pa = 0.0, pb = 0.0;  // pa = sum c_j (a+j), pb = sum c_j (a+j)(a+j-1)
   int k = 0;
-  for (int j = int(jb); j < int(jb) + 400000; ++j) {
+  // the terms j <= je - 2 cannot end the sweep (the test below starts at
+  // j + 1 > je - 1; je = 0 is the single term): without the tests, the same
+  // arithmetic
+  double dj = jb;
+  const double jm = je == 0.0 ? -1.0 : fmin(je - 2.0, jb + 399999.0);
+  for (; dj <= jm; dj += 1.0) {
+    const double Aj = a + dj;
+    sf += G;
+    pa = fma(c, Aj, pa);
+    pb = fma(c, Aj * (Aj - 1.0), pb);
+    const double d = 1.0 / ((dj + 1.0) * (Aj + 1.0));
+    const double rw = mu * (Aj + 1.0) * d;
+    G = rw * (G + c);
+    c = c * (muy * d);
+    w = w * rw;
+    if (G > kNcx2Big || c > kNcx2Big) {
+      G *= kNcx2Small;
+      c *= kNcx2Small;
+      sf *= kNcx2Small;
+      pa *= kNcx2Small;
+      pb *= kNcx2Small;
+      T *= kNcx2Big;
+      ++k;
+    }
+  }
+  for (int j = int(dj); j < int(jb) + 400000; ++j) {
     const double Aj = a + j;
     sf += G;
     pa = fma(c, Aj, pa);
@@ -241,16 +295,16 @@ __host__ __device__ inline __noinline__ Ncx2Val ncx2_sf(double x, double nu, dou
       sf *= kNcx2Small;
       pa *= kNcx2Small;
       pb *= kNcx2Small;
+      T *= kNcx2Big;
       ++k;
     }
     if (j + 1 > mu && j + 1 > je - 1.0) {
       // remaining tail: sum_(k>j+1) w_k Q_k <= w_(j+1) rw'/(1-rw'), rw' = mu/(j+2)
+      // (r < 1 here: j + 2 > mu + 1)
       const double r = mu / (j + 2.0);
       const double rc = r * (y / (Aj + 2.0));
-      if (rc < 1.0) {
-        const double log_tail = log(w) + lw - L - k * 415.88830833596718 + log(r / (1.0 - r));
-        if (log_tail <= log(1e-17 * sf) && G <= 1e-17 * sf && c * rc / (1.0 - rc) <= 0.5e-17 * pa) break;
-      }
+      if (rc < 1.0 && w * r <= T * (1.0 - r) * sf && G <= 1e-17 * sf && c * rc <= 0.5e-17 * pa * (1.0 - rc))
+        break;
     }
   }
   const double ls = L + k * 415.88830833596718;  // e^L 2^(600 k)
@@ -294,32 +348,6 @@ __host__ __device__ inline __noinline__ double ncx2_sankaran_start(double t, boo
   return B > 0.0 ? kl * pow(B, 1.0 / c1) : 0.0;
 }
 
-// Inverse CDF by safeguarded Halley steps, inside a bracket that is valid
-// before any evaluation:
-//   lower: C(x) <= P(a, x/2) <= (x/2)^a / Gamma(a+1), so
-//          x_lo = 2 (u Gamma(a+1))^(1/a) has C(x_lo) <= u;
-//   upper: the Chernoff bound 1 - C(x) <= 2^(nu/2) e^(lambda/2) e^(-x/4)
-//          (moment generating function at s = 1/4), so
-//          x_hi = 2 nu log 2 + 2 lambda - 4 log(1-u) has 1 - C(x_hi) <= 1-u.
-// The target is given as u = t (upper = false) or as the tail probability
-// 1 - u = t (upper = true), so that upper-tail targets below the FP64
-// spacing near 1 keep full precision; ncx2_icdf takes the upper form only for
-// 1 - u < 2^-10 (or lambda > 4096), where 1 - C computed from C would lose
-// digits, so that nearly every lane of a batch runs the same (downward) sweep.
-// lower: g(w) = log C(e^w) - log t in w = log x (the lower tail of C is
-//        close to a power of x, so g is close to linear in w),
-//        g' = x f / C,  g'' = g' + x^2 f' / C - g'^2;
-// upper: g(x) = log t - log(1 - C(x)) in x (close to linear in x in the
-//        upper tail),  g' = f / S,  g'' = f' / S + g'^2,  S = 1 - C.
-// The Halley step 2 g g' / (2 g'^2 - g g'') is taken when it points the way
-// of the Newton step g / g' and is at most twice as long; otherwise the
-// Newton step.  Steps that leave the bracket are replaced by bisection
-// (geometric while the bracket spans more than a factor of two).  The
-// iteration stops when a step is below 2e-15 relative, or when a Halley
-// (Newton) step inside the bracket is below 1e-6 (1e-9) relative: the error
-// after it is of the order of the cube (square) of the step, far below the
-// FP64 resolution, so the confirming evaluation is skipped.  `iters`
-// receives the number of CDF evaluations.
 // The Halley step if usable, else the Newton step; `halley` tells which.
 __host__ __device__ inline double ncx2_step(double g, double dg, double d2g, bool& halley) {
   const double newton = g / dg;
@@ -335,16 +363,27 @@ __host__ __device__ inline double ncx2_step(double g, double dg, double d2g, boo
   return newton;
 }
 
-// Ev supplies Ncx2Val cdf(x) and Ncx2Val sf(x) for the given (nu, lambda).
-// x0 > 0 inside the bracket replaces the built-in initial value (a caller
-// holding an approximation of the root passes it here).
-template <class Ev>
-__host__ __device__ inline double ncx2_solve(double t, bool upper, double nu, double lam, const Ev& ev,
-                                             int* iters, double x0 = 0.0) {
+// The iteration as an explicit state: ncx2_root_init sets the bracket and
+// the start, each evaluation of C (lower form) or 1 - C (upper form) at r.xx
+// goes to ncx2_root_update, until r.done; the root is then
+// ncx2_root_result(r).
+// lga1 = log Gamma(nu/2 + 1).  x0 > 0 inside the bracket replaces the
+// built-in initial value (a caller holding an approximation of the root
+// passes it here).
+struct Ncx2Root {
+  double lo, hi, cur;  // bracket and iterate: w = log x (lower form) or x (upper form)
+  double xx;           // the point of the next evaluation, e^w or x
+  double lt;           // log u (lower form) or log(1 - u) (upper form)
+  int it;              // completed iterations
+  bool upper, done;
+};
+
+__host__ __device__ inline void ncx2_root_init(Ncx2Root& r, double t, bool upper, double nu, double lam, double x0,
+                                               double lga1) {
   const double a = 0.5 * nu;
   const double lu = upper ? log1p(-t) : log(t);    // log u
   const double lq = upper ? log(t) : log1p(-t);    // log (1 - u)
-  double xlo = 2.0 * exp((lu + ncx2_lgamma(a + 1.0)) / a);
+  double xlo = 2.0 * exp((lu + lga1) / a);
   double xhi = 2.0 * nu * 0.69314718055994531 + 2.0 * lam - 4.0 * lq;
   if (!(xhi > xlo * 1.001)) xhi = xlo * 1.001 + 1e-300;
   // built-in start: Sankaran's approximation from lambda = 100 on, else (or
@@ -354,68 +393,137 @@ __host__ __device__ inline double ncx2_solve(double t, bool upper, double nu, do
   if (!(x > xlo && x < xhi) && lam >= 100.0) x = ncx2_sankaran_start(t, upper, nu, lam);
   if (!(x > xlo && x < xhi)) x = ncx2_guess(upper || t <= 0.5 ? t : 1.0 - t, upper || t > 0.5, nu, lam);
   if (!(x > xlo && x < xhi)) x = sqrt(xlo) * sqrt(xhi);
-  int it = 0;
+  r.upper = upper;
+  r.done = false;
+  r.it = 0;
   if (!upper) {
-    double wlo = log(xlo), whi = log(xhi), w = log(x);
-    for (; it < 100; ++it) {
-      const double xx = exp(w);
-      const Ncx2Val v = ev.cdf(xx);
-      const double g = v.cdf > 0.0 ? log(v.cdf) - lu : -1e300;
-      if (g == 0.0) break;
-      if (g < 0.0) wlo = w; else whi = w;
-      const double tol = 2e-15 * fmax(1.0, fabs(w));
-      double wn = 0.5 * (wlo + whi);
-      bool halley = false, good = false;
-      if (v.cdf > 0.0 && v.pdf > 0.0) {
-        const double dg = xx * v.pdf / v.cdf;
-        const double d2g = dg + xx * xx * v.dpdf / v.cdf - dg * dg;
-        wn = w - ncx2_step(g, dg, d2g, halley);
-        good = true;
-      }
-      if (good && fabs(wn - w) <= tol) {  // converged (may sit on the bracket end)
-        w = wn;
-        break;
-      }
-      if (!(wn > wlo && wn < whi)) {
-        wn = 0.5 * (wlo + whi);
-      } else if (good && fabs(wn - w) <= (halley ? 1e-6 : 1e-9) * fmax(1.0, fabs(w))) {
-        w = wn;
-        break;
-      }
-      w = wn;
-      if (whi - wlo <= tol) break;
-    }
-    x = exp(w);
+    r.lt = lu;
+    r.lo = log(xlo);
+    r.hi = log(xhi);
+    r.cur = log(x);
+    r.xx = exp(r.cur);
   } else {
-    for (; it < 100; ++it) {
-      const Ncx2Val v = ev.sf(x);
-      const double g = v.sf > 0.0 ? lq - log(v.sf) : 1e300;
-      if (g == 0.0) break;
-      if (g < 0.0) xlo = x; else xhi = x;
-      double xn = -1.0;
-      bool halley = false, good = false;
-      if (v.sf > 0.0 && v.pdf > 0.0) {
-        const double dg = v.pdf / v.sf;
-        const double d2g = v.dpdf / v.sf + dg * dg;
-        xn = x - ncx2_step(g, dg, d2g, halley);
-        good = true;
-      }
-      if (good && xn > 0.0 && fabs(xn - x) <= 2e-15 * x) {  // converged (may sit on the bracket end)
-        x = xn;
-        break;
-      }
-      if (!(xn > xlo && xn < xhi)) {
-        xn = (xhi > 2.0 * xlo) ? sqrt(xlo) * sqrt(xhi) : 0.5 * (xlo + xhi);
-      } else if (good && fabs(xn - x) <= (halley ? 1e-6 : 1e-9) * x) {
-        x = xn;
-        break;
-      }
-      x = xn;
-      if (xhi - xlo <= 2e-15 * x) break;
-    }
+    r.lt = lq;
+    r.lo = xlo;
+    r.hi = xhi;
+    r.cur = x;
+    r.xx = x;
   }
-  if (iters) *iters = it + 1;
-  return x;
+}
+
+__host__ __device__ inline double ncx2_root_result(const Ncx2Root& r) { return r.upper ? r.cur : exp(r.cur); }
+
+// One iteration with v = the evaluation at r.xx:
+// lower: g(w) = log C(e^w) - log u in w = log x (the lower tail of C is
+//        close to a power of x, so g is close to linear in w),
+//        g' = x f / C,  g'' = g' + x^2 f' / C - g'^2;
+// upper: g(x) = log(1 - u) - log(1 - C(x)) in x (close to linear in x in
+//        the upper tail),  g' = f / S,  g'' = f' / S + g'^2,  S = 1 - C.
+// The Halley step 2 g g' / (2 g'^2 - g g'') is taken when it points the way
+// of the Newton step g / g' and is at most twice as long; otherwise the
+// Newton step.  Steps that leave the bracket are replaced by bisection
+// (geometric while the bracket spans more than a factor of two).  The
+// iteration stops when a step is below 2e-15 relative, or when a Halley
+// (Newton) step inside the bracket is below 1e-6 (1e-9) relative: the error
+// after it is of the order of the cube (square) of the step, far below the
+// FP64 resolution, so the confirming evaluation is skipped; at the latest
+// after 100 iterations.
+__host__ __device__ inline void ncx2_root_update(Ncx2Root& r, const Ncx2Val& v) {
+  if (!r.upper) {
+    const double w = r.cur, xx = r.xx;
+    const double g = v.cdf > 0.0 ? log(v.cdf) - r.lt : -1e300;
+    if (g == 0.0) {
+      r.done = true;
+      return;
+    }
+    if (g < 0.0) r.lo = w; else r.hi = w;
+    const double tol = 2e-15 * fmax(1.0, fabs(w));
+    double wn = 0.5 * (r.lo + r.hi);
+    bool halley = false, good = false;
+    if (v.cdf > 0.0 && v.pdf > 0.0) {
+      const double dg = xx * v.pdf / v.cdf;
+      const double d2g = dg + xx * xx * v.dpdf / v.cdf - dg * dg;
+      wn = w - ncx2_step(g, dg, d2g, halley);
+      good = true;
+    }
+    if (good && fabs(wn - w) <= tol) {  // converged (may sit on the bracket end)
+      r.cur = wn;
+      r.done = true;
+      return;
+    }
+    if (!(wn > r.lo && wn < r.hi)) {
+      wn = 0.5 * (r.lo + r.hi);
+    } else if (good && fabs(wn - w) <= (halley ? 1e-6 : 1e-9) * fmax(1.0, fabs(w))) {
+      r.cur = wn;
+      r.done = true;
+      return;
+    }
+    r.cur = wn;
+    if (r.hi - r.lo <= tol) {
+      r.done = true;
+      return;
+    }
+    r.xx = exp(wn);
+  } else {
+    const double x = r.cur;
+    const double g = v.sf > 0.0 ? r.lt - log(v.sf) : 1e300;
+    if (g == 0.0) {
+      r.done = true;
+      return;
+    }
+    if (g < 0.0) r.lo = x; else r.hi = x;
+    double xn = -1.0;
+    bool halley = false, good = false;
+    if (v.sf > 0.0 && v.pdf > 0.0) {
+      const double dg = v.pdf / v.sf;
+      const double d2g = v.dpdf / v.sf + dg * dg;
+      xn = x - ncx2_step(g, dg, d2g, halley);
+      good = true;
+    }
+    if (good && xn > 0.0 && fabs(xn - x) <= 2e-15 * x) {  // converged (may sit on the bracket end)
+      r.cur = xn;
+      r.done = true;
+      return;
+    }
+    if (!(xn > r.lo && xn < r.hi)) {
+      xn = (r.hi > 2.0 * r.lo) ? sqrt(r.lo) * sqrt(r.hi) : 0.5 * (r.lo + r.hi);
+    } else if (good && fabs(xn - x) <= (halley ? 1e-6 : 1e-9) * x) {
+      r.cur = xn;
+      r.done = true;
+      return;
+    }
+    r.cur = xn;
+    if (r.hi - r.lo <= 2e-15 * xn) {
+      r.done = true;
+      return;
+    }
+    r.xx = xn;
+  }
+  if (++r.it >= 100) r.done = true;
+}
+
+// Inverse CDF by the iteration above, inside a bracket that is valid before
+// any evaluation:
+//   lower: C(x) <= P(a, x/2) <= (x/2)^a / Gamma(a+1), so
+//          x_lo = 2 (u Gamma(a+1))^(1/a) has C(x_lo) <= u;
+//   upper: the Chernoff bound 1 - C(x) <= 2^(nu/2) e^(lambda/2) e^(-x/4)
+//          (moment generating function at s = 1/4), so
+//          x_hi = 2 nu log 2 + 2 lambda - 4 log(1-u) has 1 - C(x_hi) <= 1-u.
+// The target is given as u = t (upper = false) or as the tail probability
+// 1 - u = t (upper = true), so that upper-tail targets below the FP64
+// spacing near 1 keep full precision; ncx2_icdf takes the upper form only for
+// 1 - u < 2^-10 (or lambda > 4096), where 1 - C computed from C would lose
+// digits, so that nearly every lane of a batch runs the same (downward) sweep.
+// Ev supplies Ncx2Val cdf(x) and Ncx2Val sf(x) for the given (nu, lambda).
+// `iters` receives the number of CDF evaluations.
+template <class Ev>
+__host__ __device__ inline double ncx2_solve(double t, bool upper, double nu, double lam, const Ev& ev,
+                                             int* iters, double x0 = 0.0) {
+  Ncx2Root r;
+  ncx2_root_init(r, t, upper, nu, lam, x0, ncx2_lgamma(0.5 * nu + 1.0));
+  while (!r.done) ncx2_root_update(r, r.upper ? ev.sf(r.xx) : ev.cdf(r.xx));
+  if (iters) *iters = r.it + 1;
+  return ncx2_root_result(r);
 }
 
 // The sequential evaluator: one lane sums every term.

@@ -146,8 +146,8 @@ def test_trained_surrogate_gain():
     from paper_2012_09715_amd import mlmc_driver as D
     from oracle import cir
     s = A.Surrogate.create(NU, LO, HI, seed=7)
-    u, ll, t = s.make_data(1 << 20, seed=10)
-    s.train(u, ll, t, epochs=8, batch=2048, lr=3e-3, seed=2)
+    u, ll, t = s.make_data(1 << 22, seed=10)
+    s.train(u, ll, t, epochs=32, batch=65536, lr=1e-2, seed=2)
     del u, ll, t
     L = 4
     r = D.nested_mlmc("cir", D.CIR_PARAMS, L, 1e-3, s, seed=77, n_pilot=1 << 15, steps_budget=1 << 22)
@@ -159,3 +159,22 @@ def test_trained_surrogate_gain():
     assert abs(r["theta_tilde"] - ref) < 5 * r["se_tilde"] + 1e-12
     for p in r["per_level"]:
         assert p["v4"] < 0.05 * p["v_hat"], p
+    # against Section 5.1's non-learned approximation on the same levels (the
+    # piecewise linear chi-squared table): the network's correction variance
+    # is lower on the coarse levels, where lambda is small and the transition
+    # furthest from normal, and summed over the levels; the table gains on
+    # the network as lambda grows (both tend to the normal limit, the table's
+    # error with lambda, the network's not).  The network's approximate level
+    # costs more per path (a 2 -> 64 -> 64 -> 1 network against one table
+    # row per step), so the table's formula speed-up is the larger one.
+    rt = D.nested_mlmc("cir", D.CIR_PARAMS, L, 1e-3, A.Chi2Table.create(NU, 1), seed=77, n_pilot=1 << 15,
+                       steps_budget=1 << 22)
+    v4s = [p["v4"] for p in r["per_level"]]
+    v4t = [p["v4"] for p in rt["per_level"]]
+    print("log2 v4, surrogate:", [round(math.log2(v), 2) for v in v4s])
+    print("log2 v4, linear table:", [round(math.log2(v), 2) for v in v4t])
+    assert v4s[0] < v4t[0] and v4s[1] < v4t[1] and sum(v4s) < sum(v4t), (v4s, v4t)
+    for ps, pt in zip(r["per_level"], rt["per_level"]):
+        assert ps["c2_ns"] > pt["c2_ns"], (ps, pt)
+    assert rt["formula_speedup"] > r["formula_speedup"], (rt["formula_speedup"], r["formula_speedup"])
+    assert abs(rt["theta_tilde"] - ref) < 5 * rt["se_tilde"] + 1e-12
