@@ -73,12 +73,13 @@ def compact_row(r, n=3):
     return sig(r, n)
 
 
-def time_kernel(fn, reps, stream):
-    """Average device time of fn() over reps launches (after one untimed
-    launch), by HIP events on the stream the library launches on (torch's
+def time_kernel(fn, reps, stream, warm=1):
+    """Average device time of fn() over reps launches (after `warm` untimed
+    launches), by HIP events on the stream the library launches on (torch's
     current stream)."""
     import torch
-    fn()
+    for _ in range(warm):
+        fn()
     torch.cuda.synchronize()
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
@@ -181,18 +182,22 @@ def c1_leg(A, torch, stream):
         fn = (lambda: A.approx_icdf_const(tab, u)) if name == "const1024" else (lambda: A.approx_icdf_linear(tab, u))
         z = fn().cpu().numpy().astype(np.float64)
         idx = A.approx_icdf_index(tab, u).cpu().numpy().astype(np.int64)
-        t1 = time.perf_counter()
-        if name == "const1024":
-            io = transform.const_index(1024, uo)
-            zo = transform.const_transform(otab[name], uo)
-        else:
-            zo, io = transform.dyadic_transform(otab[name], uo)
-        t_one = time.perf_counter() - t1
+        for rep in range(2):  # the second pass is timed (the first touches numpy's arrays)
+            t1 = time.perf_counter()
+            if name == "const1024":
+                io = transform.const_index(1024, uo)
+                zo = transform.const_transform(otab[name], uo)
+            else:
+                zo, io = transform.dyadic_transform(otab[name], uo)
+            t_one = time.perf_counter() - t1
         w = host["workers"]
         ctx = mp.get_context("spawn")
         with ctx.Pool(w) as pool:
-            # each worker times its own slice; the slowest one is the wall time
-            t_all = max(pool.map(_c1_oracle_slice, [(name, otab[name], k * (n // w), n // w) for k in range(w)]))
+            # each worker times its own slice from a common start (after every
+            # worker has started and warmed up); the slowest one is the wall time
+            t0 = time.time() + 5.0
+            t_all = max(pool.map(_c1_oracle_slice,
+                                 [(name, otab[name], k * (n // w), n // w, t0) for k in range(w)]))
         ms = time_kernel(fn, 20, stream)
         d = z - zx
         out[name] = compact_row({"index_mismatches": int(np.count_nonzero(idx != io)),
@@ -206,8 +211,10 @@ def c1_leg(A, torch, stream):
 
 
 def _c1_oracle_slice(args):
-    """One worker's slice of the C1 oracle transform; returns its time."""
-    name, tab, off, m = args
+    """One worker's slice of the C1 oracle transform; returns its time, taken
+    from the wall-clock start t0 common to all workers (so that no worker is
+    timed while others still start up)."""
+    name, tab, off, m, t0 = args
     from oracle import rng, transform
     uo = rng.uniform_fill_f64(SEED, 1, off, m)
 
@@ -218,6 +225,7 @@ def _c1_oracle_slice(args):
         else:
             transform.dyadic_transform(tab, uo)
     run()  # warm: first-touch of the arrays numpy allocates
+    time.sleep(max(0.0, t0 - time.time()))
     t1 = time.perf_counter()
     run()
     return time.perf_counter() - t1
@@ -410,7 +418,8 @@ def profile_transforms(A, torch):
     """--profile-transforms: one call each (after one untimed call) of the
     streaming transforms on 2^30 FP32 uniforms, for hardware counters: the
     headline 16-row linear table to FP32, the same to FP16, the 32-row cubic
-    table to FP16 and the 1024-interval constant table to FP32."""
+    and 8-row linear tables to FP16, the 64-row geometric cubic table
+    (r = 0.7) to FP32 and the 1024-interval constant table to FP32."""
     u = torch.empty(N_MAIN, dtype=torch.float32, device="cuda")
     A.uniform_fill(u, SEED, 3, 0)
     z = torch.empty(N_MAIN, dtype=torch.float32, device="cuda")
@@ -418,6 +427,8 @@ def profile_transforms(A, torch):
     calls = [("dyadic16 d1 f32", lambda: A.approx_icdf_linear(A.Table.dyadic(16, 1), u, z=z)),
              ("dyadic16 d1 f16", lambda: A.approx_icdf_linear(A.Table.dyadic(16, 1, torch.float16), u, z=z16)),
              ("dyadic32 d3 f16", lambda: A.approx_icdf_linear(A.Table.dyadic(32, 3, torch.float16), u, z=z16)),
+             ("dyadic8 d1 f16", lambda: A.approx_icdf_linear(A.Table.dyadic(8, 1, torch.float16), u, z=z16)),
+             ("geometric64 r0.7 d3 f32", lambda: A.approx_icdf_linear(A.Table.geometric(0.7, 64, 3), u, z=z)),
              ("const1024 f32", lambda: A.approx_icdf_const(A.Table.const(1024), u, z=z))]
     out = {}
     for name, fn in calls:
@@ -514,20 +525,18 @@ def main():
     # one 16-bit output buffer for every 16-bit variant (a fresh 2 GiB
     # allocation per variant made the first variant timed on it slower)
     z16 = torch.empty(N_MAIN, dtype=torch.float16, device=dev)
-    # the 16-bit-output transforms reach their steady rate only after some
-    # 20-30 ms of such launches (measured: the first 16-bit variant timed ran
-    # at 65-75 % of peak, the same kernel later at ~84 %), so they are warmed
-    # up before the sweep
-    warm16 = A.Table.dyadic(16, 1, torch.float16)
-    for _ in range(40):
-        A.approx_icdf_linear(warm16, u, z=z16)
-    torch.cuda.synchronize()
+    # a transform that follows one of the other output width runs below its
+    # steady rate for some 10-20 launches (measured: the first 16-bit variant
+    # after an FP32 one at 65-70 % of peak in its first ten launches, ~83 %
+    # later and under the profiler), so every variant is timed after 20
+    # untimed launches of its own
+    warm = 20
     for T in (8, 16, 32):
         for d in (1, 3):
             for cdt, name in ((torch.float32, "f32"), (torch.float16, "f16"), (torch.bfloat16, "bf16")):
                 t = A.Table.dyadic(T, d, cdt)
                 zo = z if cdt == torch.float32 else z16.view(cdt)
-                ms = time_kernel(lambda: A.approx_icdf_linear(t, u, z=zo), reps, stream)
+                ms = time_kernel(lambda: A.approx_icdf_linear(t, u, z=zo), reps, stream, warm)
                 nb = N_MAIN * (4 + zo.element_size())
                 rmse, mx = exact_error_on_grid(A, torch, t, cdt, "dyadic")
                 sweep.append({"table": f"dyadic{T}", "degree": d, "coef": name, "out": name,
@@ -539,7 +548,7 @@ def main():
     for rr in (0.5, 0.6, 0.7, 0.8, 0.9):
         for d in (1, 3):
             t = A.Table.geometric(rr, 64, d)
-            ms = time_kernel(lambda: A.approx_icdf_linear(t, u, z=z), reps, stream)
+            ms = time_kernel(lambda: A.approx_icdf_linear(t, u, z=z), reps, stream, warm)
             rmse, mx = exact_error_on_grid(A, torch, t, torch.float32, "geometric")
             sweep.append({"table": f"geometric64_r{rr}", "degree": d, "coef": "f32", "out": "f32",
                           "samples_per_s": N_MAIN / (ms * 1e-3), "GBs": 8 * N_MAIN / (ms * 1e-3) / 1e9,
@@ -547,7 +556,7 @@ def main():
                           "rmse_vs_fp64": rmse, "max_err_vs_fp64": mx})
             log(f"sweep {sweep[-1]}")
     tc = A.Table.const(1024, 0, torch.float32)
-    ms = time_kernel(lambda: A.approx_icdf_const(tc, u, z=z), reps, stream)
+    ms = time_kernel(lambda: A.approx_icdf_const(tc, u, z=z), reps, stream, warm)
     rmse, mx = exact_error_on_grid(A, torch, tc, torch.float32, "const")
     sweep.append({"table": "const1024", "degree": 0, "coef": "f32", "out": "f32",
                   "samples_per_s": N_MAIN / (ms * 1e-3), "GBs": 8 * N_MAIN / (ms * 1e-3) / 1e9,
