@@ -53,6 +53,9 @@ def parse():
                     help="only one GPU-filling call of each fused level kernel and of the surrogate (for counters)")
     ap.add_argument("--detail", default=None, help="write the full per-level MLMC results to this JSON file")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="processes for the oracle's all-worker timings (0: the host's share; 1: no process "
+                         "pool, e.g. under a profiler that follows child processes)")
     return ap.parse_args()
 
 
@@ -91,10 +94,10 @@ def time_kernel(fn, reps, stream, warm=1):
     return float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
 
 
-def host_cpu():
+def host_cpu(workers=0):
     """The host's CPU model and the worker count the oracle may use: the
     process's CPU affinity, capped at the OMP_NUM_THREADS share (16 when
-    unset)."""
+    unset), or `workers` when given."""
     model = "unknown"
     try:
         with open("/proc/cpuinfo") as f:
@@ -106,7 +109,7 @@ def host_cpu():
         pass
     avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     share = int(os.environ.get("OMP_NUM_THREADS", "16") or 16)
-    return {"cpu_model": model, "nproc": avail, "workers": max(1, min(avail, share, 16))}
+    return {"cpu_model": model, "nproc": avail, "workers": workers if workers > 0 else max(1, min(avail, share, 16))}
 
 
 def _oracle_chunk(args):
@@ -122,7 +125,7 @@ def _oracle_chunk(args):
     return time.perf_counter() - t1
 
 
-def cpu_baseline(seconds):
+def cpu_baseline(seconds, workers=0):
     """The oracle's dyadic transform (FP64 numpy) on the benchmark stream:
     one process on 2^22 uniforms, repeated until `seconds` of CPU work, and
     then the host's workers (one process each, numpy being single-threaded
@@ -138,15 +141,20 @@ def cpu_baseline(seconds):
         t += _oracle_chunk((tab, 0, chunk, 1))
         reps += 1
     one = reps * chunk / t
-    host = host_cpu()
+    host = host_cpu(workers)
     w = host["workers"]
-    ctx = mp.get_context("spawn")
     reps_w = max(1, reps // 2)
-    with ctx.Pool(w) as pool:
-        pool.map(_oracle_chunk, [(tab, k * chunk, 1 << 12, 1) for k in range(w)])  # start-up outside the timing
+    if w == 1:
         t0 = time.perf_counter()
-        pool.map(_oracle_chunk, [(tab, k * chunk, chunk, reps_w) for k in range(w)])
+        _oracle_chunk((tab, 0, chunk, reps_w))
         tw = time.perf_counter() - t0
+    else:
+        ctx = mp.get_context("spawn")
+        with ctx.Pool(w) as pool:
+            pool.map(_oracle_chunk, [(tab, k * chunk, 1 << 12, 1) for k in range(w)])  # start-up outside the timing
+            t0 = time.perf_counter()
+            pool.map(_oracle_chunk, [(tab, k * chunk, chunk, reps_w) for k in range(w)])
+            tw = time.perf_counter() - t0
     allc = w * reps_w * chunk / tw
     return {"value": allc, "unit": "samples/s", "cores": w, "kind": "oracle",
             "single_core_value": one, "cpu_model": host["cpu_model"], "nproc": host["nproc"],
@@ -155,7 +163,7 @@ def cpu_baseline(seconds):
                       f"processes x {reps_w} passes over their own 2^22 uniforms ({tw:.1f} s)"}
 
 
-def c1_leg(A, torch, stream):
+def c1_leg(A, torch, stream, workers=0):
     """The small correctness configuration of Section 3.2 (Code 1) and 3.3
     (Code 2): 2^20 FP64 uniforms on the u53 grid from the Philox stream
     (seed 20201217, stream 1), through the 1024-interval constant table and
@@ -177,7 +185,7 @@ def c1_leg(A, torch, stream):
     tabs = {"const1024": A.Table.const(1024, 0, torch.float32), "linear16": A.Table.dyadic(16, 1, torch.float32)}
     otab = {"const1024": round_f32(tables.const_table(1024)), "linear16": round_f32(tables.dyadic_table(16, 1))}
     out = {"n": n, "input": "u53 grid, FP64", "output": "FP32"}
-    host = host_cpu()
+    host = host_cpu(workers)
     for name, tab in tabs.items():
         fn = (lambda: A.approx_icdf_const(tab, u)) if name == "const1024" else (lambda: A.approx_icdf_linear(tab, u))
         z = fn().cpu().numpy().astype(np.float64)
@@ -191,13 +199,16 @@ def c1_leg(A, torch, stream):
                 zo, io = transform.dyadic_transform(otab[name], uo)
             t_one = time.perf_counter() - t1
         w = host["workers"]
-        ctx = mp.get_context("spawn")
-        with ctx.Pool(w) as pool:
-            # each worker times its own slice from a common start (after every
-            # worker has started and warmed up); the slowest one is the wall time
-            t0 = time.time() + 5.0
-            t_all = max(pool.map(_c1_oracle_slice,
-                                 [(name, otab[name], k * (n // w), n // w, t0) for k in range(w)]))
+        if w == 1:
+            t_all = t_one
+        else:
+            ctx = mp.get_context("spawn")
+            with ctx.Pool(w) as pool:
+                # each worker times its own slice from a common start (after every
+                # worker has started and warmed up); the slowest one is the wall time
+                t0 = time.time() + 5.0
+                t_all = max(pool.map(_c1_oracle_slice,
+                                     [(name, otab[name], k * (n // w), n // w, t0) for k in range(w)]))
         ms = time_kernel(fn, 20, stream)
         d = z - zx
         out[name] = compact_row({"index_mismatches": int(np.count_nonzero(idx != io)),
@@ -577,7 +588,7 @@ def main():
     torch.cuda.empty_cache()
 
     # ---------------------------------------------------------- C1
-    result["c1"] = c1_leg(A, torch, stream)
+    result["c1"] = c1_leg(A, torch, stream, args.cpu_workers)
 
     # ---------------------------------------------------------- MLMC
     if not args.no_mlmc:
@@ -590,7 +601,7 @@ def main():
 
     # ---------------------------------------------------------- CPU baseline
     log("cpu baseline (oracle) ...")
-    result["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    result["cpu_baseline"] = cpu_baseline(args.cpu_seconds, args.cpu_workers)
     print(json.dumps(result), flush=True)
     return 0
 
