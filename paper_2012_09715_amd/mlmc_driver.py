@@ -346,6 +346,7 @@ def run_estimators(model, params, L, eps, approx, seed, accs, alloc, lats=None, 
                measured_speedup_concurrent=wall["hat"] / wall["tilde"], concurrent_streams=n_streams,
                concurrent_sums_identical=bool(same),
                fallbacks=sum(runs[l][k].fallbacks for l in range(L + 1) for k in KINDS),
+               fallbacks_per_level=[sum(runs[l][k].fallbacks for k in KINDS) for l in range(L + 1)],
                level_ms={name: [runs[l][k].ms for l in range(L + 1)]
                          for name, k in (("exact", A.KIND_EXACT), ("approx", A.KIND_APPROX),
                                          ("correction", A.KIND_CORRECTION))})
@@ -483,7 +484,8 @@ def compact(full):
     """The benchmark's MLMC results in a compact form for the one-line JSON
     record: per estimator the speed-ups, device times, estimates and, per
     level, log2 of the variances v^_l, v~_l, V~_l, the costs c^_l, c~_l,
-    C~_l (ns per path) and the allocated path counts m^_l, m~_l, M~_l."""
+    C~_l (ns per path), the allocated path counts m^_l, m~_l, M~_l and, for
+    the surrogate, the steps counted outside its trained range."""
     out = {}
     for key, r in full.items():
         if key == "fig4b_time_average":
@@ -501,7 +503,8 @@ def compact(full):
                         for s in ("em", "milstein")}
             out[key]["paths"] = r["paths"]
             continue
-        c = {k: _sig(v, 4 if k.startswith("theta") else 3) for k, v in _short(r).items() if k != "levels"}
+        c = {k: _sig(v, 4 if k.startswith("theta") else 3) for k, v in _short(r).items()
+             if k != "levels" and not (k == "fallbacks" and not v)}
         if key not in ("gbm_em", "gbm_milstein_1e8", "cir", "cir_1e8"):
             out[key] = c  # per-level figures for the configurations' estimators only
             continue
@@ -514,6 +517,9 @@ def compact(full):
             "c4_ns": [_sig(p["c4_ns"]) for p in pl],
             "m_hat": [math.ceil(p["m_hat"]) for p in pl], "m_tilde": [math.ceil(p["m_tilde"]) for p in pl],
             "M_tilde": [math.ceil(p["M_tilde"]) for p in pl]}
+        fbl = r.get("fallbacks_per_level")
+        if fbl and any(fbl):  # surrogate steps outside the trained log-lambda range, per level
+            c["per_level"]["fallbacks"] = fbl
         out[key] = c
     return out
 
