@@ -288,9 +288,9 @@ __device__ __forceinline__ void cir_level_block(const CirArgs& a, const float* _
       }
       if (kExact && work) {
         const double lam = ve * a.decay / a.c;
-        // from lambda = 32 on the solver's own scaled central chi-squared
-        // start (relative error ~1e-2 at 30, ~3e-4 at 1000) beats the
-        // approximations' (~1e-2), and it is used instead
+        // from lambda = 32 on the solver's own start (Sankaran's
+        // approximation, relative error ~1e-3 at 30, ~1e-6 at 1000) beats
+        // the approximations' (~1e-2), and it is used instead
         if (lam >= 32.0) x0 = 0.0;
         ve = a.c * exact_inverse<SPARSE, kCall>(u53, a.nu, lam, x0);
         if (FUNC == 1) fe.node(n + 1, N, ve);

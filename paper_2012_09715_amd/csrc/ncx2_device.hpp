@@ -386,11 +386,12 @@ __host__ __device__ inline void ncx2_root_init(Ncx2Root& r, double t, bool upper
   double xlo = 2.0 * exp((lu + lga1) / a);
   double xhi = 2.0 * nu * 0.69314718055994531 + 2.0 * lam - 4.0 * lq;
   if (!(xhi > xlo * 1.001)) xhi = xlo * 1.001 + 1e-300;
-  // built-in start: Sankaran's approximation from lambda = 100 on, else (or
+  // built-in start: Sankaran's approximation from lambda = 10 on, else (or
   // outside the bracket) the scaled central chi-squared one on the smaller
-  // tail probability
+  // tail probability (from lambda = 10 to 32 Sankaran's start leaves a third
+  // evaluation in 2 % of the CIR steps against 30 %)
   double x = x0;
-  if (!(x > xlo && x < xhi) && lam >= 100.0) x = ncx2_sankaran_start(t, upper, nu, lam);
+  if (!(x > xlo && x < xhi) && lam >= 10.0) x = ncx2_sankaran_start(t, upper, nu, lam);
   if (!(x > xlo && x < xhi)) x = ncx2_guess(upper || t <= 0.5 ? t : 1.0 - t, upper || t > 0.5, nu, lam);
   if (!(x > xlo && x < xhi)) x = sqrt(xlo) * sqrt(xhi);
   r.upper = upper;
@@ -424,10 +425,12 @@ __host__ __device__ inline double ncx2_root_result(const Ncx2Root& r) { return r
 // Newton step.  Steps that leave the bracket are replaced by bisection
 // (geometric while the bracket spans more than a factor of two).  The
 // iteration stops when a step is below 2e-15 relative, or when a Halley
-// (Newton) step inside the bracket is below 1e-6 (1e-9) relative: the error
-// after it is of the order of the cube (square) of the step, far below the
-// FP64 resolution, so the confirming evaluation is skipped; at the latest
-// after 100 iterations.
+// (Newton) step inside the bracket is below 1e-5 (1e-9) relative: the error
+// after it is of the order of the cube (square) of the step, 1e-15 (1e-18),
+// so the confirming evaluation is skipped (measured on the CIR steps: the
+// roots stay within 9e-12 of a solve to 2e-15, the CDF's own rounding
+// amplified by 2/nu, and 14 % fewer evaluations than with 1e-6); at the
+// latest after 100 iterations.
 __host__ __device__ inline void ncx2_root_update(Ncx2Root& r, const Ncx2Val& v) {
   if (!r.upper) {
     const double w = r.cur, xx = r.xx;
@@ -453,7 +456,7 @@ __host__ __device__ inline void ncx2_root_update(Ncx2Root& r, const Ncx2Val& v) 
     }
     if (!(wn > r.lo && wn < r.hi)) {
       wn = 0.5 * (r.lo + r.hi);
-    } else if (good && fabs(wn - w) <= (halley ? 1e-6 : 1e-9) * fmax(1.0, fabs(w))) {
+    } else if (good && fabs(wn - w) <= (halley ? 1e-5 : 1e-9) * fmax(1.0, fabs(w))) {
       r.cur = wn;
       r.done = true;
       return;
@@ -487,7 +490,7 @@ __host__ __device__ inline void ncx2_root_update(Ncx2Root& r, const Ncx2Val& v) 
     }
     if (!(xn > r.lo && xn < r.hi)) {
       xn = (r.hi > 2.0 * r.lo) ? sqrt(r.lo) * sqrt(r.hi) : 0.5 * (r.lo + r.hi);
-    } else if (good && fabs(xn - x) <= (halley ? 1e-6 : 1e-9) * x) {
+    } else if (good && fabs(xn - x) <= (halley ? 1e-5 : 1e-9) * x) {
       r.cur = xn;
       r.done = true;
       return;
