@@ -167,6 +167,78 @@ __device__ __forceinline__ double exact_inverse(double u, double nu, double lam,
   return SPARSE ? ncx2_icdf_wave(u, nu, lam, x0) : ncx2_icdf(u, nu, lam, nullptr, x0);
 }
 
+// Regrouping of the paths between steps in the kinds with the exact inverse
+// (one path per thread).  The exact inverse's cost per step grows with lambda
+// (its sweeps visit about 18 sqrt(lambda/2) + 32 terms; small lambda needs a
+// third evaluation), and a wave runs as long as its dearest lane.  Every
+// kRegroupEvery steps the work-group ranks its 256 paths by the exact path's
+// current v (lambda is v times a per-level constant) and moves them through
+// LDS so that each wave holds 64 paths of neighbouring lambda.  Which wave
+// takes which quarter of the order rotates with the regrouping and the
+// work-group, so that no SIMD keeps the dearest quarter.  A path's arithmetic
+// does not depend on the lane that runs it, and its results go back to its own
+// lane before the sums: values and sums are those of the loop without
+// regrouping, bit for bit.  kRegroupEvery is even: the Philox block of a pair
+// of steps is drawn at the even step, after the move.
+constexpr uint32_t kRegroupEvery = 4;
+constexpr int kRegroupRows = 6;  // carried doubles: v, two trapezoid sums, per path (exact and approximate)
+static_assert(kLevelBlock == 256 && kRegroupEvery % 2 == 0, "regrouping assumes four waves and step pairs");
+
+struct RegroupLds {
+  __align__(16) uint32_t key[kLevelBlock];
+  uint32_t sid[kLevelBlock];
+  double st[kRegroupRows][kLevelBlock];
+};
+
+// One LDS area per kernel that regroups (a function-scope static: kernels
+// that never call this do not allocate it).
+__device__ __forceinline__ RegroupLds& regroup_lds() {
+  __shared__ RegroupLds R;
+  return R;
+}
+
+// Moves this lane's path (block-local index sid and NST carried doubles, st[0]
+// = v of the exact path) to lane dst of the order and takes the path that
+// lands on this lane.  Keys are unique (the FP32 bits of v, order-preserving
+// for v >= 0, with the low 8 bits replaced by the lane), so the ranks are a
+// permutation whatever the values (NaN included).
+template <int NST>
+__device__ __forceinline__ void regroup(uint32_t rot, uint32_t& sid, double (&st)[NST]) {
+  static_assert(NST <= kRegroupRows, "too many carried values");
+  RegroupLds& R = regroup_lds();
+  const uint32_t t = threadIdx.x;
+  const uint32_t key = (__float_as_uint(float(st[0])) & ~0xFFu) | t;
+  R.key[t] = key;
+  __syncthreads();
+  uint32_t r = 0;
+  for (int j = 0; j < kLevelBlock; j += 4) {
+    const u32x4 k = *reinterpret_cast<const u32x4*>(&R.key[j]);
+    r += (k[0] < key ? 1u : 0u) + (k[1] < key ? 1u : 0u) + (k[2] < key ? 1u : 0u) + (k[3] < key ? 1u : 0u);
+  }
+  const uint32_t dst = ((((r >> 6) + rot) & 3u) << 6) | (r & 63u);
+  R.sid[dst] = sid;
+#pragma unroll
+  for (int q = 0; q < NST; ++q) R.st[q][dst] = st[q];
+  __syncthreads();
+  sid = R.sid[t];
+#pragma unroll
+  for (int q = 0; q < NST; ++q) st[q] = R.st[q][t];
+}
+
+// Returns the three results of the path this lane ran to the lane of its
+// block-local index sid (the first barrier ends the last regrouping's reads).
+__device__ __forceinline__ void regroup_return(uint32_t sid, double& y, double& pf, double& pc) {
+  RegroupLds& R = regroup_lds();
+  __syncthreads();
+  R.st[0][sid] = y;
+  R.st[1][sid] = pf;
+  R.st[2][sid] = pc;
+  __syncthreads();
+  y = R.st[0][threadIdx.x];
+  pf = R.st[1][threadIdx.x];
+  pc = R.st[2][threadIdx.x];
+}
+
 // Static LDS of a level work-group: the surrogate's staged parameters, the
 // per-wave exchange of the one-sample network call, W2 (one path per
 // wavefront only: W2 = true), the 16-row cubic table of the network's input
@@ -222,12 +294,15 @@ __device__ __forceinline__ void cir_level_block(const CirArgs& a, const float* _
   const uint32_t per_block = SPARSE ? kLevelBlock / 64 : kLevelBlock;
   const uint32_t slot = SPARSE ? threadIdx.x / 64 : threadIdx.x;
   const bool lead = SPARSE ? (threadIdx.x % 64) == 0 : true;
+  constexpr bool kRegroup = kExact && !SPARSE;
   for (uint64_t base = uint64_t(bid) * per_block; base < a.n_paths; base += uint64_t(nblk) * per_block) {
     const uint64_t i = base + slot;
     const bool act = lead && i < a.n_paths;   // lanes that keep the sums
     const bool work = SPARSE ? i < a.n_paths : true;  // wave-uniform when SPARSE
-    const uint64_t P = a.path_offset + i;
-    const uint32_t plo = uint32_t(P), phi = uint32_t(P >> 32);
+    uint32_t sid = slot;  // block-local index of the path this lane runs (moves when regrouped)
+    bool cact = act;      // that path is one of the call's
+    uint64_t P = a.path_offset + i;
+    uint32_t plo = uint32_t(P), phi = uint32_t(P >> 32);
     double ve = a.v0;
     float vs = a.v0f;
     FuncAcc fe, fs;
@@ -237,6 +312,39 @@ __device__ __forceinline__ void cir_level_block(const CirArgs& a, const float* _
     }
     u32x4 w{};
     for (uint32_t n = 0; n < N; ++n) {
+      if (kRegroup && n != 0 && n % kRegroupEvery == 0) {
+        constexpr int kF = FUNC == 1 ? 3 : 1;
+        double st[kApx ? 2 * kF : kF];
+        st[0] = ve;
+        if (FUNC == 1) {
+          st[1] = fe.fine;
+          st[2] = fe.coarse;
+        }
+        if (kApx) {
+          st[kF] = double(vs);
+          if (FUNC == 1) {
+            st[kF + 1] = fs.fine;
+            st[kF + 2] = fs.coarse;
+          }
+        }
+        regroup(n / kRegroupEvery + bid, sid, st);
+        ve = st[0];
+        if (FUNC == 1) {
+          fe.fine = st[1];
+          fe.coarse = st[2];
+        }
+        if (kApx) {
+          vs = float(st[kF]);
+          if (FUNC == 1) {
+            fs.fine = st[kF + 1];
+            fs.coarse = st[kF + 2];
+          }
+        }
+        P = a.path_offset + base + sid;
+        plo = uint32_t(P);
+        phi = uint32_t(P >> 32);
+        cact = base + sid < a.n_paths;
+      }
       double u53 = 0.5;
       float u24 = 0.5f;
       if (KIND == AICDF_KIND_APPROX) {
@@ -264,7 +372,7 @@ __device__ __forceinline__ void cir_level_block(const CirArgs& a, const float* _
                                 : mlp_wave_forward(L, A, dyadic_w16(u24, tab), g);
         const float s = lam + a.nuf;
         const float x = fmaxf(fmaf(2.0f * __builtin_amdgcn_sqrtf(s), Pt, s), 0.0f);
-        fb += (act && !(gr >= -1.0f && gr <= 1.0f)) ? 1 : 0;
+        fb += (cact && !(gr >= -1.0f && gr <= 1.0f)) ? 1 : 0;
         if (kExact) x0 = double(x) + (ve * a.decay / a.c - double(lam));
         vs = a.cf * x;
         if (FUNC == 1) fs.node(n + 1, N, double(vs));
@@ -314,6 +422,7 @@ __device__ __forceinline__ void cir_level_block(const CirArgs& a, const float* _
         Y -= Qf - Qc;
       }
     }
+    if (kRegroup && N > kRegroupEvery) regroup_return(sid, Y, Pf, Pc);
     if (act) {
       acc.add(Y, Pf, Pc);
       if (path_out) {

@@ -232,6 +232,34 @@ def test_thread_per_path_launch_parity(damped, kind):
     assert ok, worst
 
 
+@pytest.mark.parametrize("kind", [0, 2])
+def test_regrouped_paths_against_oracle(damped, kind):
+    # one path per thread with more than four steps: every four steps the
+    # work-group regroups its 256 paths by lambda through LDS and, at the end,
+    # returns each path's results to its own lane.  Paths from every wave of a
+    # work-group and from the ragged last one (7 of 256 lanes in use) against
+    # the oracle; against the same paths from a one-path-per-wavefront call;
+    # and the level sums against the sums of the path outputs (each path
+    # counted once)
+    s, q = damped
+    p = dict(CIR, functional=1)
+    n, seed, level = (1 << 17) + 7, 83, 5
+    st, got = run(p, level, n, kind, s if kind else None, seed)
+    pick = np.array([0, 1, 63, 64, 127, 191, 255, 256, 70000, n - 7, n - 3, n - 1])
+    ref = cir.level_replay(p, level, kind, seed, pick, surrogate_x=oracle_surrogate_x(q) if kind else None)
+    scale = np.maximum(np.abs(ref[1]), 1e-3)
+    tol = (1e-9 if kind == 0 else 2e-4 * (1 << level)) * scale
+    for j in range(3):
+        assert np.all(np.abs(got[pick, j] - ref[j]) <= tol), j
+    _, few = run(p, level, 300, kind, s if kind else None, seed, n - 300)
+    ok, worst = same_paths(few, got[n - 300:], shape_rel(level))
+    assert ok, worst
+    assert st["n"] == n
+    for key, col in (("sum_pf", 1), ("sum_pc", 2)):
+        assert abs(st[key] - got[:, col].sum()) <= 1e-12 * np.abs(got[:, col]).sum(), key
+    assert abs(st["sum"][0] - got[:, 0].sum()) <= 1e-12 * np.abs(got[:, 0]).sum()
+
+
 def test_one_path_per_wavefront_surrogate_is_bit_exact(damped):
     # TWOWAY returns P_c = P~_f, the surrogate path alone: its network calls
     # spread one sample over a wavefront when the call runs one path per
