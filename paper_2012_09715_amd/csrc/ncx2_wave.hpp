@@ -13,18 +13,18 @@
 // splits the index range into 64 contiguous chunks, one per lane.  Each lane
 // forms the product T of its chunk's matrices and the linear functionals
 // that give its chunk's partial sums from the chunk's incoming state; an
-// exclusive scan of the T over the lanes (shuffles) gives every lane its
-// incoming state from the state at the start of the range, and a butterfly
-// reduction sums the partials.  Matrices, states and sums carry a binary
+// exclusive scan of the T over the lanes (register moves between lanes, DPP)
+// gives every lane its incoming state from the state at the start of the
+// range, and an inclusive scan sums the partials into lane 63.  Matrices, states and sums carry a binary
 // exponent of their own (all entries are non-negative), so no product
 // overflows whatever the range.  Start states, ranges and stopping bounds are
 // those of the sequential sweeps, except that a sweep starts further out
 // (down to A = 2y for C, up to A = y/2 for 1 - C, at most 4096 terms more),
 // where the series (continued fraction) that gives its first term converges
 // in a few dozen serial steps; passes continue past the first range while
-// the bound on the remaining head (tail) is not met.  The butterfly gives
-// every lane the same bits, so the root driver around it takes identical
-// decisions in all lanes.
+// the bound on the remaining head (tail) is not met.  Totals are read back
+// from lane 63 as scalars, so every lane holds the same bits and the root
+// driver around it takes identical decisions in all lanes.
 #pragma once
 
 #include "ncx2_device.hpp"
@@ -55,44 +55,92 @@ __device__ __forceinline__ Ncx2Tri ncx2_compose(const Ncx2Tri& Y, const Ncx2Tri&
   return z;
 }
 
-__device__ __forceinline__ Ncx2Tri ncx2_shfl_up(const Ncx2Tri& t, int d) {
-  return Ncx2Tri{__shfl_up(t.p, d), __shfl_up(t.r, d), __shfl_up(t.q, d), __shfl_up(t.e, d)};
+// Cross-lane moves on the vector ALU (DPP), 32 bits at a time: lane l takes
+// v from the lane that CTRL names, or keeps `old` where that lane lies outside
+// its 16-lane row or the row is masked off (ROWS).  Shift right within rows
+// by 1, 2, 4, 8; broadcast of lane 15 of each row to the next row (rows 1
+// and 3 written) and of lane 31 to rows 2 and 3; shift of the whole wave
+// right by one lane.  They replace LDS-routed shuffles, whose round trips
+// set the latency of the one-path-per-wavefront inverse.
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShr1 = 0x138;
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int ncx2_dpp(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xF, false);
 }
 
-__device__ __forceinline__ Ncx2Tri ncx2_shfl(const Ncx2Tri& t, int src) {
-  return Ncx2Tri{__shfl(t.p, src), __shfl(t.r, src), __shfl(t.q, src), __shfl(t.e, src)};
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double ncx2_dpp(double old, double v) {
+  const long long o = __double_as_longlong(old), x = __double_as_longlong(v);
+  const unsigned lo = unsigned(ncx2_dpp<CTRL, ROWS>(int(o), int(x)));
+  const unsigned hi = unsigned(ncx2_dpp<CTRL, ROWS>(int(o >> 32), int(x >> 32)));
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+__device__ __forceinline__ double ncx2_readlane(double v, int l) {
+  const long long x = __double_as_longlong(v);
+  const unsigned lo = unsigned(__builtin_amdgcn_readlane(int(x), l));
+  const unsigned hi = unsigned(__builtin_amdgcn_readlane(int(x >> 32), l));
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+// The six steps of an inclusive scan over the 64 lanes with operator
+// op(x, y) (x the lane's own value, y the one moved in) and identity `id`:
+// four shifts within rows, then the two row broadcasts.
+template <class T, class Op>
+__device__ __forceinline__ T ncx2_wave_scan(T v, T id, Op op) {
+  v = op(v, ncx2_dpp<kDppRowShr1, 0xF>(id, v));
+  v = op(v, ncx2_dpp<kDppRowShr2, 0xF>(id, v));
+  v = op(v, ncx2_dpp<kDppRowShr4, 0xF>(id, v));
+  v = op(v, ncx2_dpp<kDppRowShr8, 0xF>(id, v));
+  v = op(v, ncx2_dpp<kDppRowBcast15, 0xA>(id, v));
+  v = op(v, ncx2_dpp<kDppRowBcast31, 0xC>(id, v));
+  return v;
+}
+
+// Sum over the 64 lanes, the same bits in every lane (lane 63's inclusive
+// sum, read back as a scalar).
+__device__ __forceinline__ double ncx2_wave_total(double v) {
+  return ncx2_readlane(ncx2_wave_scan(v, 0.0, [](double x, double y) { return x + y; }), 63);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ Ncx2Tri ncx2_dpp_tri(const Ncx2Tri& t) {
+  return Ncx2Tri{ncx2_dpp<CTRL, ROWS>(1.0, t.p), ncx2_dpp<CTRL, ROWS>(0.0, t.r), ncx2_dpp<CTRL, ROWS>(1.0, t.q),
+                 ncx2_dpp<CTRL, ROWS>(0, t.e)};
 }
 
 // Exclusive scan: lane l receives T_(l-1) ... T_0 (identity in lane 0); `all`
-// receives T_63 ... T_0 in every lane.
+// receives T_63 ... T_0 in every lane.  Composing with the identity leaves a
+// normalised matrix unchanged bit for bit, so the lanes that take no value
+// in a step need no branch.
 __device__ __forceinline__ Ncx2Tri ncx2_scan(Ncx2Tri t, int lane, Ncx2Tri& all) {
-  for (int d = 1; d < 64; d <<= 1) {
-    const Ncx2Tri o = ncx2_shfl_up(t, d);
-    if (lane >= d) t = ncx2_compose(t, o);
-  }
-  all = ncx2_shfl(t, 63);
-  Ncx2Tri x = ncx2_shfl_up(t, 1);
-  if (lane == 0) x = Ncx2Tri{1.0, 0.0, 1.0, 0};
-  return x;
+  (void)lane;
+  t = ncx2_compose(t, ncx2_dpp_tri<kDppRowShr1, 0xF>(t));
+  t = ncx2_compose(t, ncx2_dpp_tri<kDppRowShr2, 0xF>(t));
+  t = ncx2_compose(t, ncx2_dpp_tri<kDppRowShr4, 0xF>(t));
+  t = ncx2_compose(t, ncx2_dpp_tri<kDppRowShr8, 0xF>(t));
+  t = ncx2_compose(t, ncx2_dpp_tri<kDppRowBcast15, 0xA>(t));
+  t = ncx2_compose(t, ncx2_dpp_tri<kDppRowBcast31, 0xC>(t));
+  all = Ncx2Tri{ncx2_readlane(t.p, 63), ncx2_readlane(t.r, 63), ncx2_readlane(t.q, 63),
+                __builtin_amdgcn_readlane(t.e, 63)};
+  return ncx2_dpp_tri<kDppWaveShr1, 0xF>(t);
 }
 
 // Sums over the wave of three values m_i 2^(e_l) with a common per-lane
-// exponent, returned as mantissas on one exponent in every lane (the
-// butterfly gives every lane the same bits).  m1, m2 >= 0; m3 may be negative.
+// exponent, returned as mantissas on one exponent in every lane (the same
+// bits in every lane).  m1, m2 >= 0; m3 may be negative.
 __device__ __forceinline__ void ncx2_wave_sum3(double m1, double m2, double m3, int e, double& s1, double& s2,
                                                double& s3, int& es) {
-  int emax = (m1 > 0.0 || m2 > 0.0 || m3 != 0.0) ? e : -100000;
-  for (int k = 32; k > 0; k >>= 1) emax = max(emax, __shfl_xor(emax, k));
+  const int emax = __builtin_amdgcn_readlane(
+      ncx2_wave_scan((m1 > 0.0 || m2 > 0.0 || m3 != 0.0) ? e : -100000, -100000,
+                     [](int x, int y) { return max(x, y); }),
+      63);
   const int sh = max(e - emax, -2000);
-  double a1 = ldexp(m1, sh), a2 = ldexp(m2, sh), a3 = ldexp(m3, sh);
-  for (int k = 32; k > 0; k >>= 1) {
-    a1 += __shfl_xor(a1, k);
-    a2 += __shfl_xor(a2, k);
-    a3 += __shfl_xor(a3, k);
-  }
-  s1 = a1;
-  s2 = a2;
-  s3 = a3;
+  s1 = ncx2_wave_total(ldexp(m1, sh));
+  s2 = ncx2_wave_total(ldexp(m2, sh));
+  s3 = ncx2_wave_total(ldexp(m3, sh));
   es = emax == -100000 ? 0 : emax;
 }
 
@@ -124,22 +172,16 @@ __device__ __forceinline__ void ncx2_acc3(double& m1, double& m2, double& m3, in
 // S = sum_(k>=0) prod_(i=1..k) y/(A+i), so that P(A, y) = t S with
 // t = y^A e^-y / Gamma(A+1) (the power series of the sequential sweeps, for
 // y < A + 1), by the wave: lane l takes term k0 + l + 1 of each chunk of 64,
-// the terms of a chunk are the prefix products of its ratios (a shuffle
-// scan) times the product carried in, and a butterfly sums them.  The
+// the terms of a chunk are the prefix products of its ratios (a scan) times
+// the product carried in, and a second scan sums them.  The
 // ratios fall below 1/2 when A >= 2y, and one chunk then suffices.
 __device__ inline double ncx2_series_wave(double A, double y, int lane) {
   double sum = 1.0, carry = 1.0;
   for (int k0 = 0; k0 < 1 << 20; k0 += 64) {
-    double p = y / (A + double(k0 + lane + 1));
-    for (int d = 1; d < 64; d <<= 1) {
-      const double o = __shfl_up(p, d);
-      if (lane >= d) p *= o;
-    }
+    const double p = ncx2_wave_scan(y / (A + double(k0 + lane + 1)), 1.0, [](double x, double o) { return x * o; });
     const double term = carry * p;
-    double sc = term;
-    for (int k = 32; k > 0; k >>= 1) sc += __shfl_xor(sc, k);
-    sum += sc;
-    carry = __shfl(term, 63);
+    sum += ncx2_wave_total(term);
+    carry = ncx2_readlane(term, 63);
     // the rest is below carry r / (1 - r), r the next ratio (< 1 here)
     const double r = y / (A + double(k0 + 65));
     if (!(r < 1.0) || carry * r <= 1e-17 * sum * (1.0 - r)) break;
@@ -152,7 +194,7 @@ __device__ inline double ncx2_series_wave(double A, double y, int lane) {
 __device__ __forceinline__ void ncx2_logs_wave(double j, double A, double y, double ly, double mu, int lane,
                                                double& lw, double& lt) {
   const double lg = ncx2_lgamma_stirling(lane == 0 ? j + 1.0 : A + 1.0);
-  const double lgj = __shfl(lg, 0), lgA = __shfl(lg, 1);
+  const double lgj = ncx2_readlane(lg, 0), lgA = ncx2_readlane(lg, 1);
   lw = mu > 0.0 ? -mu + j * log(mu) - lgj : (j == 0.0 ? 0.0 : -1e308);
   lt = A * ly - y - lgA;
 }
