@@ -154,17 +154,19 @@ struct FuncAcc {
 // leave one wave per SIMD; behind a call the kernel needs the larger of the
 // two.  (One path per wavefront the network reads its weights from LDS and
 // the inverse stays inline: there a call's register saves cost more.)
-__device__ __noinline__ double ncx2_icdf_call(double u, double nu, double lam, double x0) {
-  return ncx2_icdf(u, nu, lam, nullptr, x0);
+// lga1 = log Gamma(nu/2 + 1), taken once per thread instead of once per
+// inverse (the library log-gamma is a long serial chain).
+__device__ __noinline__ double ncx2_icdf_call(double u, double nu, double lam, double x0, double lga1) {
+  return ncx2_icdf(u, nu, lam, nullptr, x0, lga1);
 }
-__device__ __noinline__ double ncx2_icdf_wave_call(double u, double nu, double lam, double x0) {
-  return ncx2_icdf_wave(u, nu, lam, x0);
+__device__ __noinline__ double ncx2_icdf_wave_call(double u, double nu, double lam, double x0, double lga1) {
+  return ncx2_icdf_wave(u, nu, lam, x0, lga1);
 }
 
 template <bool SPARSE, bool CALL>
-__device__ __forceinline__ double exact_inverse(double u, double nu, double lam, double x0) {
-  if (CALL) return SPARSE ? ncx2_icdf_wave_call(u, nu, lam, x0) : ncx2_icdf_call(u, nu, lam, x0);
-  return SPARSE ? ncx2_icdf_wave(u, nu, lam, x0) : ncx2_icdf(u, nu, lam, nullptr, x0);
+__device__ __forceinline__ double exact_inverse(double u, double nu, double lam, double x0, double lga1) {
+  if (CALL) return SPARSE ? ncx2_icdf_wave_call(u, nu, lam, x0, lga1) : ncx2_icdf_call(u, nu, lam, x0, lga1);
+  return SPARSE ? ncx2_icdf_wave(u, nu, lam, x0, lga1) : ncx2_icdf(u, nu, lam, nullptr, x0, lga1);
 }
 
 // Regrouping of the paths between steps in the kinds with the exact inverse
@@ -291,6 +293,7 @@ __device__ __forceinline__ void cir_level_block(const CirArgs& a, const float* _
   LevelAcc acc;
   unsigned long long fb = 0;
   const uint32_t N = a.nsteps;
+  const double lga1 = kExact ? ncx2_lgamma(0.5 * a.nu + 1.0) : 0.0;
   const uint32_t per_block = SPARSE ? kLevelBlock / 64 : kLevelBlock;
   const uint32_t slot = SPARSE ? threadIdx.x / 64 : threadIdx.x;
   const bool lead = SPARSE ? (threadIdx.x % 64) == 0 : true;
@@ -400,7 +403,7 @@ __device__ __forceinline__ void cir_level_block(const CirArgs& a, const float* _
         // approximation, relative error ~1e-3 at 30, ~1e-6 at 1000) beats
         // the approximations' (~1e-2), and it is used instead
         if (lam >= 32.0) x0 = 0.0;
-        ve = a.c * exact_inverse<SPARSE, kCall>(u53, a.nu, lam, x0);
+        ve = a.c * exact_inverse<SPARSE, kCall>(u53, a.nu, lam, x0, lga1);
         if (FUNC == 1) fe.node(n + 1, N, ve);
       }
     }

@@ -519,11 +519,12 @@ __host__ __device__ inline void ncx2_root_update(Ncx2Root& r, const Ncx2Val& v) 
 // digits, so that nearly every lane of a batch runs the same (downward) sweep.
 // Ev supplies Ncx2Val cdf(x) and Ncx2Val sf(x) for the given (nu, lambda).
 // `iters` receives the number of CDF evaluations.
+// lga1: log Gamma(nu/2 + 1) when the caller holds it (NaN: computed here).
 template <class Ev>
 __host__ __device__ inline double ncx2_solve(double t, bool upper, double nu, double lam, const Ev& ev,
-                                             int* iters, double x0 = 0.0) {
+                                             int* iters, double x0 = 0.0, double lga1 = __builtin_nan("")) {
   Ncx2Root r;
-  ncx2_root_init(r, t, upper, nu, lam, x0, ncx2_lgamma(0.5 * nu + 1.0));
+  ncx2_root_init(r, t, upper, nu, lam, x0, lga1 == lga1 ? lga1 : ncx2_lgamma(0.5 * nu + 1.0));
   while (!r.done) ncx2_root_update(r, r.upper ? ev.sf(r.xx) : ev.cdf(r.xx));
   if (iters) *iters = r.it + 1;
   return ncx2_root_result(r);
@@ -537,8 +538,9 @@ struct Ncx2Seq {
 };
 
 __host__ __device__ inline double ncx2_icdf_tail(double t, bool upper, double nu, double lam,
-                                                 int* iters = nullptr, double x0 = 0.0) {
-  return ncx2_solve(t, upper, nu, lam, Ncx2Seq{nu, lam}, iters, x0);
+                                                 int* iters = nullptr, double x0 = 0.0,
+                                                 double lga1 = __builtin_nan("")) {
+  return ncx2_solve(t, upper, nu, lam, Ncx2Seq{nu, lam}, iters, x0, lga1);
 }
 
 // Targets 1 - u below kNcx2UpperTail use the upper-tail form (1 - C by the
@@ -559,14 +561,14 @@ constexpr double kNcx2MaxLam = 1e8;
 
 // C_nu^-1(u; lambda) for u in [0, 1]: 0 at u = 0, +inf at u = 1, NaN outside
 // (and NaN for lambda outside [0, kNcx2MaxLam]).
-// x0 > 0: an approximation of the root to start from.
+// x0 > 0: an approximation of the root to start from; lga1 as in ncx2_solve.
 __host__ __device__ inline double ncx2_icdf(double u, double nu, double lam, int* iters = nullptr,
-                                            double x0 = 0.0) {
+                                            double x0 = 0.0, double lga1 = __builtin_nan("")) {
   if (!(u > 0.0)) return u == 0.0 ? 0.0 : __builtin_nan("");
   if (!(u < 1.0)) return u == 1.0 ? __builtin_inf() : __builtin_nan("");
   if (!(lam >= 0.0 && lam <= kNcx2MaxLam)) return __builtin_nan("");
   const bool upper = u > 0.5 && (1.0 - u < kNcx2UpperTail || lam > kNcx2UpperLam);
-  return ncx2_icdf_tail(upper ? 1.0 - u : u, upper, nu, lam, iters, x0);
+  return ncx2_icdf_tail(upper ? 1.0 - u : u, upper, nu, lam, iters, x0, lga1);
 }
 
 }  // namespace aicdf

@@ -189,13 +189,28 @@ __device__ inline double ncx2_series_wave(double A, double y, int lane) {
   return sum;
 }
 
-// log w_j (Poisson weight) and log t_A (as ncx2_logw, ncx2_logt), with the
-// two log-gamma values taken by two lanes at once.
-__device__ __forceinline__ void ncx2_logs_wave(double j, double A, double y, double ly, double mu, int lane,
+// log y, log w_j (Poisson weight) and log t_A (as ncx2_logw, ncx2_logt):
+// their four logarithms at once, one per lane (lanes 0..3: log y, log mu,
+// log (j+1), log (A+1)), and Stirling's series completed on the last two,
+// the arithmetic of ncx2_lgamma_stirling bit for bit (the library log-gamma
+// where its argument is below 16).
+__device__ __forceinline__ void ncx2_logs_wave(double j, double A, double y, double mu, int lane, double& ly,
                                                double& lw, double& lt) {
-  const double lg = ncx2_lgamma_stirling(lane == 0 ? j + 1.0 : A + 1.0);
-  const double lgj = ncx2_readlane(lg, 0), lgA = ncx2_readlane(lg, 1);
-  lw = mu > 0.0 ? -mu + j * log(mu) - lgj : (j == 0.0 ? 0.0 : -1e308);
+  const double z = lane == 0 ? y : lane == 1 ? mu : lane == 2 ? j + 1.0 : A + 1.0;
+  const double lz = log(z);
+  double lg;
+  if (!(z >= 16.0)) {
+    lg = ncx2_lgamma(z);
+  } else {
+    const double w = 1.0 / z, w2 = w * w;
+    const double s =
+        w * (1.0 / 12 + w2 * (-1.0 / 360 + w2 * (1.0 / 1260 + w2 * (-1.0 / 1680 + w2 * (1.0 / 1188 +
+                                                                    w2 * (-691.0 / 360360 + w2 * (1.0 / 156)))))));
+    lg = (z - 0.5) * lz - z + 0.91893853320467274 + s;
+  }
+  ly = ncx2_readlane(lz, 0);
+  const double lmu = ncx2_readlane(lz, 1), lgj = ncx2_readlane(lg, 2), lgA = ncx2_readlane(lg, 3);
+  lw = mu > 0.0 ? -mu + j * lmu - lgj : (j == 0.0 ? 0.0 : -1e308);
   lt = A * ly - y - lgA;
 }
 
@@ -246,7 +261,7 @@ __device__ inline __noinline__ Ncx2Val ncx2_cdf_wave(double x, double nu, double
   if (!(x > 0.0)) return Ncx2Val{0.0, 1.0, 0.0, 0.0};
   if (x > 1.7976931348623157e308) return Ncx2Val{1.0, 0.0, 0.0, 0.0};
   const int lane = __lane_id();
-  const double y = 0.5 * x, a = 0.5 * nu, mu = 0.5 * lam, ly = log(y);
+  const double y = 0.5 * x, a = 0.5 * nu, mu = 0.5 * lam;
   double jbd, jed;
   ncx2_sweep_range(y, a, mu, jbd, jed);
   // start high enough that the power series for P converges fast (y / A <=
@@ -254,8 +269,8 @@ __device__ inline __noinline__ Ncx2Val ncx2_cdf_wave(double x, double nu, double
   // (je = 0: the single term j = 0)
   if (jed > 0.0) jed = fmax(jed, fmin(ceil(2.0 * y - a), jed + 4096.0));
   const double A = a + jed;
-  double lw, lt;
-  ncx2_logs_wave(jed, A, y, ly, mu, lane, lw, lt);
+  double ly, lw, lt;
+  ncx2_logs_wave(jed, A, y, mu, lane, ly, lw, lt);
   double P, Q;
   if (y < A + 1.0)
     P = ncx2_series_wave(A, y, lane);
@@ -375,15 +390,15 @@ __device__ inline __noinline__ Ncx2Val ncx2_sf_wave(double x, double nu, double 
   if (!(x > 0.0)) return Ncx2Val{0.0, 1.0, 0.0, 0.0};
   if (x > 1.7976931348623157e308) return Ncx2Val{1.0, 0.0, 0.0, 0.0};
   const int lane = __lane_id();
-  const double y = 0.5 * x, a = 0.5 * nu, mu = 0.5 * lam, ly = log(y);
+  const double y = 0.5 * x, a = 0.5 * nu, mu = 0.5 * lam;
   double jbd, jed;
   ncx2_sweep_range(y, a, mu, jbd, jed);
   // start low enough that the continued fraction for Q converges fast
   // (A <= y / 2); the longer sweep is spread over the lanes
   if (jed > 0.0) jbd = fmin(jbd, fmax(fmax(0.0, floor(0.5 * y - a)), jbd - 4096.0));
   const double A = a + jbd;
-  double lw, lt;
-  ncx2_logs_wave(jbd, A, y, ly, mu, lane, lw, lt);
+  double ly, lw, lt;
+  ncx2_logs_wave(jbd, A, y, mu, lane, ly, lw, lt);
   double P, Q;
   if (y < A + 1.0)
     P = ncx2_series_wave(A, y, lane);
@@ -469,13 +484,15 @@ struct Ncx2Wave {
 
 // C_nu^-1(u; lambda) computed by the whole wavefront; every lane must pass
 // the same (u, nu, lambda, x0) and receives the same result.  x0 > 0: an
-// approximation of the root to start the iteration from.
-__device__ inline double ncx2_icdf_wave(double u, double nu, double lam, double x0 = 0.0) {
+// approximation of the root to start the iteration from; lga1 as in
+// ncx2_solve.
+__device__ inline double ncx2_icdf_wave(double u, double nu, double lam, double x0 = 0.0,
+                                        double lga1 = __builtin_nan("")) {
   if (!(u > 0.0)) return u == 0.0 ? 0.0 : __builtin_nan("");
   if (!(u < 1.0)) return u == 1.0 ? __builtin_inf() : __builtin_nan("");
   if (!(lam >= 0.0 && lam <= kNcx2MaxLam)) return __builtin_nan("");
   const bool upper = u > 0.5 && (1.0 - u < kNcx2UpperTail || lam > kNcx2UpperLam);
-  return ncx2_solve(upper ? 1.0 - u : u, upper, nu, lam, Ncx2Wave{nu, lam}, nullptr, x0);
+  return ncx2_solve(upper ? 1.0 - u : u, upper, nu, lam, Ncx2Wave{nu, lam}, nullptr, x0, lga1);
 }
 
 }  // namespace aicdf
