@@ -475,8 +475,9 @@ aicdf_status mlmc_allocate(uint32_t n_levels, double eps, const double* v_hat, c
 /* x[i] = C_nu^-1(u[i]; lambda[i]) in FP64: the CDF is the Poisson mixture of
  * central chi-squared CDFs (Abramowitz & Stegun 26.4.25, which Section 5
  * cites), summed outward from the Poisson mode with incomplete-gamma
- * recurrences; the root is found by safeguarded Halley steps (with the
- * density and its derivative from the same sweep) in log x on log C, or,
+ * recurrences; the root is found by safeguarded third-order (Householder)
+ * steps (with the density and its first two derivatives from the same
+ * sweep) in log x on log C, or,
  * for 1 - u < 2^-10 (any u > 1/2 when lambda > 4096), in x on log(1 - C)
  * with 1 - C from the upward sweep,
  * inside a maintained bracket.

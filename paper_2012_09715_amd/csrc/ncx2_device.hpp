@@ -29,13 +29,15 @@
 
 namespace aicdf {
 
-// C, 1 - C, the density f and its derivative f' = df/dx.  With the central
-// densities f_k(x) = (1/2) y^(a+j-1) e^-y / Gamma(a+j), k = 2(a+j), and
-// d f_k/dx = f_k ((a+j-1)/y - 1)/2:
-//   f  = sum_j c_j (a+j) / (2y),
-//   f' = sum_j c_j (a+j)(a+j-1) / (4y^2) - f/2.
+// C, 1 - C, the density f and its first two derivatives in x.  With the
+// central densities f_k(x) = (1/2) y^(A-1) e^-y / Gamma(A), A = a+j,
+// k = 2A, d f_k/dx = f_k ((A-1)/y - 1)/2 and
+// d^2 f_k/dx^2 = f_k ((A-1)(A-2)/y^2 - 2(A-1)/y + 1)/4:
+//   f   = sum_j c_j A / (2y),
+//   f'  = sum_j c_j A(A-1) / (4y^2) - f/2,
+//   f'' = sum_j c_j A(A-1)(A-2) / (8y^3) - f' - f/4.
 struct Ncx2Val {
-  double cdf, sf, pdf, dpdf;
+  double cdf, sf, pdf, dpdf, d2pdf = 0.0;
 };
 
 // P(A, y) and Q(A, y) with t = y^A e^-y / Gamma(A+1) given (A > 0, y > 0).
@@ -166,7 +168,8 @@ __host__ __device__ inline __noinline__ Ncx2Val ncx2_cdf(double x, double nu, do
   double T = ncx2_scale(1e-17, L - lw);
   // mu = 0 ends the sweep at j = 0 before inv_mu is used
   const double inv_mu = 1.0 / mu, inv_y = 1.0 / y;
-  double cdf = 0.0, pa = 0.0, pb = 0.0;  // pa = sum c_j (a+j), pb = sum c_j (a+j)(a+j-1)
+  // pa = sum c_j A_j, pb = sum c_j A_j (A_j - 1), pq = sum c_j A_j^2 (A_j - 1)
+  double cdf = 0.0, pa = 0.0, pb = 0.0, pq = 0.0;
   int k = 0;
   // the terms j >= max(jb + 2, 1) cannot end the sweep (the tests below
   // start at j - 1 < jb + 1): without the tests, the same arithmetic
@@ -176,7 +179,9 @@ __host__ __device__ inline __noinline__ Ncx2Val ncx2_cdf(double x, double nu, do
     const double Aj = a + dj;
     cdf += D;
     pa = fma(c, Aj, pa);
-    pb = fma(c, Aj * (Aj - 1.0), pb);
+    const double qj = Aj * (Aj - 1.0);
+    pb = fma(c, qj, pb);
+    pq = fma(c * qj, Aj, pq);
     const double rw = dj * inv_mu;
     c = c * rw * (Aj * inv_y);
     w = w * rw;
@@ -187,6 +192,7 @@ __host__ __device__ inline __noinline__ Ncx2Val ncx2_cdf(double x, double nu, do
       cdf *= kNcx2Small;
       pa *= kNcx2Small;
       pb *= kNcx2Small;
+      pq *= kNcx2Small;
       T *= kNcx2Big;
       ++k;
     }
@@ -195,7 +201,9 @@ __host__ __device__ inline __noinline__ Ncx2Val ncx2_cdf(double x, double nu, do
     const double Aj = a + j;
     cdf += D;
     pa = fma(c, Aj, pa);
-    pb = fma(c, Aj * (Aj - 1.0), pb);
+    const double qj = Aj * (Aj - 1.0);
+    pb = fma(c, qj, pb);
+    pq = fma(c * qj, Aj, pq);
     if (j == 0) break;
     // step to j - 1: D_(j-1) = (j/mu) D_j + c_(j-1),  c_(j-1) = c_j (j/mu) ((a+j)/y)
     const double rw = j * inv_mu;
@@ -208,6 +216,7 @@ __host__ __device__ inline __noinline__ Ncx2Val ncx2_cdf(double x, double nu, do
       cdf *= kNcx2Small;
       pa *= kNcx2Small;
       pb *= kNcx2Small;
+      pq *= kNcx2Small;
       T *= kNcx2Big;
       ++k;
     }
@@ -221,7 +230,9 @@ __host__ __device__ inline __noinline__ Ncx2Val ncx2_cdf(double x, double nu, do
           c * rc <= 0.5e-17 * pa * (1.0 - rc)) {
         cdf += D;
         pa = fma(c, a + j - 1, pa);
-        pb = fma(c, (a + j - 1) * (a + j - 2), pb);
+        const double qj = (a + j - 1) * (a + j - 2);
+        pb = fma(c, qj, pb);
+        pq = fma(c * qj, a + j - 1, pq);
         break;
       }
     }
@@ -229,7 +240,8 @@ __host__ __device__ inline __noinline__ Ncx2Val ncx2_cdf(double x, double nu, do
   const double ls = L + k * 415.88830833596718;  // e^L 2^(600 k)
   const double C = ncx2_scale(cdf, ls), f = ncx2_scale(pa * (0.5 * inv_y), ls);
   const double fp = ncx2_scale(pb * (0.25 * inv_y * inv_y), ls) - 0.5 * f;
-  return Ncx2Val{fmin(C, 1.0), fmax(1.0 - C, 0.0), f, fp};
+  const double fpp = ncx2_scale((pq - 2.0 * pb) * (0.125 * inv_y * inv_y * inv_y), ls) - fp - 0.25 * f;
+  return Ncx2Val{fmin(C, 1.0), fmax(1.0 - C, 0.0), f, fp, fpp};
 }
 
 // 1 - C(x) and pdf(x) by the upward sweep.
@@ -249,7 +261,7 @@ __host__ __device__ inline __noinline__ Ncx2Val ncx2_sf(double x, double nu, dou
   double G = exp(lG - L), c = exp(lc - L), w = 1.0;
   double T = ncx2_scale(1e-17, L - lw);  // the stopping bound's factor, as in ncx2_cdf
   const double muy = mu * y;
-  double sf = 0.0, pa = 0.0, pb = 0.0;  // pa = sum c_j (a+j), pb = sum c_j (a+j)(a+j-1)
+  double sf = 0.0, pa = 0.0, pb = 0.0, pq = 0.0;  // as in ncx2_cdf
   int k = 0;
   // the terms j <= je - 2 cannot end the sweep (the test below starts at
   // j + 1 > je - 1; je = 0 is the single term): without the tests, the same
@@ -260,7 +272,9 @@ __host__ __device__ inline __noinline__ Ncx2Val ncx2_sf(double x, double nu, dou
     const double Aj = a + dj;
     sf += G;
     pa = fma(c, Aj, pa);
-    pb = fma(c, Aj * (Aj - 1.0), pb);
+    const double qj = Aj * (Aj - 1.0);
+    pb = fma(c, qj, pb);
+    pq = fma(c * qj, Aj, pq);
     const double d = 1.0 / ((dj + 1.0) * (Aj + 1.0));
     const double rw = mu * (Aj + 1.0) * d;
     G = rw * (G + c);
@@ -272,6 +286,7 @@ __host__ __device__ inline __noinline__ Ncx2Val ncx2_sf(double x, double nu, dou
       sf *= kNcx2Small;
       pa *= kNcx2Small;
       pb *= kNcx2Small;
+      pq *= kNcx2Small;
       T *= kNcx2Big;
       ++k;
     }
@@ -280,7 +295,9 @@ __host__ __device__ inline __noinline__ Ncx2Val ncx2_sf(double x, double nu, dou
     const double Aj = a + j;
     sf += G;
     pa = fma(c, Aj, pa);
-    pb = fma(c, Aj * (Aj - 1.0), pb);
+    const double qj = Aj * (Aj - 1.0);
+    pb = fma(c, qj, pb);
+    pq = fma(c * qj, Aj, pq);
     if (je == 0.0) break;  // the single term j = 0
     // step to j + 1: G_(j+1) = (mu/(j+1)) (G_j + c_j),  c_(j+1) = c_j (mu/(j+1)) (y/(a+j+1)),
     // with one division: d = 1 / ((j+1)(a+j+1))
@@ -295,6 +312,7 @@ __host__ __device__ inline __noinline__ Ncx2Val ncx2_sf(double x, double nu, dou
       sf *= kNcx2Small;
       pa *= kNcx2Small;
       pb *= kNcx2Small;
+      pq *= kNcx2Small;
       T *= kNcx2Big;
       ++k;
     }
@@ -310,7 +328,8 @@ __host__ __device__ inline __noinline__ Ncx2Val ncx2_sf(double x, double nu, dou
   const double ls = L + k * 415.88830833596718;  // e^L 2^(600 k)
   const double S = ncx2_scale(sf, ls), f = ncx2_scale(pa * (0.5 / y), ls);
   const double fp = ncx2_scale(pb * (0.25 / (y * y)), ls) - 0.5 * f;
-  return Ncx2Val{fmax(1.0 - S, 0.0), fmin(S, 1.0), f, fp};
+  const double fpp = ncx2_scale((pq - 2.0 * pb) * (0.125 / (y * y * y)), ls) - fp - 0.25 * f;
+  return Ncx2Val{fmax(1.0 - S, 0.0), fmin(S, 1.0), f, fp, fpp};
 }
 
 // Quick initial value: Patnaik's scaled central chi-squared with the
@@ -336,7 +355,7 @@ __host__ __device__ inline __noinline__ double ncx2_guess(double t, bool upper, 
 //   x = (nu+lambda) B^(1/c1);
 // its relative error falls from ~1e-4 at lambda = 100 to ~1e-6 at 1000
 // (against ~3e-4 for the scaled central chi-squared start), which leaves one
-// or two Halley steps.  Returns 0 where B <= 0 (far lower tail).
+// or two root steps.  Returns 0 where B <= 0 (far lower tail).
 __host__ __device__ inline __noinline__ double ncx2_sankaran_start(double t, bool upper, double nu, double lam) {
   const double z = upper ? -exact_phi_inv(t) : exact_phi_inv(t);
   const double kl = nu + lam, k2l = nu + 2.0 * lam, k3l = nu + 3.0 * lam;
@@ -348,20 +367,38 @@ __host__ __device__ inline __noinline__ double ncx2_sankaran_start(double t, boo
   return B > 0.0 ? kl * pow(B, 1.0 / c1) : 0.0;
 }
 
-// The Halley step if usable, else the Newton step; `halley` tells which.
-__host__ __device__ inline double ncx2_step(double g, double dg, double d2g, bool& halley) {
+// The step of the highest order that is usable: Householder's third-order
+// step g (6 g'^2 - 3 g g'') / (6 g'^3 - 6 g g' g'' + g^2 g'''), else
+// Halley's 2 g g' / (2 g'^2 - g g''), else Newton's g / g' (each to be
+// subtracted); a higher-order step is usable when it points the way of the
+// Newton step and is at most twice as long.  `order` tells which was taken
+// (3, 2 or 1).
+__host__ __device__ inline double ncx2_step(double g, double dg, double d2g, double d3g, int& order) {
   const double newton = g / dg;
-  const double den = 2.0 * dg * dg - g * d2g;
-  halley = false;
-  if (den > 0.0) {
-    const double h = 2.0 * g * dg / den;
+  const double den3 = 6.0 * dg * dg * dg - 6.0 * g * dg * d2g + g * g * d3g;
+  if (den3 != 0.0) {
+    const double h = g * (6.0 * dg * dg - 3.0 * g * d2g) / den3;
     if (h * newton > 0.0 && fabs(h) <= 2.0 * fabs(newton)) {
-      halley = true;
+      order = 3;
       return h;
     }
   }
+  const double den = 2.0 * dg * dg - g * d2g;
+  if (den > 0.0) {
+    const double h = 2.0 * g * dg / den;
+    if (h * newton > 0.0 && fabs(h) <= 2.0 * fabs(newton)) {
+      order = 2;
+      return h;
+    }
+  }
+  order = 1;
   return newton;
 }
+
+// Relative step below which the iteration stops after a step of order 3, 2
+// or 1: the error left is of the order of the step's fourth, third or
+// second power (1e-16, 1e-15, 1e-18).
+__host__ __device__ inline double ncx2_stop(int order) { return order == 3 ? 1e-4 : order == 2 ? 1e-5 : 1e-9; }
 
 // The iteration as an explicit state: ncx2_root_init sets the bracket and
 // the start, each evaluation of C (lower form) or 1 - C (upper form) at r.xx
@@ -416,21 +453,22 @@ __host__ __device__ inline double ncx2_root_result(const Ncx2Root& r) { return r
 
 // One iteration with v = the evaluation at r.xx:
 // lower: g(w) = log C(e^w) - log u in w = log x (the lower tail of C is
-//        close to a power of x, so g is close to linear in w),
-//        g' = x f / C,  g'' = g' + x^2 f' / C - g'^2;
+//        close to a power of x, so g is close to linear in w); with
+//        q1 = x f / C, q2 = x^2 f' / C, q3 = x^3 f'' / C:
+//        g' = q1,  g'' = q1 + q2 - q1^2,
+//        g''' = g'' + 2 q2 + q3 - q1 q2 - 2 q1 g'';
 // upper: g(x) = log(1 - u) - log(1 - C(x)) in x (close to linear in x in
-//        the upper tail),  g' = f / S,  g'' = f' / S + g'^2,  S = 1 - C.
-// The Halley step 2 g g' / (2 g'^2 - g g'') is taken when it points the way
-// of the Newton step g / g' and is at most twice as long; otherwise the
-// Newton step.  Steps that leave the bracket are replaced by bisection
-// (geometric while the bracket spans more than a factor of two).  The
-// iteration stops when a step is below 2e-15 relative, or when a Halley
-// (Newton) step inside the bracket is below 1e-5 (1e-9) relative: the error
-// after it is of the order of the cube (square) of the step, 1e-15 (1e-18),
-// so the confirming evaluation is skipped (measured on the CIR steps: the
-// roots stay within 9e-12 of a solve to 2e-15, the CDF's own rounding
-// amplified by 2/nu, and 14 % fewer evaluations than with 1e-6); at the
-// latest after 100 iterations.
+//        the upper tail), S = 1 - C:
+//        g' = f / S,  g'' = f' / S + g'^2,
+//        g''' = f'' / S + (f' / S) g' + 2 g' g''.
+// The step is that of ncx2_step.  Steps that leave the bracket are replaced
+// by bisection (geometric while the bracket spans more than a factor of
+// two).  The iteration stops when a step is below 2e-15 relative, or when a
+// step inside the bracket is below ncx2_stop of its order, so the
+// confirming evaluation is skipped (measured on the CIR steps: with the
+// third-order step the roots stay within 6e-12 of a solve to 2e-15, the
+// CDF's own rounding amplified by 2/nu, and take a quarter fewer
+// evaluations than with Halley steps); at the latest after 100 iterations.
 __host__ __device__ inline void ncx2_root_update(Ncx2Root& r, const Ncx2Val& v) {
   if (!r.upper) {
     const double w = r.cur, xx = r.xx;
@@ -442,11 +480,13 @@ __host__ __device__ inline void ncx2_root_update(Ncx2Root& r, const Ncx2Val& v) 
     if (g < 0.0) r.lo = w; else r.hi = w;
     const double tol = 2e-15 * fmax(1.0, fabs(w));
     double wn = 0.5 * (r.lo + r.hi);
-    bool halley = false, good = false;
+    int order = 0;
+    bool good = false;
     if (v.cdf > 0.0 && v.pdf > 0.0) {
-      const double dg = xx * v.pdf / v.cdf;
-      const double d2g = dg + xx * xx * v.dpdf / v.cdf - dg * dg;
-      wn = w - ncx2_step(g, dg, d2g, halley);
+      const double q1 = xx * v.pdf / v.cdf, q2 = xx * xx * v.dpdf / v.cdf, q3 = xx * xx * xx * v.d2pdf / v.cdf;
+      const double d2g = q1 + q2 - q1 * q1;
+      const double d3g = d2g + 2.0 * q2 + q3 - q1 * q2 - 2.0 * q1 * d2g;
+      wn = w - ncx2_step(g, q1, d2g, d3g, order);
       good = true;
     }
     if (good && fabs(wn - w) <= tol) {  // converged (may sit on the bracket end)
@@ -456,7 +496,7 @@ __host__ __device__ inline void ncx2_root_update(Ncx2Root& r, const Ncx2Val& v) 
     }
     if (!(wn > r.lo && wn < r.hi)) {
       wn = 0.5 * (r.lo + r.hi);
-    } else if (good && fabs(wn - w) <= (halley ? 1e-5 : 1e-9) * fmax(1.0, fabs(w))) {
+    } else if (good && fabs(wn - w) <= ncx2_stop(order) * fmax(1.0, fabs(w))) {
       r.cur = wn;
       r.done = true;
       return;
@@ -476,11 +516,13 @@ __host__ __device__ inline void ncx2_root_update(Ncx2Root& r, const Ncx2Val& v) 
     }
     if (g < 0.0) r.lo = x; else r.hi = x;
     double xn = -1.0;
-    bool halley = false, good = false;
+    int order = 0;
+    bool good = false;
     if (v.sf > 0.0 && v.pdf > 0.0) {
-      const double dg = v.pdf / v.sf;
-      const double d2g = v.dpdf / v.sf + dg * dg;
-      xn = x - ncx2_step(g, dg, d2g, halley);
+      const double dg = v.pdf / v.sf, q2 = v.dpdf / v.sf;
+      const double d2g = q2 + dg * dg;
+      const double d3g = v.d2pdf / v.sf + q2 * dg + 2.0 * dg * d2g;
+      xn = x - ncx2_step(g, dg, d2g, d3g, order);
       good = true;
     }
     if (good && xn > 0.0 && fabs(xn - x) <= 2e-15 * x) {  // converged (may sit on the bracket end)
@@ -490,7 +532,7 @@ __host__ __device__ inline void ncx2_root_update(Ncx2Root& r, const Ncx2Val& v) 
     }
     if (!(xn > r.lo && xn < r.hi)) {
       xn = (r.hi > 2.0 * r.lo) ? sqrt(r.lo) * sqrt(r.hi) : 0.5 * (r.lo + r.hi);
-    } else if (good && fabs(xn - x) <= (halley ? 1e-5 : 1e-9) * x) {
+    } else if (good && fabs(xn - x) <= ncx2_stop(order) * x) {
       r.cur = xn;
       r.done = true;
       return;
@@ -520,8 +562,12 @@ __host__ __device__ inline void ncx2_root_update(Ncx2Root& r, const Ncx2Val& v) 
 // Ev supplies Ncx2Val cdf(x) and Ncx2Val sf(x) for the given (nu, lambda).
 // `iters` receives the number of CDF evaluations.
 // lga1: log Gamma(nu/2 + 1) when the caller holds it (NaN: computed here).
+// The driver is inlined into its callers (the CDF evaluations stay calls):
+// called as a function it needs ~200 registers under the calling convention,
+// which leaves the one-path-per-thread CIR levels two waves per SIMD instead
+// of three.
 template <class Ev>
-__host__ __device__ inline double ncx2_solve(double t, bool upper, double nu, double lam, const Ev& ev,
+__host__ __device__ __forceinline__ double ncx2_solve(double t, bool upper, double nu, double lam, const Ev& ev,
                                              int* iters, double x0 = 0.0, double lga1 = __builtin_nan("")) {
   Ncx2Root r;
   ncx2_root_init(r, t, upper, nu, lam, x0, lga1 == lga1 ? lga1 : ncx2_lgamma(0.5 * nu + 1.0));
@@ -537,7 +583,7 @@ struct Ncx2Seq {
   __host__ __device__ Ncx2Val sf(double x) const { return ncx2_sf(x, nu, lam); }
 };
 
-__host__ __device__ inline double ncx2_icdf_tail(double t, bool upper, double nu, double lam,
+__host__ __device__ __forceinline__ double ncx2_icdf_tail(double t, bool upper, double nu, double lam,
                                                  int* iters = nullptr, double x0 = 0.0,
                                                  double lga1 = __builtin_nan("")) {
   return ncx2_solve(t, upper, nu, lam, Ncx2Seq{nu, lam}, iters, x0, lga1);
@@ -562,7 +608,7 @@ constexpr double kNcx2MaxLam = 1e8;
 // C_nu^-1(u; lambda) for u in [0, 1]: 0 at u = 0, +inf at u = 1, NaN outside
 // (and NaN for lambda outside [0, kNcx2MaxLam]).
 // x0 > 0: an approximation of the root to start from; lga1 as in ncx2_solve.
-__host__ __device__ inline double ncx2_icdf(double u, double nu, double lam, int* iters = nullptr,
+__host__ __device__ __forceinline__ double ncx2_icdf(double u, double nu, double lam, int* iters = nullptr,
                                             double x0 = 0.0, double lga1 = __builtin_nan("")) {
   if (!(u > 0.0)) return u == 0.0 ? 0.0 : __builtin_nan("");
   if (!(u < 1.0)) return u == 1.0 ? __builtin_inf() : __builtin_nan("");

@@ -128,44 +128,37 @@ __device__ __forceinline__ Ncx2Tri ncx2_scan(Ncx2Tri t, int lane, Ncx2Tri& all) 
   return ncx2_dpp_tri<kDppWaveShr1, 0xF>(t);
 }
 
-// Sums over the wave of three values m_i 2^(e_l) with a common per-lane
+// Sums over the wave of four values m_i 2^(e_l) with a common per-lane
 // exponent, returned as mantissas on one exponent in every lane (the same
-// bits in every lane).  m1, m2 >= 0; m3 may be negative.
-__device__ __forceinline__ void ncx2_wave_sum3(double m1, double m2, double m3, int e, double& s1, double& s2,
-                                               double& s3, int& es) {
+// bits in every lane).  m[0..2] >= 0; m[3] may be negative.
+__device__ __forceinline__ void ncx2_wave_sum4(const double (&m)[4], int e, double (&s)[4], int& es) {
+  const bool any = m[0] > 0.0 || m[1] > 0.0 || m[2] > 0.0 || m[3] != 0.0;
   const int emax = __builtin_amdgcn_readlane(
-      ncx2_wave_scan((m1 > 0.0 || m2 > 0.0 || m3 != 0.0) ? e : -100000, -100000,
-                     [](int x, int y) { return max(x, y); }),
-      63);
+      ncx2_wave_scan(any ? e : -100000, -100000, [](int x, int y) { return max(x, y); }), 63);
   const int sh = max(e - emax, -2000);
-  s1 = ncx2_wave_total(ldexp(m1, sh));
-  s2 = ncx2_wave_total(ldexp(m2, sh));
-  s3 = ncx2_wave_total(ldexp(m3, sh));
+#pragma unroll
+  for (int i = 0; i < 4; ++i) s[i] = ncx2_wave_total(ldexp(m[i], sh));
   es = emax == -100000 ? 0 : emax;
 }
 
-// (m1, m2, m3) 2^e += (a1, a2, a3) 2^ea: the three totals share one exponent.
-__device__ __forceinline__ void ncx2_acc3(double& m1, double& m2, double& m3, int& e, double a1, double a2,
-                                          double a3, int ea) {
-  if (!(a1 > 0.0 || a2 > 0.0 || a3 != 0.0)) return;
-  if (!(m1 > 0.0 || m2 > 0.0 || m3 != 0.0)) {
-    m1 = a1;
-    m2 = a2;
-    m3 = a3;
+// m 2^e += a 2^ea for four totals on one exponent.
+__device__ __forceinline__ void ncx2_acc4(double (&m)[4], int& e, const double (&a)[4], int ea) {
+  if (!(a[0] > 0.0 || a[1] > 0.0 || a[2] > 0.0 || a[3] != 0.0)) return;
+  if (!(m[0] > 0.0 || m[1] > 0.0 || m[2] > 0.0 || m[3] != 0.0)) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) m[i] = a[i];
     e = ea;
     return;
   }
   if (ea > e) {
     const int sh = max(e - ea, -2000);
-    m1 = ldexp(m1, sh) + a1;
-    m2 = ldexp(m2, sh) + a2;
-    m3 = ldexp(m3, sh) + a3;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) m[i] = ldexp(m[i], sh) + a[i];
     e = ea;
   } else {
     const int sh = max(ea - e, -2000);
-    m1 += ldexp(a1, sh);
-    m2 += ldexp(a2, sh);
-    m3 += ldexp(a3, sh);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) m[i] += ldexp(a[i], sh);
   }
 }
 
@@ -222,7 +215,8 @@ constexpr int kNcx2PassTerms = 64 * 16;
 // when the chunk's growth bound shows that no entry can.
 template <bool CHECK>
 __device__ __forceinline__ void ncx2_chunk_down(double jd, int cnt, double a, double inv_mu, double inv_y,
-                                                Ncx2Tri& T, double& sp, double& sr, double& sq, double& sq2) {
+                                                Ncx2Tri& T, double& sp, double& sr, double& sq, double& sq2,
+                                                double& sq3) {
   // the chunk that ends at j = 0 takes no step below it
   const bool last0 = cnt > 0 && jd - (cnt - 1) == 0.0;
   const int steps = last0 ? cnt - 1 : cnt;
@@ -232,7 +226,9 @@ __device__ __forceinline__ void ncx2_chunk_down(double jd, int cnt, double a, do
     sp += T.p;
     sr += T.r;
     sq = fma(Aj, T.q, sq);
-    sq2 = fma(Aj * (Aj - 1.0), T.q, sq2);
+    const double qj = Aj * (Aj - 1.0);
+    sq2 = fma(qj, T.q, sq2);
+    sq3 = fma(qj * T.q, Aj, sq3);
     const double rw = jd * inv_mu, f = rw * (Aj * inv_y);
     T.r = fma(rw, T.r, f * T.q);
     T.p *= rw;
@@ -245,6 +241,7 @@ __device__ __forceinline__ void ncx2_chunk_down(double jd, int cnt, double a, do
       sr *= kNcx2Small;
       sq *= kNcx2Small;
       sq2 *= kNcx2Small;
+      sq3 *= kNcx2Small;
       T.e += 600;
     }
   }
@@ -252,7 +249,9 @@ __device__ __forceinline__ void ncx2_chunk_down(double jd, int cnt, double a, do
     sp += T.p;
     sr += T.r;
     sq = fma(a, T.q, sq);
-    sq2 = fma(a * (a - 1.0), T.q, sq2);
+    const double q0 = a * (a - 1.0);
+    sq2 = fma(q0, T.q, sq2);
+    sq3 = fma(q0 * T.q, a, sq3);
   }
 }
 
@@ -283,7 +282,7 @@ __device__ inline __noinline__ Ncx2Val ncx2_cdf_wave(double x, double nu, double
   double D = exp(lD - L), c = exp(lc - L);
   int E = 0;
   const double inv_mu = 1.0 / mu, inv_y = 1.0 / y;
-  double cdf = 0.0, pa = 0.0, pb = 0.0;  // totals: (cdf, pa, pb) 2^Et e^L
+  double tot[4] = {0.0, 0.0, 0.0, 0.0};  // totals (cdf, pa, pb, pq) 2^Et e^L, pa .. pq as in ncx2_cdf
   int Et = 0;
   double wm = 1.0;  // w_(jhi) / w_(jed) = wm 2^we: the scans' products of j/mu
   int we = 0;
@@ -293,16 +292,16 @@ __device__ inline __noinline__ Ncx2Val ncx2_cdf_wave(double x, double nu, double
     const int m = (n + 63) / 64;
     const int my_hi = jhi - lane * m, my_lo = max(jlo, my_hi - m + 1);
     Ncx2Tri T{1.0, 0.0, 1.0, 0};
-    double sp = 0.0, sr = 0.0, sq = 0.0, sq2 = 0.0;  // sums of T's rows, relative to 2^T.e
+    double sp = 0.0, sr = 0.0, sq = 0.0, sq2 = 0.0, sq3 = 0.0;  // sums of T's rows, relative to 2^T.e
     {
       // the step factors j/mu and (j/mu)(a+j)/y grow with j, so every entry
       // grows by at most 2 g per step, g the larger factor at the top index
       const int cnt = my_hi - my_lo + 1;
       const double jt = double(my_hi), g = fmax(jt * inv_mu, jt * inv_mu * ((a + jt) * inv_y));
       if (cnt * (ilogb(fmin(fmax(2.0 * g, 1.0), 0x1p1000)) + 1) < 500)
-        ncx2_chunk_down<false>(jt, cnt, a, inv_mu, inv_y, T, sp, sr, sq, sq2);
+        ncx2_chunk_down<false>(jt, cnt, a, inv_mu, inv_y, T, sp, sr, sq, sq2, sq3);
       else
-        ncx2_chunk_down<true>(jt, cnt, a, inv_mu, inv_y, T, sp, sr, sq, sq2);
+        ncx2_chunk_down<true>(jt, cnt, a, inv_mu, inv_y, T, sp, sr, sq, sq2, sq3);
     }
     const int es = T.e;
     ncx2_norm(T);
@@ -310,11 +309,11 @@ __device__ inline __noinline__ Ncx2Val ncx2_cdf_wave(double x, double nu, double
     const Ncx2Tri X = ncx2_scan(T, lane, all);
     // incoming state of this lane's chunk, and its partial sums
     const double Din = fma(X.p, D, X.r * c), cin = X.q * c;
-    const double pc = fma(sp, Din, sr * cin), pp = sq * cin, pp2 = sq2 * cin;
-    double s1, s2, s3;
+    const double part[4] = {fma(sp, Din, sr * cin), sq * cin, sq2 * cin, sq3 * cin};
+    double sum[4];
     int e12;
-    ncx2_wave_sum3(pc, pp, pp2, es + X.e + E, s1, s2, s3, e12);
-    ncx2_acc3(cdf, pa, pb, Et, s1, s2, s3, e12);
+    ncx2_wave_sum4(part, es + X.e + E, sum, e12);
+    ncx2_acc4(tot, Et, sum, e12);
     if (jlo == 0) break;
     // state at jlo - 1
     {
@@ -338,10 +337,12 @@ __device__ inline __noinline__ Ncx2Val ncx2_cdf_wave(double x, double nu, double
         // w_jn r/(1-r) on the scale 2^Et e^L of the totals
         const double head = ncx2_scale(wm * (r / (1.0 - r)), lw - L + (we - Et) * 0.69314718055994531);
         const double Dr = ldexp(D, E - Et), cr = ldexp(c, E - Et);
-        if (head <= 1e-17 * cdf && Dr <= 1e-17 * cdf && cr * rc / (1.0 - rc) <= 0.5e-17 * pa) {
-          cdf += Dr;
-          pa = fma(cr, a + jn, pa);
-          pb = fma(cr, (a + jn) * (a + jn - 1.0), pb);
+        if (head <= 1e-17 * tot[0] && Dr <= 1e-17 * tot[0] && cr * rc / (1.0 - rc) <= 0.5e-17 * tot[1]) {
+          const double An = a + jn, qn = An * (An - 1.0);
+          tot[0] += Dr;
+          tot[1] = fma(cr, An, tot[1]);
+          tot[2] = fma(cr, qn, tot[2]);
+          tot[3] = fma(cr * qn, An, tot[3]);
           break;
         }
       }
@@ -350,23 +351,26 @@ __device__ inline __noinline__ Ncx2Val ncx2_cdf_wave(double x, double nu, double
     jlo = max(0, jn - (kNcx2PassTerms - 1));
   }
   const double ls = L + Et * 0.69314718055994531;
-  const double C = ncx2_scale(cdf, ls), f = ncx2_scale(pa * (0.5 * inv_y), ls);
-  const double fp = ncx2_scale(pb * (0.25 * inv_y * inv_y), ls) - 0.5 * f;
-  return Ncx2Val{fmin(C, 1.0), fmax(1.0 - C, 0.0), f, fp};
+  const double C = ncx2_scale(tot[0], ls), f = ncx2_scale(tot[1] * (0.5 * inv_y), ls);
+  const double fp = ncx2_scale(tot[2] * (0.25 * inv_y * inv_y), ls) - 0.5 * f;
+  const double fpp = ncx2_scale((tot[3] - 2.0 * tot[2]) * (0.125 * inv_y * inv_y * inv_y), ls) - fp - 0.25 * f;
+  return Ncx2Val{fmin(C, 1.0), fmax(1.0 - C, 0.0), f, fp, fpp};
 }
 
 // One lane's chunk of the upward sweep (indices j_lo, j_lo + 1, ..), as
 // ncx2_chunk_down.
 template <bool CHECK>
 __device__ __forceinline__ void ncx2_chunk_up(double jd, int cnt, double a, double mu, double muy, Ncx2Tri& T,
-                                              double& sp, double& sr, double& sq, double& sq2) {
+                                              double& sp, double& sr, double& sq, double& sq2, double& sq3) {
 #pragma unroll 2
   for (int i = 0; i < cnt; ++i, jd += 1.0) {
     const double Aj = a + jd;
     sp += T.p;
     sr += T.r;
     sq = fma(Aj, T.q, sq);
-    sq2 = fma(Aj * (Aj - 1.0), T.q, sq2);
+    const double qj = Aj * (Aj - 1.0);
+    sq2 = fma(qj, T.q, sq2);
+    sq3 = fma(qj * T.q, Aj, sq3);
     const double d = 1.0 / ((jd + 1.0) * (Aj + 1.0));
     const double rw = mu * (Aj + 1.0) * d, g = muy * d;
     T.r = rw * (T.r + T.q);
@@ -380,6 +384,7 @@ __device__ __forceinline__ void ncx2_chunk_up(double jd, int cnt, double a, doub
       sr *= kNcx2Small;
       sq *= kNcx2Small;
       sq2 *= kNcx2Small;
+      sq3 *= kNcx2Small;
       T.e += 600;
     }
   }
@@ -410,7 +415,7 @@ __device__ inline __noinline__ Ncx2Val ncx2_sf_wave(double x, double nu, double 
   double G = exp(lG - L), c = exp(lc - L);
   int E = 0;
   const double muy = mu * y;
-  double sf = 0.0, pa = 0.0, pb = 0.0;
+  double tot[4] = {0.0, 0.0, 0.0, 0.0};  // totals (sf, pa, pb, pq) 2^Et e^L
   int Et = 0;
   double wm = 1.0;  // w_(jlo) / w_(jbd) = wm 2^we: the scans' products of mu/(j+1)
   int we = 0;
@@ -420,7 +425,7 @@ __device__ inline __noinline__ Ncx2Val ncx2_sf_wave(double x, double nu, double 
     const int m = (n + 63) / 64;
     const int my_lo = jlo + lane * m, my_hi = min(jhi, my_lo + m - 1);
     Ncx2Tri T{1.0, 0.0, 1.0, 0};
-    double sp = 0.0, sr = 0.0, sq = 0.0, sq2 = 0.0;
+    double sp = 0.0, sr = 0.0, sq = 0.0, sq2 = 0.0, sq3 = 0.0;
     {
       // the step factors mu/(j+1) and mu y/((j+1)(a+j+1)) fall with j: every
       // entry grows by at most 2 g per step, g the larger factor at the bottom
@@ -428,20 +433,20 @@ __device__ inline __noinline__ Ncx2Val ncx2_sf_wave(double x, double nu, double 
       const double jb = double(my_lo);
       const double g = fmax(mu / (jb + 1.0), muy / ((jb + 1.0) * (a + jb + 1.0)));
       if (cnt * (ilogb(fmin(fmax(2.0 * g, 1.0), 0x1p1000)) + 1) < 500)
-        ncx2_chunk_up<false>(jb, cnt, a, mu, muy, T, sp, sr, sq, sq2);
+        ncx2_chunk_up<false>(jb, cnt, a, mu, muy, T, sp, sr, sq, sq2, sq3);
       else
-        ncx2_chunk_up<true>(jb, cnt, a, mu, muy, T, sp, sr, sq, sq2);
+        ncx2_chunk_up<true>(jb, cnt, a, mu, muy, T, sp, sr, sq, sq2, sq3);
     }
     const int es = T.e;
     ncx2_norm(T);
     Ncx2Tri all;
     const Ncx2Tri X = ncx2_scan(T, lane, all);
     const double Gin = fma(X.p, G, X.r * c), cin = X.q * c;
-    const double pc = fma(sp, Gin, sr * cin), pp = sq * cin, pp2 = sq2 * cin;
-    double s1, s2, s3;
+    const double part[4] = {fma(sp, Gin, sr * cin), sq * cin, sq2 * cin, sq3 * cin};
+    double sum[4];
     int e12;
-    ncx2_wave_sum3(pc, pp, pp2, es + X.e + E, s1, s2, s3, e12);
-    ncx2_acc3(sf, pa, pb, Et, s1, s2, s3, e12);
+    ncx2_wave_sum4(part, es + X.e + E, sum, e12);
+    ncx2_acc4(tot, Et, sum, e12);
     if (jed == 0.0) break;  // the single term j = 0
     {
       wm *= all.p;
@@ -464,16 +469,17 @@ __device__ inline __noinline__ Ncx2Val ncx2_sf_wave(double x, double nu, double 
         // w_jn r/(1-r) on the scale 2^Et e^L of the totals
         const double tail = ncx2_scale(wm * (r / (1.0 - r)), lw - L + (we - Et) * 0.69314718055994531);
         const double Gr = ldexp(G, E - Et), cr = ldexp(c, E - Et);
-        if (tail <= 1e-17 * sf && Gr <= 1e-17 * sf && cr * rc / (1.0 - rc) <= 0.5e-17 * pa) break;
+        if (tail <= 1e-17 * tot[0] && Gr <= 1e-17 * tot[0] && cr * rc / (1.0 - rc) <= 0.5e-17 * tot[1]) break;
       }
     }
     jlo = jn;
     jhi = jn + kNcx2PassTerms - 1;
   }
   const double ls = L + Et * 0.69314718055994531;
-  const double S = ncx2_scale(sf, ls), f = ncx2_scale(pa * (0.5 / y), ls);
-  const double fp = ncx2_scale(pb * (0.25 / (y * y)), ls) - 0.5 * f;
-  return Ncx2Val{fmax(1.0 - S, 0.0), fmin(S, 1.0), f, fp};
+  const double S = ncx2_scale(tot[0], ls), f = ncx2_scale(tot[1] * (0.5 / y), ls);
+  const double fp = ncx2_scale(tot[2] * (0.25 / (y * y)), ls) - 0.5 * f;
+  const double fpp = ncx2_scale((tot[3] - 2.0 * tot[2]) * (0.125 / (y * y * y)), ls) - fp - 0.25 * f;
+  return Ncx2Val{fmax(1.0 - S, 0.0), fmin(S, 1.0), f, fp, fpp};
 }
 
 struct Ncx2Wave {
