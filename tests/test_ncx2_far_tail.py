@@ -90,3 +90,34 @@ def test_far_lower_tail_against_mpmath(tmp_path):
         assert abs(x - ref) <= 5e-11 * ref, (nu, lam, u, x, float(ref), float(abs(x - ref) / ref))
     for x in got[len(CASES):]:
         assert 0.0 <= x < 1e-300, x
+
+
+# The body and both tails at moderate and large lambda (the CIR levels' range
+# and beyond, both sweep directions: upper-tail targets 1 - u < 2^-10, and
+# every u > 1/2 once lambda > 4096), against the oracle's bisection in log x:
+# the root iteration's third-order steps and its stopping rule, through the
+# host build.  Bound: 5e-11 relative.
+BODY = [(nu, lam, u) for nu in (0.889, 5.0) for lam in (0.0, 0.5, 20.0, 300.0, 5000.0)
+        for u in (1e-8, 0.01, 0.3, 0.5, 0.7, 0.99, 1.0 - 1e-6)]
+
+
+@pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not available")
+def test_body_and_upper_tail_against_oracle(tmp_path):
+    from oracle import ncx2 as oracle_ncx2
+    src = tmp_path / "probe.hip"
+    src.write_text(PROGRAM)
+    exe = tmp_path / "probe"
+    r = subprocess.run([HIPCC, "-O2", "-std=c++17", "--offload-arch=gfx950", f"-I{CSRC}",
+                        f"-I{os.path.join(ROOT, 'include')}", str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    inp = "".join(f"{nu!r} {lam!r} {u!r}\n" for nu, lam, u in BODY)
+    out = subprocess.run([str(exe)], input=inp, capture_output=True, text=True, check=True).stdout.split()
+    got = np.array([float(v) for v in out])
+    worst = 0.0
+    for (nu, lam, u), x in zip(BODY, got):
+        ref = float(oracle_ncx2.icdf(u, nu, lam)[0])
+        rel = abs(x - ref) / ref
+        worst = max(worst, rel)
+        assert rel <= 5e-11, (nu, lam, u, x, ref, rel)
+    assert worst > 0.0  # the two sides are computed independently
